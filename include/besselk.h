@@ -1,0 +1,244 @@
+/*
+ * besselk.h - C ABI of libbesselk.so: the modified Bessel function of the second
+ * kind K_nu(x), evaluated on MI355X (gfx950) by finite-window trapezoid
+ * quadrature of its integral form, standalone and fused into tiled Matern
+ * covariance generation (arXiv 2502.00356, "GPU-Accelerated Modified Bessel
+ * Function of the Second Kind for Gaussian Processes").
+ *
+ * Conventions shared by every entry point
+ *  - Array arguments are DEVICE pointers owned by the caller, unless a comment
+ *    says "host". The library never frees or retains them.
+ *  - Calls only enqueue work on the given HIP stream (NULL = the default stream)
+ *    and return without synchronising, unless documented otherwise.
+ *  - The return value is a bk_status; arguments are checked before anything is
+ *    enqueued, and no call aborts or throws. n == 0 is valid and enqueues nothing.
+ *  - Element-level domain (as scipy.special.kv): x < 0 or NaN -> NaN, x == 0 ->
+ *    +inf, NaN order -> NaN; a negative order is replaced by its absolute value
+ *    because K_{-nu} = K_nu (the integrand of Sec. IV-B is even in nu).
+ */
+#ifndef BESSELK_H
+#define BESSELK_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BK_OK = 0,
+    BK_EINVAL = 1,   /* bad argument: null pointer, negative size, bad parameter */
+    BK_EHIP = 2,     /* a HIP runtime call or kernel launch failed */
+    BK_ENOMEM = 3,   /* workspace too small or allocation failed */
+    BK_ENOMODEL = 4, /* BK_LEARNED without a trained model */
+    BK_EIO = 5       /* model file could not be read or written, or is malformed */
+} bk_status;
+
+/* Evaluation form.
+ *  BK_PLAIN_F64  : per-entry peak and window solve in FP64 (the bracket/Newton
+ *                  search of Sec. IV-B), node count from the trapezoid strip
+ *                  bound, FP64 node terms and FP64 accumulation.
+ *  BK_MIXED_F32C : the same FP64 solve; node exponents formed in FP64 without
+ *                  cancellation, exponentials in FP32, Kahan-compensated FP32 sum,
+ *                  FP64 prefactor. Looser window (relative error ~1e-7 class).
+ *  BK_LEARNED    : a 2-64-64-3 MLP on (log10 x, nu) predicts the window and node
+ *                  count in place of the solve; terms as in BK_MIXED_F32C; entries
+ *                  outside the model's training box, or failing the tail and
+ *                  step-halving checks, are recomputed with BK_MIXED_F32C. */
+typedef enum { BK_PLAIN_F64 = 0, BK_MIXED_F32C = 1, BK_LEARNED = 2 } bk_mode;
+
+/* Matern output element type. */
+typedef enum { BK_OUT_F64 = 0, BK_OUT_F32 = 1 } bk_dtype;
+
+/* What bk_besselk_ex writes per entry. */
+typedef enum { BK_RESULT_K = 0, BK_RESULT_SCALED = 1, BK_RESULT_LOG = 2 } bk_result;
+
+/* Indices into the optional statistics array (device, unsigned 64-bit counters,
+ * accumulated, never cleared by the library). */
+enum {
+    BK_STAT_ENTRIES = 0,      /* entries evaluated by quadrature               */
+    BK_STAT_NODES = 1,        /* sum over entries of (N + 1) trapezoid nodes    */
+    BK_STAT_FB_RANGE = 2,     /* learned: (nu, x) outside the training box      */
+    BK_STAT_FB_TAIL = 3,      /* learned: an end node carried too much weight   */
+    BK_STAT_FB_STEP = 4,      /* learned: step-halving estimate above tolerance */
+    BK_STAT_FB_NONFINITE = 5, /* learned: non-finite prediction or sum          */
+    BK_STATS_LEN = 8
+};
+
+typedef struct bk_model bk_model;
+
+/* Per-call options. Zero-initialise and set what you need.
+ *  L_window : window threshold L of Sec. IV-B, [t0,t1] = {t : g(t) >= g(t_max) - L}.
+ *             0 selects the form's default (38 for BK_PLAIN_F64, 16 otherwise).
+ *  L_quad   : node-count target: the step keeps the strip-bound discretisation
+ *             error near exp(-L_quad). 0 selects 36.5 (plain) or 15.4 (others).
+ *  result   : bk_result, for bk_besselk_ex only.
+ *  sigma2, beta, nu : Matern parameters theta = (sigma^2, beta, nu) of Sec. III-A
+ *             (sigma2 >= 0, beta > 0, nu > 0), for bk_matern_tiles only.
+ *  out_dtype: bk_dtype of the Matern output, for bk_matern_tiles only.
+ *  model    : trained model, required for BK_LEARNED.
+ *  stats    : device array of BK_STATS_LEN counters, or NULL.
+ *  workspace, workspace_bytes : device scratch owned by the caller; BK_LEARNED
+ *             needs at least bk_workspace_bytes(n) bytes (the fallback queue). */
+typedef struct {
+    int32_t mode;
+    int32_t result;
+    int32_t out_dtype;
+    int32_t reserved0;
+    double L_window;
+    double L_quad;
+    double sigma2;
+    double beta;
+    double nu;
+    const bk_model* model;
+    unsigned long long* stats;
+    void* workspace;
+    size_t workspace_bytes;
+} bk_params;
+
+/* Human-readable name of a status code (static string). */
+const char* bk_status_str(int status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int bk_version(void);
+
+/* K_nu(x) for n pairs in plain FP64 (BK_PLAIN_F64, default window).
+ * Defines: the integral K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt of
+ * Sec. IV-B, evaluated as g(t_max) + log of the trapezoid sum of
+ * exp(g(t_m) - g(t_max)) over the window (Sec. IV-B, Eq. "refined").
+ * nu, x : n doubles each (device). out : n doubles (device), K_nu(x).
+ * Past x ~ 708 K underflows double; use bk_besselk_ex with BK_RESULT_SCALED. */
+int bk_besselk(const double* nu, const double* x, double* out, int64_t n, hipStream_t stream);
+
+/* K_nu(x) with options: any bk_mode, and result K, e^x K or log K.
+ * Same layout and ownership as bk_besselk. Returns BK_ENOMODEL for BK_LEARNED
+ * without params->model, BK_ENOMEM if the workspace is too small. */
+int bk_besselk_ex(const double* nu, const double* x, double* out, int64_t n,
+                  const bk_params* params, hipStream_t stream);
+
+/* Device workspace that BK_LEARNED needs for n entries (bytes). */
+size_t bk_workspace_bytes(int64_t n);
+
+/* Location set for Matern generation: n points as FP64 structure-of-arrays,
+ * x[i], y[i] (device). Sec. IV-C, Alg. 3 passes locations as coordinate vectors. */
+typedef struct {
+    const double* x;
+    const double* y;
+    int64_t n;
+} bk_locs;
+
+/* Tiled Matern covariance matrix (Sec. III-A formula; Alg. 3 per tile):
+ *   C(r) = sigma2 / (2^(nu-1) Gamma(nu)) (r/beta)^nu K_nu(r/beta),  C(0) = sigma2,
+ * with r the FP64 Euclidean distance between locations i and j and an exactly
+ * zero distance giving sigma2 (Alg. 3).
+ * Tiling: T = ceil(n / tile_size) tile rows and columns; tile (I, J) covers rows
+ * [I*ts, min(n,(I+1)*ts)) and columns [J*ts, ...). With lower_only != 0 the tiles
+ * with J <= I are stored, else all tiles. Tiles are stored one after another in
+ * J-major order (J = 0, 1, ...; within a column I ascending), each m_I x n_J
+ * column-major with leading dimension m_I: entry (i, j) of tile (I, J) is at
+ * bk_matern_tile_offset(I, J) + i + j * m_I. Diagonal tiles are written in full
+ * (both triangles). With tile_size >= n and lower_only == 0 the output is the
+ * whole n x n column-major matrix.
+ * out : device buffer of bk_matern_out_elems(n, tile_size, lower_only) elements
+ *       of params->out_dtype. params->mode selects the form (BK_LEARNED needs a
+ *       model; the Matern path uses no workspace). */
+int bk_matern_tiles(const bk_locs* locs, const bk_params* params, int32_t tile_size,
+                    int32_t lower_only, void* out, hipStream_t stream);
+
+/* Number of output elements bk_matern_tiles writes (host computation). */
+int64_t bk_matern_out_elems(int64_t n, int32_t tile_size, int32_t lower_only);
+
+/* Element offset of tile (I, J) in the bk_matern_tiles output, or -1 if the tile
+ * is not stored or out of range (host computation). */
+int64_t bk_matern_tile_offset(int64_t n, int32_t tile_size, int32_t lower_only, int32_t I, int32_t J);
+
+/* Integration window of the plain solver (Sec. IV-B): t_lo, t_hi bound
+ * {t : g(t) >= g(t_max) - L_window} (t_lo = 0 when g(0) is above the threshold)
+ * and nodes = N, the trapezoid interval count for target exp(-L_quad).
+ * These are the training targets of the window-predicting MLP.
+ * nu, x : n doubles (device). t_lo, t_hi : n doubles, nodes : n int32 (device).
+ * L_window, L_quad > 0 (0 selects 16 and 15.4). */
+int bk_window(const double* nu, const double* x, double* t_lo, double* t_hi, int32_t* nodes,
+              int64_t n, double L_window, double L_quad, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Window-predicting MLP (2 -> 64 -> 64 -> 3, ReLU).
+ * Inputs u = ((log10 x - cx)/sx, (nu - cnu)/snu); outputs (t_lo/st, t_hi/st, N/sn).
+ * Flat FP32 parameter vector of BK_MLP_NPARAM floats, in this order:
+ *   W1[64][2], b1[64], W2[64][64], b2[64], W3[3][64], b3[3]   (row-major, W[out][in])
+ * ------------------------------------------------------------------------- */
+#define BK_MLP_NPARAM 4547
+
+/* Training configuration. */
+typedef struct {
+    int32_t epochs;        /* passes over the training set                     */
+    int32_t batch;         /* minibatch size, 1..65536                         */
+    float lr;              /* Adam step size                                   */
+    float beta1, beta2;    /* Adam moment decay rates                          */
+    float eps;             /* Adam denominator offset                          */
+    float tau_lo, tau_hi, tau_n; /* expectile levels of the three outputs      */
+    uint64_t seed;         /* initialisation and shuffling seed                */
+    double L_window, L_quad; /* window targets (0 selects 16 and 15.4)         */
+} bk_train_cfg;
+
+/* Create an empty model (host handle; device memory owned by the model). */
+int bk_model_create(bk_model** model);
+/* Release a model and its device memory. NULL is accepted. */
+void bk_model_destroy(bk_model* model);
+/* Load / save a model file (host path). Format: little-endian, magic "BKMLP001",
+ * header of doubles (normalisation, training box, margins), then the parameters.
+ * bk_model_load synchronises the device. */
+int bk_model_load(bk_model* model, const char* path);
+int bk_model_save(const bk_model* model, const char* path);
+
+/* Train the model on n (nu, x) pairs (device arrays): targets come from
+ * bk_window at cfg's thresholds, then minibatch Adam on the expectile loss.
+ * Synchronises the stream; *final_loss (host, may be NULL) receives the mean
+ * loss of the last epoch. Sets the training box from the data range. */
+int bk_model_train(bk_model* model, const double* nu, const double* x, int64_t n,
+                   const bk_train_cfg* cfg, float* final_loss, hipStream_t stream);
+
+/* Set the safety margins used at inference: t_lo -= d_lo, t_hi += d_hi,
+ * N = ceil(N_pred * (1 + eta) + n_add) (host values). */
+int bk_model_set_margins(bk_model* model, double d_lo, double d_hi, double eta, double n_add);
+
+/* Copy the flat FP32 parameter vector to host (BK_MLP_NPARAM floats) or set it. */
+int bk_model_get_params(const bk_model* model, float* host_params);
+int bk_model_set_params(bk_model* model, const float* host_params);
+
+/* Normalisation constants: norm[0..7] = cx, sx, cnu, snu, st, sn, (unused) (host). */
+int bk_model_get_norm(const bk_model* model, double* norm8);
+int bk_model_set_norm(bk_model* model, const double* norm8);
+
+/* Training box: box[0..3] = log10 x min, log10 x max, nu min, nu max (host). */
+int bk_model_get_box(const bk_model* model, double* box4);
+int bk_model_set_box(bk_model* model, const double* box4);
+
+/* MLP forward pass as used at inference (FP16 matrix-core products with FP32
+ * accumulation) on n normalised inputs u (n x 2 floats, device), writing y
+ * (n x 3 floats, device): y = W3 relu(W2 relu(W1 u + b1) + b2) + b3. */
+int bk_mlp_infer(const bk_model* model, const float* u, float* y, int64_t n, hipStream_t stream);
+
+/* Loss and gradient for one batch in FP32, the kernels training uses:
+ * params (BK_MLP_NPARAM floats), u (B x 2), target (B x 3), tau (3) device;
+ * grad (BK_MLP_NPARAM floats) and loss (1 float) device outputs, overwritten.
+ * Loss = sum_k mean_b |tau_k - [e_bk < 0]| e_bk^2 with e = target - y.
+ * scratch: device buffer of at least bk_mlp_grad_scratch_bytes(B) bytes. */
+int bk_mlp_grad(const float* params, const float* u, const float* target, const float* tau,
+                int64_t B, float* grad, float* loss, void* scratch, size_t scratch_bytes,
+                hipStream_t stream);
+size_t bk_mlp_grad_scratch_bytes(int64_t B);
+
+/* One Adam update in place on device arrays of length n (Kingma & Ba 2015):
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; p -= lr mhat / (sqrt(vhat) + eps),
+ * with mhat = m / (1 - b1^step), vhat = v / (1 - b2^step); step >= 1. */
+int bk_adam_step(float* p, const float* g, float* m, float* v, int64_t n, int32_t step,
+                 float lr, float beta1, float beta2, float eps, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BESSELK_H */

@@ -1,0 +1,307 @@
+"""ctypes binding of libbesselk.so (include/besselk.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library. Tensors are torch CUDA (HIP) tensors; the work is enqueued on torch's
+current stream unless a stream is given. If the library is missing this module
+raises at import: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbesselk.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libbesselk.so is not built (run __graft_entry__.build() or "
+                      "python paper_2502_00356_amd/build.py); there is no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+PLAIN_F64, MIXED_F32C, LEARNED = 0, 1, 2
+RESULT_K, RESULT_SCALED, RESULT_LOG = 0, 1, 2
+OUT_F64, OUT_F32 = 0, 1
+STAT_ENTRIES, STAT_NODES, STAT_FB_RANGE, STAT_FB_TAIL, STAT_FB_STEP, STAT_FB_NONFINITE = range(6)
+STATS_LEN = 8
+MLP_NPARAM = 4547
+MODES = {"plain": PLAIN_F64, "mixed": MIXED_F32C, "learned": LEARNED}
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("mode", _i32), ("result", _i32), ("out_dtype", _i32), ("reserved0", _i32),
+                ("L_window", _dbl), ("L_quad", _dbl), ("sigma2", _dbl), ("beta", _dbl), ("nu", _dbl),
+                ("model", _vp), ("stats", _vp), ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class Locs(ctypes.Structure):
+    _fields_ = [("x", _vp), ("y", _vp), ("n", _i64)]
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("epochs", _i32), ("batch", _i32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("tau_lo", ctypes.c_float),
+                ("tau_hi", ctypes.c_float), ("tau_n", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("L_window", _dbl), ("L_quad", _dbl)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_status_str = _sig("bk_status_str", ctypes.c_char_p, [ctypes.c_int])
+_version = _sig("bk_version", ctypes.c_int, [])
+_besselk = _sig("bk_besselk", ctypes.c_int, [_vp, _vp, _vp, _i64, _vp])
+_besselk_ex = _sig("bk_besselk_ex", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(Params), _vp])
+_ws_bytes = _sig("bk_workspace_bytes", ctypes.c_size_t, [_i64])
+_matern = _sig("bk_matern_tiles", ctypes.c_int, [ctypes.POINTER(Locs), ctypes.POINTER(Params), _i32, _i32, _vp, _vp])
+_out_elems = _sig("bk_matern_out_elems", _i64, [_i64, _i32, _i32])
+_tile_off = _sig("bk_matern_tile_offset", _i64, [_i64, _i32, _i32, _i32, _i32])
+_window = _sig("bk_window", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _dbl, _dbl, _vp])
+_m_create = _sig("bk_model_create", ctypes.c_int, [ctypes.POINTER(_vp)])
+_m_destroy = _sig("bk_model_destroy", None, [_vp])
+_m_load = _sig("bk_model_load", ctypes.c_int, [_vp, ctypes.c_char_p])
+_m_save = _sig("bk_model_save", ctypes.c_int, [_vp, ctypes.c_char_p])
+_m_train = _sig("bk_model_train", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(TrainCfg),
+                                                 ctypes.POINTER(ctypes.c_float), _vp])
+_m_margins = _sig("bk_model_set_margins", ctypes.c_int, [_vp, _dbl, _dbl, _dbl, _dbl])
+_m_getp = _sig("bk_model_get_params", ctypes.c_int, [_vp, _vp])
+_m_setp = _sig("bk_model_set_params", ctypes.c_int, [_vp, _vp])
+_m_getn = _sig("bk_model_get_norm", ctypes.c_int, [_vp, _vp])
+_m_setn = _sig("bk_model_set_norm", ctypes.c_int, [_vp, _vp])
+_m_getb = _sig("bk_model_get_box", ctypes.c_int, [_vp, _vp])
+_m_setb = _sig("bk_model_set_box", ctypes.c_int, [_vp, _vp])
+_mlp_infer = _sig("bk_mlp_infer", ctypes.c_int, [_vp, _vp, _vp, _i64, _vp])
+_mlp_grad = _sig("bk_mlp_grad", ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, ctypes.c_size_t, _vp])
+_mlp_grad_scratch = _sig("bk_mlp_grad_scratch_bytes", ctypes.c_size_t, [_i64])
+_adam = _sig("bk_adam_step", ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float, ctypes.c_float,
+                                            ctypes.c_float, ctypes.c_float, _vp])
+
+
+class BkError(RuntimeError):
+    def __init__(self, status):
+        self.status = status
+        super().__init__(_status_str(status).decode())
+
+
+def _check(st):
+    if st != 0:
+        raise BkError(st)
+
+
+def status_str(st):
+    return _status_str(st).decode()
+
+
+def version():
+    return _version()
+
+
+def _stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev(t, dtype):
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError("expected a contiguous %s tensor" % dtype)
+    return t.data_ptr()
+
+
+def _mode(mode):
+    return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def workspace_bytes(n):
+    return int(_ws_bytes(int(n)))
+
+
+def besselk(nu, x, out=None, mode="plain", result=RESULT_K, L_window=0.0, L_quad=0.0,
+            stats=None, model=None, workspace=None, stream=None):
+    """K_nu(x) (or e^x K, log K) for device float64 tensors nu, x of equal size."""
+    n = x.numel()
+    if nu.numel() != n:
+        raise ValueError("nu and x differ in size")
+    if out is None:
+        out = torch.empty_like(x)
+    if out.numel() != n:
+        raise ValueError("out has the wrong size")
+    m = _mode(mode)
+    if m == LEARNED and workspace is None and n > 0:
+        workspace = torch.empty(workspace_bytes(n), dtype=torch.uint8, device=x.device)
+    p = Params(mode=m, result=int(result), L_window=float(L_window), L_quad=float(L_quad),
+               model=(model.handle if model is not None else None),
+               stats=(_dev(stats, torch.int64) if stats is not None else None),
+               workspace=(workspace.data_ptr() if workspace is not None else None),
+               workspace_bytes=(workspace.numel() * workspace.element_size() if workspace is not None else 0))
+    _check(_besselk_ex(_dev(nu, torch.float64), _dev(x, torch.float64), _dev(out, torch.float64), n,
+                       ctypes.byref(p), _stream(stream)))
+    return out
+
+
+def besselk_plain(nu, x, out, stream=None):
+    """The fixed-signature entry point bk_besselk (plain FP64, default window)."""
+    _check(_besselk(_dev(nu, torch.float64), _dev(x, torch.float64), _dev(out, torch.float64),
+                    x.numel(), _stream(stream)))
+    return out
+
+
+def window(nu, x, L_window=0.0, L_quad=0.0, stream=None):
+    """Plain-solver window (t_lo, t_hi, N) per pair (training targets of the MLP)."""
+    n = x.numel()
+    tlo = torch.empty_like(x)
+    thi = torch.empty_like(x)
+    nodes = torch.empty(n, dtype=torch.int32, device=x.device)
+    _check(_window(_dev(nu, torch.float64), _dev(x, torch.float64), tlo.data_ptr(), thi.data_ptr(),
+                   nodes.data_ptr(), n, float(L_window), float(L_quad), _stream(stream)))
+    return tlo, thi, nodes
+
+
+def matern_out_elems(n, tile_size, lower_only):
+    return int(_out_elems(int(n), int(tile_size), int(lower_only)))
+
+
+def matern_tile_offset(n, tile_size, lower_only, I, J):
+    return int(_tile_off(int(n), int(tile_size), int(lower_only), int(I), int(J)))
+
+
+def matern_tiles(lx, ly, sigma2, beta, nu, tile_size, lower_only, mode="plain", out_dtype=OUT_F64,
+                 out=None, model=None, L_window=0.0, L_quad=0.0, stream=None):
+    """Tiled Matern covariance (packed tiles, see bk_matern_tiles)."""
+    n = lx.numel()
+    if ly.numel() != n:
+        raise ValueError("lx and ly differ in size")
+    elems = matern_out_elems(n, tile_size, lower_only)
+    dt = torch.float32 if int(out_dtype) == OUT_F32 else torch.float64
+    if out is None:
+        out = torch.empty(max(elems, 0), dtype=dt, device=lx.device)
+    if out.numel() < elems or out.dtype != dt:
+        raise ValueError("out too small or of the wrong dtype")
+    locs = Locs(x=_dev(lx, torch.float64), y=_dev(ly, torch.float64), n=n)
+    p = Params(mode=_mode(mode), out_dtype=int(out_dtype), sigma2=float(sigma2), beta=float(beta), nu=float(nu),
+               L_window=float(L_window), L_quad=float(L_quad),
+               model=(model.handle if model is not None else None))
+    _check(_matern(ctypes.byref(locs), ctypes.byref(p), int(tile_size), int(lower_only), out.data_ptr(),
+                   _stream(stream)))
+    return out
+
+
+def unpack_tiles(packed, n, tile_size, lower_only):
+    """Host helper: rebuild the dense n x n matrix (torch CPU tensor) from the packed
+    tile buffer; tiles not stored (upper part when lower_only) are filled by symmetry."""
+    packed = packed.cpu()
+    A = torch.zeros((n, n), dtype=packed.dtype)
+    T = (n + tile_size - 1) // tile_size
+    for J in range(T):
+        for I in range(T):
+            off = matern_tile_offset(n, tile_size, lower_only, I, J)
+            if off < 0:
+                continue
+            m = min(tile_size, n - I * tile_size)
+            w = min(tile_size, n - J * tile_size)
+            blk = packed[off:off + m * w].reshape(w, m).T
+            A[I * tile_size:I * tile_size + m, J * tile_size:J * tile_size + w] = blk
+            if lower_only and I != J:
+                A[J * tile_size:J * tile_size + w, I * tile_size:I * tile_size + m] = blk.T
+    return A
+
+
+class Model:
+    """Handle of a window-predicting MLP (bk_model)."""
+
+    def __init__(self, path=None):
+        h = _vp()
+        _check(_m_create(ctypes.byref(h)))
+        self.handle = h.value
+        if path is not None:
+            self.load(path)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _m_destroy(h)
+            self.handle = None
+
+    def load(self, path):
+        _check(_m_load(self.handle, os.fsencode(path)))
+
+    def save(self, path):
+        _check(_m_save(self.handle, os.fsencode(path)))
+
+    def train(self, nu, x, epochs=40, batch=4096, lr=2e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              tau=(0.1, 0.9, 0.9), seed=1234, L_window=0.0, L_quad=0.0, stream=None):
+        cfg = TrainCfg(epochs=epochs, batch=batch, lr=lr, beta1=beta1, beta2=beta2, eps=eps,
+                       tau_lo=tau[0], tau_hi=tau[1], tau_n=tau[2], seed=seed,
+                       L_window=float(L_window), L_quad=float(L_quad))
+        loss = ctypes.c_float(0.0)
+        _check(_m_train(self.handle, _dev(nu, torch.float64), _dev(x, torch.float64), x.numel(),
+                        ctypes.byref(cfg), ctypes.byref(loss), _stream(stream)))
+        return loss.value
+
+    def set_margins(self, d_lo, d_hi, eta, n_add):
+        _check(_m_margins(self.handle, float(d_lo), float(d_hi), float(eta), float(n_add)))
+
+    def get_params(self):
+        t = torch.empty(MLP_NPARAM, dtype=torch.float32)
+        _check(_m_getp(self.handle, t.data_ptr()))
+        return t
+
+    def set_params(self, params):
+        t = params.detach().to("cpu", torch.float32).contiguous()
+        _check(_m_setp(self.handle, t.data_ptr()))
+
+    def get_norm(self):
+        t = torch.empty(8, dtype=torch.float64)
+        _check(_m_getn(self.handle, t.data_ptr()))
+        return t
+
+    def set_norm(self, norm8):
+        t = torch.as_tensor(norm8, dtype=torch.float64).contiguous()
+        _check(_m_setn(self.handle, t.data_ptr()))
+
+    def get_box(self):
+        t = torch.empty(4, dtype=torch.float64)
+        _check(_m_getb(self.handle, t.data_ptr()))
+        return t
+
+    def set_box(self, box4):
+        t = torch.as_tensor(box4, dtype=torch.float64).contiguous()
+        _check(_m_setb(self.handle, t.data_ptr()))
+
+    def infer(self, u, stream=None):
+        """Raw MLP forward (FP16 matrix cores) on normalised inputs u (n x 2 float32)."""
+        n = u.shape[0]
+        y = torch.empty((n, 3), dtype=torch.float32, device=u.device)
+        _check(_mlp_infer(self.handle, _dev(u, torch.float32), y.data_ptr(), n, _stream(stream)))
+        return y
+
+
+def mlp_grad(params, u, target, tau, stream=None):
+    """FP32 loss and gradient of one batch with the training kernels."""
+    B = u.shape[0]
+    grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=u.device)
+    loss = torch.empty(1, dtype=torch.float32, device=u.device)
+    sb = int(_mlp_grad_scratch(B))
+    scratch = torch.empty(max(sb, 1), dtype=torch.uint8, device=u.device)
+    _check(_mlp_grad(_dev(params, torch.float32), _dev(u, torch.float32), _dev(target, torch.float32),
+                     _dev(tau, torch.float32), B, grad.data_ptr(), loss.data_ptr(), scratch.data_ptr(), sb,
+                     _stream(stream)))
+    return loss, grad
+
+
+def adam_step(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(_adam(_dev(p, torch.float32), _dev(g, torch.float32), _dev(m, torch.float32), _dev(v, torch.float32),
+                 p.numel(), int(step), float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))

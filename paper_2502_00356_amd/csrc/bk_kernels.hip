@@ -1,0 +1,360 @@
+// bk_kernels.hip - HIP kernels and C ABI for standalone K_nu(x), the window
+// export and tiled Matern covariance generation (arXiv 2502.00356, Sec. IV-B,
+// Sec. III-A, Alg. 3), for gfx950.
+//
+// Mapping: one lane per output entry, 256-lane workgroups (four wave64s).
+// Standalone: entry i = global lane id, coalesced FP64 loads/stores.
+// Matern: each wave covers 64 consecutive rows of a tile column (one 512-byte
+// FP64 or 256-byte FP32 store per column); the row location lives in VGPRs and
+// the column location is wave-uniform, so it is read through scalar loads
+// instead of being staged in LDS.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/besselk.h"
+#include "bk_math.hpp"
+#include "bk_internal.hpp"
+
+namespace bk {
+
+// ---------------------------------------------------------------------------
+// Host-side constants of the node-count rule: strip half-widths
+// a = (pi/2) 2^(-k/2) and (pi/2)(1 - 2^(-k/2)), k = 1..8 (15 distinct values).
+// ---------------------------------------------------------------------------
+const RuleTable& rule_table()
+{
+    static RuleTable R = [] {
+        RuleTable t;
+        double vals[16];
+        int n = 0;
+        for (int k = 1; k <= 8; ++k) {
+            double f = pow(2.0, -k / 2.0);
+            double c1 = 1.5707963267948966192 * f, c2 = 1.5707963267948966192 * (1.0 - f);
+            bool d1 = false, d2 = false;
+            for (int j = 0; j < n; ++j) {
+                if (fabs(vals[j] - c1) < 1e-15) d1 = true;
+                if (fabs(vals[j] - c2) < 1e-15) d2 = true;
+            }
+            if (!d1) vals[n++] = c1;
+            if (!d2 && fabs(c1 - c2) >= 1e-15) vals[n++] = c2;
+        }
+        for (int k = 0; k < kRuleCand; ++k) {
+            double a = vals[k < n ? k : n - 1];
+            t.a[k] = a;
+            t.omc[k] = 1.0 - cos(a);
+            t.lsec[k] = -log(cos(a));
+        }
+        return t;
+    }();
+    return R;
+}
+
+void resolve_thresholds(int mode, double L_in, double Lq_in, double* L, double* Lq)
+{
+    bool plain = (mode == BK_PLAIN_F64);
+    *L = L_in > 0.0 ? L_in : (plain ? kDefaultLPlain : kDefaultLMixed);
+    *Lq = Lq_in > 0.0 ? Lq_in : (plain ? kDefaultLqPlain : kDefaultLqMixed);
+}
+
+// Sum of a per-lane value over the workgroup, added once to a global counter.
+__device__ void block_count(unsigned long long* dst, unsigned long long v)
+{
+    __shared__ unsigned long long red[4];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(dst, red[0] + red[1] + red[2] + red[3]);
+}
+
+// Special values shared by every form; returns true if handled.
+__device__ __forceinline__ bool special_value(double v, double z, int result, double& r)
+{
+    if (isnan(v) || isnan(z) || z < 0.0) { r = __builtin_nan(""); return true; }
+    if (z == 0.0 || isinf(v)) { r = __builtin_inf(); return true; }
+    if (isinf(z)) { r = (result == BK_RESULT_LOG) ? -__builtin_inf() : 0.0; return true; }
+    return false;
+}
+
+// Final assembly from exp(-x) exp(Delta) h S (see bk_math.hpp).
+__device__ __forceinline__ double assemble(double z, double delta, double hs, int result)
+{
+    if (result == BK_RESULT_SCALED) return exp(delta) * hs;
+    if (result == BK_RESULT_LOG) return (delta - z) + log(hs);
+    if (z < 708.0) return exp(-z) * exp(delta) * hs;   // exp(-z) still a normal number
+    return exp((delta - z) + log(hs));                   // subnormal range: one rounding
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_besselk(const double* __restrict__ nu,
+                                                 const double* __restrict__ x,
+                                                 double* __restrict__ out, int64_t n, int result,
+                                                 double L, double Lq, RuleTable R,
+                                                 unsigned long long* __restrict__ stats)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    unsigned long long nodes = 0, ents = 0;
+    if (i < n) {
+        double v = fabs(nu[i]), z = x[i], r;
+        if (!special_value(v, z, result, r)) {
+            Solved s = plain_solve(v, z, L, Lq, R);
+            double S = (MODE == BK_PLAIN_F64) ? sum_f64(v, s.p, s.A, s.B) : sum_mixed(v, s.p, s.A, s.B);
+            r = assemble(z, s.delta, s.p.h * S, result);
+            nodes = (unsigned long long)(s.p.N + 1);
+            ents = 1;
+        }
+        out[i] = r;
+    }
+    if (stats) {
+        block_count(stats + BK_STAT_NODES, nodes);
+        block_count(stats + BK_STAT_ENTRIES, ents);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_window(const double* __restrict__ nu,
+                                                const double* __restrict__ x,
+                                                double* __restrict__ tlo, double* __restrict__ thi,
+                                                int32_t* __restrict__ nodes, int64_t n, double L,
+                                                double Lq, RuleTable R)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double v = fabs(nu[i]), z = x[i];
+    if (!(z > 0.0) || isinf(z) || isnan(v) || isinf(v)) {
+        tlo[i] = __builtin_nan(""); thi[i] = __builtin_nan(""); nodes[i] = 0;
+        return;
+    }
+    Solved s = plain_solve(v, z, L, Lq, R);
+    tlo[i] = s.p.t0;
+    thi[i] = s.t1;
+    nodes[i] = s.p.N;
+}
+
+// ---------------------------------------------------------------------------
+// Matern tiles
+// ---------------------------------------------------------------------------
+constexpr int kRowsPerWave = 64;
+constexpr int kColsPerWave = 8;
+constexpr int kColsPerGroup = 4 * kColsPerWave;
+
+struct TileGeom {
+    int64_t n;
+    int32_t ts, T, lower;
+    int32_t rb_per_tile, cb_per_tile;
+};
+
+__host__ __device__ inline int64_t tile_offset(int64_t n, int64_t ts, int64_t T, int lower, int64_t I, int64_t J)
+{
+    int64_t nJ = (J == T - 1) ? n - J * ts : ts;
+    if (lower) return ts * (J * n - ts * (J * (J - 1) / 2)) + nJ * (I - J) * ts;
+    return J * ts * n + nJ * I * ts;
+}
+
+__device__ inline void tile_of(int64_t p, const TileGeom& g, int64_t& I, int64_t& J)
+{
+    int64_t T = g.T;
+    if (!g.lower) { J = p / T; I = p - J * T; return; }
+    // largest J with off(J) = J T - J (J - 1) / 2 <= p
+    double b = 2.0 * (double)T + 1.0;
+    int64_t j = (int64_t)floor((b - sqrt(fmax(b * b - 8.0 * (double)p, 0.0))) * 0.5);
+    if (j < 0) j = 0;
+    if (j > T - 1) j = T - 1;
+    while (j > 0 && j * T - j * (j - 1) / 2 > p) --j;
+    while (j + 1 <= T - 1 && (j + 1) * T - (j + 1) * j / 2 <= p) ++j;
+    J = j;
+    I = J + (p - (J * T - J * (J - 1) / 2));
+}
+
+template <int MODE, typename OutT>
+__global__ __launch_bounds__(256) void k_matern(const double* __restrict__ lx,
+                                                const double* __restrict__ ly, TileGeom g,
+                                                int64_t tile_base, double sigma2, double inv_beta,
+                                                double nu, double pref, double L, double Lq,
+                                                RuleTable R, OutT* __restrict__ out)
+{
+    const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
+    const int64_t p = tile_base + (int64_t)blockIdx.x / wg_per_tile;
+    const int64_t local = (int64_t)blockIdx.x % wg_per_tile;
+    const int rb = (int)(local % g.rb_per_tile), cb = (int)(local / g.rb_per_tile);
+    int64_t I, J;
+    tile_of(p, g, I, J);
+    const int64_t mI = min((int64_t)g.ts, g.n - I * g.ts);
+    const int64_t nJ = min((int64_t)g.ts, g.n - J * g.ts);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t il = (int64_t)rb * kRowsPerWave + lane;
+    const int64_t jl0 = (int64_t)cb * kColsPerGroup + (int64_t)wave * kColsPerWave;
+    if (il >= mI || jl0 >= nJ) return;
+    const int64_t base = tile_offset(g.n, g.ts, g.T, g.lower, I, J);
+    const double xi = lx[I * g.ts + il], yi = ly[I * g.ts + il];
+    const int cend = (int)min((int64_t)kColsPerWave, nJ - jl0);
+    for (int c = 0; c < cend; ++c) {
+        const int64_t jl = jl0 + c;
+        const double xj = lx[J * g.ts + jl], yj = ly[J * g.ts + jl];
+        const double dx = xj - xi, dy = yj - yi;
+        const double r = sqrt(dx * dx + dy * dy);
+        double val;
+        if (r == 0.0) {
+            val = sigma2;
+        } else {
+            const double z = r * inv_beta;
+            Solved s = plain_solve(nu, z, L, Lq, R);
+            double S = (MODE == BK_PLAIN_F64) ? sum_f64(nu, s.p, s.A, s.B) : sum_mixed(nu, s.p, s.A, s.B);
+            val = sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * (s.p.h * S);
+        }
+        out[base + il + jl * mI] = (OutT)val;
+    }
+}
+
+}  // namespace bk
+
+using namespace bk;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" const char* bk_status_str(int status)
+{
+    switch (status) {
+    case BK_OK: return "BK_OK";
+    case BK_EINVAL: return "BK_EINVAL: invalid argument";
+    case BK_EHIP: return "BK_EHIP: HIP runtime error";
+    case BK_ENOMEM: return "BK_ENOMEM: workspace too small or allocation failed";
+    case BK_ENOMODEL: return "BK_ENOMODEL: learned form requested without a trained model";
+    case BK_EIO: return "BK_EIO: model file error";
+    default: return "unknown bk_status";
+    }
+}
+
+extern "C" int bk_version(void) { return 10000; }
+
+static int launch_status() { return hipGetLastError() == hipSuccess ? BK_OK : BK_EHIP; }
+
+extern "C" int bk_besselk(const double* nu, const double* x, double* out, int64_t n, hipStream_t stream)
+{
+    bk_params p;
+    memset(&p, 0, sizeof(p));
+    p.mode = BK_PLAIN_F64;
+    return bk_besselk_ex(nu, x, out, n, &p, stream);
+}
+
+extern "C" int bk_besselk_ex(const double* nu, const double* x, double* out, int64_t n,
+                             const bk_params* prm, hipStream_t stream)
+{
+    if (!prm || n < 0) return BK_EINVAL;
+    if (n == 0) return BK_OK;
+    if (!nu || !x || !out) return BK_EINVAL;
+    if (prm->result < BK_RESULT_K || prm->result > BK_RESULT_LOG) return BK_EINVAL;
+    if (prm->L_window < 0.0 || prm->L_quad < 0.0) return BK_EINVAL;
+    double L, Lq;
+    resolve_thresholds(prm->mode, prm->L_window, prm->L_quad, &L, &Lq);
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffffLL) return BK_EINVAL;
+    const RuleTable& R = rule_table();
+    switch (prm->mode) {
+    case BK_PLAIN_F64:
+        hipLaunchKernelGGL(k_besselk<BK_PLAIN_F64>, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           nu, x, out, n, prm->result, L, Lq, R, prm->stats);
+        return launch_status();
+    case BK_MIXED_F32C:
+        hipLaunchKernelGGL(k_besselk<BK_MIXED_F32C>, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           nu, x, out, n, prm->result, L, Lq, R, prm->stats);
+        return launch_status();
+    case BK_LEARNED:
+        return bk_besselk_learned(nu, x, out, n, prm, L, Lq, stream);
+    default:
+        return BK_EINVAL;
+    }
+}
+
+extern "C" int bk_window(const double* nu, const double* x, double* t_lo, double* t_hi, int32_t* nodes,
+                         int64_t n, double L_window, double L_quad, hipStream_t stream)
+{
+    if (n < 0 || L_window < 0.0 || L_quad < 0.0) return BK_EINVAL;
+    if (n == 0) return BK_OK;
+    if (!nu || !x || !t_lo || !t_hi || !nodes) return BK_EINVAL;
+    double L, Lq;
+    resolve_thresholds(BK_MIXED_F32C, L_window, L_quad, &L, &Lq);
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffffLL) return BK_EINVAL;
+    hipLaunchKernelGGL(k_window, dim3((unsigned)blocks), dim3(256), 0, stream, nu, x, t_lo, t_hi, nodes,
+                       n, L, Lq, rule_table());
+    return launch_status();
+}
+
+extern "C" int64_t bk_matern_out_elems(int64_t n, int32_t tile_size, int32_t lower_only)
+{
+    if (n < 0 || tile_size <= 0) return -1;
+    if (n == 0) return 0;
+    int64_t ts = tile_size, T = (n + ts - 1) / ts;
+    if (!lower_only) return n * n;
+    return tile_offset(n, ts, T, 1, T - 1, T - 1) + (n - (T - 1) * ts) * (n - (T - 1) * ts);
+}
+
+extern "C" int64_t bk_matern_tile_offset(int64_t n, int32_t tile_size, int32_t lower_only, int32_t I, int32_t J)
+{
+    if (n <= 0 || tile_size <= 0) return -1;
+    int64_t ts = tile_size, T = (n + ts - 1) / ts;
+    if (I < 0 || J < 0 || I >= T || J >= T) return -1;
+    if (lower_only && J > I) return -1;
+    return tile_offset(n, ts, T, lower_only ? 1 : 0, I, J);
+}
+
+template <int MODE, typename OutT>
+static int launch_matern(const bk_locs* locs, const bk_params* prm, const TileGeom& g, int64_t ntiles,
+                         double L, double Lq, void* out, hipStream_t stream)
+{
+    const double nu = prm->nu;
+    const double pref = (1.0 - nu) * kLn2 - lgamma(nu);
+    const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
+    const int64_t max_wg = 1LL << 23;                      // keeps a launch below 2^31 work-items
+    const int64_t tiles_per_launch = max_wg / wg_per_tile > 0 ? max_wg / wg_per_tile : 1;
+    const RuleTable& R = rule_table();
+    for (int64_t t0 = 0; t0 < ntiles; t0 += tiles_per_launch) {
+        int64_t nt = ntiles - t0 < tiles_per_launch ? ntiles - t0 : tiles_per_launch;
+        hipLaunchKernelGGL((k_matern<MODE, OutT>), dim3((unsigned)(nt * wg_per_tile)), dim3(256), 0, stream,
+                           locs->x, locs->y, g, t0, prm->sigma2, 1.0 / prm->beta, nu, pref, L, Lq, R,
+                           (OutT*)out);
+        int st = launch_status();
+        if (st != BK_OK) return st;
+    }
+    return BK_OK;
+}
+
+extern "C" int bk_matern_tiles(const bk_locs* locs, const bk_params* prm, int32_t tile_size,
+                               int32_t lower_only, void* out, hipStream_t stream)
+{
+    if (!locs || !prm || tile_size <= 0 || locs->n < 0) return BK_EINVAL;
+    if (!(prm->beta > 0.0) || !(prm->nu > 0.0) || !(prm->sigma2 >= 0.0) || isinf(prm->nu) || isinf(prm->beta))
+        return BK_EINVAL;
+    if (prm->out_dtype != BK_OUT_F64 && prm->out_dtype != BK_OUT_F32) return BK_EINVAL;
+    if (prm->L_window < 0.0 || prm->L_quad < 0.0) return BK_EINVAL;
+    if (locs->n == 0) return BK_OK;
+    if (!locs->x || !locs->y || !out) return BK_EINVAL;
+    TileGeom g;
+    g.n = locs->n;
+    g.ts = tile_size;
+    g.T = (int32_t)((locs->n + tile_size - 1) / tile_size);
+    g.lower = lower_only ? 1 : 0;
+    g.rb_per_tile = (tile_size + kRowsPerWave - 1) / kRowsPerWave;
+    g.cb_per_tile = (tile_size + kColsPerGroup - 1) / kColsPerGroup;
+    const int64_t T = g.T;
+    const int64_t ntiles = g.lower ? T * (T + 1) / 2 : T * T;
+    double L, Lq;
+    resolve_thresholds(prm->mode, prm->L_window, prm->L_quad, &L, &Lq);
+    const bool f32 = prm->out_dtype == BK_OUT_F32;
+    switch (prm->mode) {
+    case BK_PLAIN_F64:
+        return f32 ? launch_matern<BK_PLAIN_F64, float>(locs, prm, g, ntiles, L, Lq, out, stream)
+                   : launch_matern<BK_PLAIN_F64, double>(locs, prm, g, ntiles, L, Lq, out, stream);
+    case BK_MIXED_F32C:
+        return f32 ? launch_matern<BK_MIXED_F32C, float>(locs, prm, g, ntiles, L, Lq, out, stream)
+                   : launch_matern<BK_MIXED_F32C, double>(locs, prm, g, ntiles, L, Lq, out, stream);
+    case BK_LEARNED:
+        return bk_matern_learned(locs, prm, tile_size, lower_only, out, L, Lq, stream);
+    default:
+        return BK_EINVAL;
+    }
+}

@@ -1,0 +1,301 @@
+// bk_math.hpp - per-entry device routines for K_nu(x) by finite-window trapezoid
+// quadrature of K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt (Sec. IV-B).
+//
+// Notation follows Sec. IV-B: g(t) = log cosh(nu t) - x cosh t is the
+// log-integrand, t* its maximiser over t >= 0 ("t_max"), [t0, t1] the window on
+// which g(t) >= g(t*) - L, and the trapezoid sum is taken relative to a reference
+// point t_ref (Eq. "refined": log K = g(t_ref) + log sum h c_m exp(g(t_m) - g(t_ref))).
+//
+// Node terms are built without cancellation. With u = t - t_ref, w = u/2:
+//   g(t) - g(t_ref) = nu u + log(1+P(t)) - log(1+P(t_ref)) - xterm,
+//   P(t) = exp(-2 nu t),   xterm = x (cosh t - cosh t_ref)
+//                                = 2 sinh w (x cosh t_ref sinh w + x sinh t_ref cosh w),
+// and along the node grid every exponential is an exact geometric progression,
+// advanced by one multiply (or fused multiply-add) per node in FP64:
+//   V = expm1(|w|), Bw = exp(w), Bb = exp(-w), P = exp(-2 nu t).
+// t_ref is the node nearest t*, so w = 0 falls on a node. Left of it |w| shrinks
+// and V follows V' = (V - qm1) / q; right of it |w| grows and V' = V q + qm1
+// (q = e^(h/2), qm1 = expm1(h/2)). Both directions keep V's relative error at
+// a few ulps; 2 sinh w = sign(w) V (1 + e^-|w|) then has no cancellation.
+// The log(1+P(t_ref)) term cancels against the prefactor, so
+//   K = exp(-x) exp(Delta) h sum_m c_m exp(nu u_m - xterm_m) (1 + P_m),
+//   Delta = nu t_ref - ln 2 - 2 x sinh^2(t_ref / 2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bk {
+
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr int kNodeMin = 4;
+constexpr int kNodeMax = 512;
+constexpr int kRuleCand = 15;
+
+// Node-count rule constants, filled on the host: for each strip half-width a_k,
+// a_k, 1 - cos a_k and log sec a_k (see node_step).
+struct RuleTable {
+    double a[kRuleCand];
+    double omc[kRuleCand];
+    double lsec[kRuleCand];
+};
+
+// Per-entry quadrature plan.
+struct Plan {
+    double tref;   // reference point: node mc, the node nearest the peak
+    double t0;     // first node
+    double h;      // step
+    int N;         // intervals; nodes m = 0..N
+    int mc;        // index of the reference node (0 <= mc <= N)
+};
+
+__device__ __forceinline__ void cosh_sinh(double t, double& ch, double& sh)
+{
+    double e = exp(t);
+    double ei = 1.0 / e;
+    ch = 0.5 * (e + ei);
+    sh = 0.5 * (e - ei);
+}
+
+// log cosh(y) for y >= 0 without overflow: y + log1p(exp(-2y)) - ln 2.
+__device__ __forceinline__ double logcosh_pos(double y)
+{
+    return y + log1p(exp(-2.0 * y)) - kLn2;
+}
+
+// g(t) and g'(t) for t >= 0.
+__device__ __forceinline__ void g_and_gp(double nu, double x, double t, double& g, double& gp)
+{
+    double p = exp(-2.0 * nu * t);
+    double ch, sh;
+    cosh_sinh(t, ch, sh);
+    g = nu * t + log1p(p) - kLn2 - x * ch;
+    gp = nu * (1.0 - p) / (1.0 + p) - x * sh;
+}
+
+// Maximiser t* of g over t >= 0 when nu^2 > x (Sec. IV-B: otherwise t* = 0).
+// g' = nu tanh(nu t) - x sinh t has one zero; since nu tanh < nu, the zero lies
+// left of asinh(nu/x). g' is concave (g''' < 0) and g'' < 0 right of t*, so
+// Newton started at asinh(nu/x) decreases monotonically onto t* (the bracket
+// search of FINDRANGE is replaced by this analytic upper bound).
+__device__ inline double peak_solve(double nu, double x)
+{
+    double t = asinh(fmin(nu / x, 1e300));
+    for (int it = 0; it < 64; ++it) {
+        double p = exp(-2.0 * nu * t);
+        double ip = 1.0 / (1.0 + p);
+        double th = (1.0 - p) * ip;
+        double s2 = 4.0 * p * ip * ip;
+        double ch, sh;
+        cosh_sinh(t, ch, sh);
+        double gp = nu * th - x * sh;
+        double gpp = nu * nu * s2 - x * ch;
+        double dt = gp / gpp;
+        if (!(dt > 0.0)) break;           // at (or numerically past) the root
+        t -= dt;
+        if (dt <= 1e-14 * t || t < 1e-150) break;
+    }
+    return t;
+}
+
+// Root t1 > t* of G(t) = g(t) - gstar + L (g concave and decreasing beyond t*).
+// Start at lo = acosh(cosh t* + L/x): there the x-term alone has dropped by L
+// and the log cosh term has grown, so G(lo) >= 0 (FINDRANGE's lower end). The
+// first Newton step from lo lands on or right of the root because G is concave;
+// from there Newton decreases monotonically onto it.
+__device__ inline double window_right(double nu, double x, double tstar, double chstar,
+                                      double gstar, double L)
+{
+    double t = acosh(chstar + L / x);
+    double tcap = tstar + 4.0 * (t - tstar) + 1.0;     // guard against a flat first step
+    for (int it = 0; it < 64; ++it) {
+        double g, gp;
+        g_and_gp(nu, x, t, g, gp);
+        double dt = (g - gstar + L) / gp;
+        double tn = fmin(t - dt, tcap);
+        if (!(tn > tstar)) tn = 0.5 * (t + tstar);
+        bool done = fabs(tn - t) <= 1e-14 * t;
+        t = tn;
+        if (done) break;
+    }
+    return t;
+}
+
+// Root t0 in (0, t*) of G when G(0) < 0 (only possible if nu t* > L, since g' <= nu).
+// Bracket: G(0) < 0 and G(t* - L/nu) >= 0. Newton, with a bisection step whenever
+// a Newton step would leave the bracket; converged when the Newton step is below
+// the tolerance.
+__device__ inline double window_left(double nu, double x, double tstar, double gstar, double L)
+{
+    double lo = 0.0, hi = fmax(tstar - L / nu, 0.0);
+    double t = hi;
+    for (int it = 0; it < 100; ++it) {
+        double g, gp;
+        g_and_gp(nu, x, t, g, gp);
+        double G = g - gstar + L;
+        if (G >= 0.0) hi = t; else lo = t;
+        double tn = t - G / gp;
+        if (fabs(tn - t) <= 1e-14 * t) { t = fmin(fmax(tn, lo), hi); break; }
+        if (!(tn >= lo && tn <= hi)) tn = 0.5 * (lo + hi);
+        t = tn;
+        if (hi - lo <= 1e-15 * hi) break;
+    }
+    return t;
+}
+
+// Trapezoid step from the strip bound: the best over the candidate half-widths a
+// of 2 pi a / (Lq + ln 2 + x (1 - cos a) + (nu + 1) log sec a).
+__device__ inline double node_step(double nu, double x, double Lq, const RuleTable& R)
+{
+    double base = Lq + kLn2;
+    double nu1 = nu + 1.0;
+    double bn = R.a[0], bd = base + x * R.omc[0] + nu1 * R.lsec[0];
+#pragma unroll
+    for (int k = 1; k < kRuleCand; ++k) {
+        double den = base + x * R.omc[k] + nu1 * R.lsec[k];
+        bool better = R.a[k] * bd > bn * den;
+        bn = better ? R.a[k] : bn;
+        bd = better ? den : bd;
+    }
+    return 6.283185307179586477 * bn / bd;
+}
+
+__device__ __forceinline__ int node_count(double width, double h)
+{
+    double r = ceil(width / h);
+    if (!(r >= (double)kNodeMin)) r = (double)kNodeMin;   // also maps NaN to the minimum
+    if (r > (double)kNodeMax) r = (double)kNodeMax;
+    return (int)r;
+}
+
+// Plain bracket solver (FP64): peak, window at threshold L, node count for Lq,
+// reference node. Also returns, for the prefactor,
+// Delta = nu t_ref - ln 2 - 2 x sinh^2(t_ref/2), and the constants
+// A = x cosh(t_ref)/2, B = x sinh(t_ref)/2 of the cancellation-free xterm.
+struct Solved {
+    Plan p;
+    double delta;
+    double A, B;
+    double gstar;   // g(t*) (used by the window export)
+    double t1;
+};
+
+__device__ inline Solved plain_solve(double nu, double x, double L, double Lq, const RuleTable& R)
+{
+    Solved s;
+    double tstar = 0.0;
+    if (nu * nu > x) tstar = peak_solve(nu, x);
+    double chs, shs;
+    cosh_sinh(tstar, chs, shs);
+    double gstar = logcosh_pos(nu * tstar) - x * chs;
+    double t1 = window_right(nu, x, tstar, chs, gstar, L);
+    double t0 = 0.0;
+    if (-x < gstar - L) t0 = window_left(nu, x, tstar, gstar, L);
+    double h0 = node_step(nu, x, Lq, R);
+    int N = node_count(t1 - t0, h0);
+    double h = (t1 - t0) / (double)N;
+    int mc = 0;
+    if (tstar > t0) {
+        double r = rint((tstar - t0) / h);
+        mc = (int)fmin(fmax(r, 0.0), (double)N);
+    }
+    double tref = t0 + (double)mc * h;
+    double ch, sh;
+    cosh_sinh(tref, ch, sh);
+    double em = expm1(0.5 * tref);                     // sinh(t/2) = em (em + 2) / (2 (em + 1))
+    double sh2 = em * (em + 2.0) / (2.0 * (em + 1.0));
+    s.p.tref = tref;
+    s.p.t0 = t0;
+    s.p.N = N;
+    s.p.mc = mc;
+    s.p.h = h;
+    s.delta = nu * tref - kLn2 - 2.0 * x * sh2 * sh2;
+    s.A = 0.5 * x * ch;
+    s.B = 0.5 * x * sh;
+    s.gstar = gstar;
+    s.t1 = t1;
+    return s;
+}
+
+// Geometric-progression state of one entry's node walk.
+struct Walk {
+    double k, V, Bw, Bb, P;        // at the current node; k = m - mc (exact), u = k h
+    double h, q, qm1, qi, rho;     // per-step factors
+    int mc;
+};
+
+__device__ __forceinline__ Walk walk_begin(double nu, const Plan& p)
+{
+    Walk w;
+    w.mc = p.mc;
+    w.k = -(double)p.mc;
+    w.V = expm1(0.5 * (double)p.mc * p.h);        // expm1(|w_0|), w_0 = -mc h / 2
+    w.Bb = w.V + 1.0;
+    w.Bw = 1.0 / w.Bb;
+    w.P = exp(-2.0 * nu * p.t0);
+    w.h = p.h;
+    w.qm1 = expm1(0.5 * p.h);
+    w.q = w.qm1 + 1.0;
+    w.qi = 1.0 / w.q;
+    w.rho = exp(-2.0 * nu * p.h);
+    return w;
+}
+
+// Exponent nu u - xterm at node m (FP64, cancellation-free).
+__device__ __forceinline__ double walk_exponent(const Walk& w, int m, double nu, double A, double B)
+{
+    double sv = (m < w.mc) ? -w.V : w.V;
+    double sg = sv * (1.0 + fmin(w.Bw, w.Bb));   // 2 sinh(u/2)
+    double c2 = w.Bw + w.Bb;                      // 2 cosh(u/2)
+    double xterm = sg * (A * sg + B * c2);        // x (cosh t - cosh t_ref)
+    return nu * (w.k * w.h) - xterm;
+}
+
+// Advance from node m to node m + 1.
+__device__ __forceinline__ void walk_step(Walk& w, int m)
+{
+    w.k += 1.0;                                   // u = k h is formed per node: no drift
+    w.Bw *= w.q;
+    w.Bb *= w.qi;
+    w.P *= w.rho;
+    double vin = fmax((w.V - w.qm1) * w.qi, 0.0);
+    double vout = fma(w.V, w.q, w.qm1);
+    w.V = (m + 1 <= w.mc) ? vin : vout;
+}
+
+// FP64 trapezoid sum S = sum_m c_m exp(d_m) (1 + P_m), c_0 = c_N = 1/2.
+__device__ inline double sum_f64(double nu, const Plan& p, double A, double B)
+{
+    Walk w = walk_begin(nu, p);
+    double S = 0.0, ends = 0.0;
+    for (int m = 0; m <= p.N; ++m) {
+        double term = exp(walk_exponent(w, m, nu, A, B)) * (1.0 + w.P);
+        S += term;
+        if (m == 0 || m == p.N) ends += term;
+        walk_step(w, m);
+    }
+    return S - 0.5 * ends;
+}
+
+// Mixed form: exponent in FP64, exponential in FP32, Kahan-compensated FP32 sum.
+// Exponents are <= 0 up to a small positive excess (t_ref is within h/2 of t*),
+// so the FP32 argument error |d| 2^-24 only matters for negligible terms.
+__device__ inline double sum_mixed(double nu, const Plan& p, double A, double B)
+{
+    Walk w = walk_begin(nu, p);
+    float s = 0.0f, c = 0.0f, ends = 0.0f;
+    for (int m = 0; m <= p.N; ++m) {
+        float d = (float)walk_exponent(w, m, nu, A, B);
+        float e = __builtin_amdgcn_exp2f(d * 1.44269504f);
+        float term = e * (float)(1.0 + w.P);
+        float y = term - c;
+        float t = s + y;
+        c = (t - s) - y;
+        s = t;
+        if (m == 0 || m == p.N) ends += term;
+        walk_step(w, m);
+    }
+    return (double)s - (double)c - 0.5 * (double)ends;
+}
+
+}  // namespace bk

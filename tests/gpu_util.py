@@ -1,0 +1,30 @@
+"""Shared helpers of the GPU tests (no method arithmetic)."""
+import numpy as np
+
+DBL_MIN = np.finfo(np.float64).tiny
+
+# Parity bars. Plain FP64: relative 1e-13. Mixed and learned: relative 2e-6.
+TOL_PLAIN = 1e-13
+TOL_MIXED = 2e-6
+
+
+def rel_err(got, ref):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        e = np.abs(got - ref) / np.abs(ref)
+    e[(got == ref)] = 0.0
+    return e
+
+
+def re_metric(logk_got, logk_ref):
+    """RE = log10(1 + |log K_ref - log K| / 2^-52), the accuracy metric of Sec. IV-C."""
+    return np.log10(1.0 + np.abs(np.asarray(logk_got) - np.asarray(logk_ref)) / 2.0 ** -52)
+
+
+def to_dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()

@@ -1,0 +1,107 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function that
+include/besselk.h declares, validates arguments before touching the device, and
+computes the tile layout on the host."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "besselk.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(bk_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    path = os.path.join(ROOT, "paper_2502_00356_amd", "libbesselk.so")
+    if not os.path.exists(path):
+        import __graft_entry__
+        __graft_entry__.build()
+    return ctypes.CDLL(path)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_loads():
+    from paper_2502_00356_amd import api
+    assert api.version() == 10000
+    assert api.status_str(0) == "BK_OK"
+    assert "invalid" in api.status_str(1)
+
+
+def test_argument_validation_is_host_side(lib):
+    """Invalid calls return BK_EINVAL before any device work (runs without a GPU)."""
+    from paper_2502_00356_amd import api
+    p = api.Params(mode=0)
+    f = lib.bk_besselk_ex
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.POINTER(api.Params), ctypes.c_void_p]
+    assert f(None, None, None, -1, ctypes.byref(p), None) == 1
+    assert f(None, None, None, 5, ctypes.byref(p), None) == 1          # null arrays
+    assert f(None, None, None, 0, ctypes.byref(p), None) == 0          # n == 0 is a no-op
+    assert f(None, None, None, 5, None, None) == 1                     # null params
+    p.result = 9
+    assert f(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 5, ctypes.byref(p), None) == 1
+    g = lib.bk_window
+    g.restype = ctypes.c_int
+    g.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
+    assert g(None, None, None, None, None, 3, 16.0, 15.0, None) == 1
+    assert g(None, None, None, None, None, -3, 16.0, 15.0, None) == 1
+    m = lib.bk_matern_tiles
+    m.restype = ctypes.c_int
+    m.argtypes = [ctypes.POINTER(api.Locs), ctypes.POINTER(api.Params), ctypes.c_int32, ctypes.c_int32,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    locs = api.Locs(x=None, y=None, n=10)
+    for kw in (dict(beta=0.0, nu=1.0), dict(beta=0.1, nu=0.0), dict(beta=0.1, nu=1.0, sigma2=-1.0),
+               dict(beta=0.1, nu=1.0, out_dtype=5)):
+        q = api.Params(mode=0, sigma2=kw.get("sigma2", 1.0), beta=kw["beta"], nu=kw["nu"],
+                       out_dtype=kw.get("out_dtype", 0))
+        assert m(ctypes.byref(locs), ctypes.byref(q), 4, 1, ctypes.c_void_p(16), None) == 1
+    q = api.Params(mode=0, sigma2=1.0, beta=0.1, nu=1.0)
+    assert m(ctypes.byref(locs), ctypes.byref(q), 0, 1, ctypes.c_void_p(16), None) == 1     # tile size 0
+    assert m(ctypes.byref(locs), ctypes.byref(q), 4, 1, None, None) == 1                   # null out
+    locs0 = api.Locs(x=None, y=None, n=0)
+    assert m(ctypes.byref(locs0), ctypes.byref(q), 4, 1, None, None) == 0
+
+
+@pytest.mark.parametrize("n,ts,lower", [(40000, 960, 1), (99856, 1024, 1), (1024, 1024, 0), (350, 100, 1),
+                                        (350, 100, 0), (1, 5, 1), (7, 7, 1)])
+def test_tile_layout(n, ts, lower):
+    """Offsets follow J-major order with each tile m_I x n_J contiguous, and the
+    last offset plus the last tile's size is the total element count."""
+    from paper_2502_00356_amd import api
+    T = (n + ts - 1) // ts
+    expect = 0
+    for J in range(T):
+        for I in range(T):
+            off = api.matern_tile_offset(n, ts, lower, I, J)
+            if lower and J > I:
+                assert off == -1
+                continue
+            assert off == expect, (I, J)
+            expect += min(ts, n - I * ts) * min(ts, n - J * ts)
+    assert api.matern_out_elems(n, ts, lower) == expect
+    if lower:
+        assert expect == sum(min(ts, n - I * ts) * min(ts, n - J * ts) for J in range(T) for I in range(J, T))
+
+
+def test_workload_sizes():
+    """Sizes of the Matern workloads: 819,097,600 entries for n = 40,000 in lower
+    960-tiles, 5,036,605,696 for the 316 x 316 grid in lower 1,024-tiles."""
+    from paper_2502_00356_amd import api
+    assert api.matern_out_elems(40000, 960, 1) == 819097600
+    assert api.matern_out_elems(99856, 1024, 1) == 5036605696
+    assert api.matern_out_elems(1024, 1024, 0) == 1024 * 1024
