@@ -63,11 +63,18 @@ static long double orc_tmax(long double nu, long double x)
     return 0.5L * (a + b);
 }
 
-typedef struct { long double nu, x, gref; } orc_integrand;
+typedef struct { long double nu, x, that, lcref; } orc_integrand;
 
+/* exp(g(t) - g(t_hat)). The difference is formed without cancellation:
+ *   log cosh(nu t) - log cosh(nu t_hat) - 2 x sinh((t + t_hat)/2) sinh((t - t_hat)/2),
+ * since cosh t - cosh t_hat = 2 sinh((t + t_hat)/2) sinh((t - t_hat)/2). Forming
+ * g(t) - g(t_hat) from the two values instead leaves an absolute error of about
+ * x * LDBL_EPSILON, which for x in the thousands is above the stopping tolerance. */
 static long double orc_phi(const orc_integrand* f, long double t)
 {
-    return expl(orc_g(f->nu, f->x, t) - f->gref);
+    long double d = orc_logcosh(f->nu * t) - f->lcref
+                    - 2.0L * f->x * sinhl(0.5L * (t + f->that)) * sinhl(0.5L * (t - f->that));
+    return expl(d);
 }
 
 /* One 15-point Kronrod evaluation on [a,b] with the embedded 7-point Gauss
@@ -127,16 +134,18 @@ static long double orc_logk(long double nu, long double x, orc_seg* seg, int* ok
     orc_integrand f;
     f.nu = nu; f.x = x;
     long double th = orc_tmax(nu, x);
-    f.gref = orc_g(nu, x, th);
+    f.that = th;
+    f.lcref = orc_logcosh(nu * th);
+    const long double gref = orc_g(nu, x, th);
     /* upper limit: step away from t_hat, doubling, until the integrand is
      * below e^-64 of its peak; past the peak g is decreasing. */
     long double step = 1.0L, T = th + step;
-    while (orc_g(nu, x, T) - f.gref > -64.0L && step < 1e4L) { step *= 2.0L; T = th + step; }
+    while (logl(orc_phi(&f, T)) > -64.0L && step < 1e4L) { step *= 2.0L; T = th + step; }
     const long double tol = 1e-17L;
     long double I = 0.0L;
     if (th > 0.0L) I += orc_adapt(&f, 0.0L, th, tol, seg, ok);
     I += orc_adapt(&f, th, T, tol, seg, ok);
-    return f.gref + logl(I);
+    return gref + logl(I);
 }
 
 /* Exported: K_nu(x) for n pairs, by OpenMP over entries.
