@@ -29,6 +29,21 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # walk in the gfx950 code object of libbesselk.so; exponentials inlined).
 NODE_SLOTS = {"plain": 48.0, "mixed": 39.0, "learned": 44.0}
 
+# HBM bytes per launch of the learned kernel on the 2^24 grid, from the FETCH_SIZE and
+# WRITE_SIZE counter runs scaled by a plain 1 GiB copy (profiles/besselk_grid_2e24_hbm_traffic.txt),
+# valid only for the kernel sources they were taken on (hash below); else reported as null.
+TRAFFIC = {"src_sha": "aeeae0324c79e2a8", "n": 1 << 24, "bytes": 404.2e6}
+KERNEL_SOURCES = ("bk_mlp.hip", "bk_math.hpp", "bk_internal.hpp")
+
+
+def kernel_src_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2502_00356_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -40,7 +55,28 @@ def parse():
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2502_00356_amd", "models", "window_mlp.bin"))
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="grid", choices=["grid", "matern-medium", "matern-large"],
+                    help="grid: the headline standalone workload; matern-*: tiled covariance generation")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a plain 1 GiB device-to-device copy instead (HBM reference for counters)")
     return ap.parse_args()
+
+
+def copy_probe(torch):
+    """A plain copy kernel of known size: 2^27 doubles (1 GiB) read and 1 GiB written."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / 5
+    print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "ms": ms,
+                      "gbps_read_plus_write": 2 * (1 << 30) / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def time_form(api, torch, nu, x, out, form, steps, warmup, model, ws):
@@ -76,7 +112,13 @@ def main():
               "(requested --gpus %d)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
+    if a.copy_probe:
+        copy_probe(torch)
+        return
     from paper_2502_00356_amd import api, workloads
+    if a.workload != "grid":
+        matern_bench(a, torch, api, workloads)
+        return
 
     dev = torch.device("cuda:0")
     nu_h, x_h, half_idx = workloads.grid_pairs(a.n, seed=2)
@@ -87,6 +129,10 @@ def main():
     model = None
     if os.path.exists(a.model):
         model = api.Model(a.model)
+    elif a.form in ("auto", "learned"):
+        # no stored model: train one on the GPU (2^20 pairs, about a second), outside the timed region
+        from paper_2502_00356_amd import train_window_mlp
+        model, _ = train_window_mlp.train(out=None, verbose=False)
     form = a.form
     if form == "auto":
         form = "learned" if model is not None else "mixed"
@@ -99,8 +145,8 @@ def main():
         forms[f] = dict(ms_per_step=ms_ev, wall_ms_per_step=ms_wall, evals_per_s=a.n / (ms_ev * 1e-3),
                         mean_nodes=float(st[api.STAT_NODES]) / max(1, int(st[api.STAT_ENTRIES])),
                         node_total=int(st[api.STAT_NODES]),
-                        fallbacks=int(st[api.STAT_FB_RANGE] + st[api.STAT_FB_TAIL] + st[api.STAT_FB_STEP]
-                                      + st[api.STAT_FB_NONFINITE]))
+                        fallbacks=int(st[api.STAT_FB_RANGE] + st[api.STAT_FB_TAIL] + st[api.STAT_FB_NONFINITE]),
+                        nodes_raised=int(st[api.STAT_NODE_RAISED]))
     head = forms[form]
 
     # accuracy of the timed forms on a bounded sample against the oracle, and the
@@ -149,12 +195,65 @@ def main():
         "speedup_vs_plain_f64": forms["plain"]["ms_per_step"] / head["ms_per_step"] if "plain" in forms else 1.0,
         "max_rel_err_sample": acc,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (VALU lane-ops)",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": (TRAFFIC["bytes"] if (form == "learned" and a.n == TRAFFIC["n"]
+                                                      and kernel_src_sha() == TRAFFIC["src_sha"]) else None),
                      "kernel": "k_besselk<%s>" % form,
                      "work": "%.0f issue slots per trapezoid node x %d nodes per step" % (NODE_SLOTS[form], head["node_total"]),
                      "hbm_gbps": 24.0 * a.n / (head["ms_per_step"] * 1e-3) / 1e9},
         "cpu_baseline": cpu,
     }
+    print(json.dumps(line), flush=True)
+
+
+def matern_bench(a, torch, api, workloads):
+    """Tiled Matern generation: entries/s and HBM write GB/s per form (one JSON line).
+    matern-medium: n = 40,000 uniform (seed 3, Morton), beta = 0.05, nu in {0.8, 2.3},
+    lower 960-tiles, FP64 output. matern-large: 316 x 316 jittered grid (seed 7),
+    beta = 0.02, nu = 3.7, lower 1,024-tiles, FP32 output for mixed/learned and FP64
+    for plain."""
+    dev = torch.device("cuda:0")
+    model = api.Model(a.model) if os.path.exists(a.model) else None
+    if a.workload == "matern-medium":
+        c = workloads.MATERN_MEDIUM
+        xy = workloads.uniform_locations(c["n"], c["seed"])
+        cases = [(nu, f, api.OUT_F64) for nu in c["nus"] for f in ("plain", "mixed", "learned")]
+        beta, ts = c["beta"], c["tile"]
+    else:
+        c = workloads.MATERN_LARGE
+        xy = workloads.jittered_grid_locations(c["side"], c["seed"])
+        cases = [(c["nu"], "plain", api.OUT_F64), (c["nu"], "mixed", api.OUT_F32), (c["nu"], "learned", api.OUT_F32)]
+        beta, ts = c["beta"], c["tile"]
+    n = xy.shape[0]
+    lx = torch.from_numpy(np.ascontiguousarray(xy[:, 0])).to(dev)
+    ly = torch.from_numpy(np.ascontiguousarray(xy[:, 1])).to(dev)
+    elems = api.matern_out_elems(n, ts, 1)
+    res = {}
+    bufs = {}
+    for nu, f, dt in cases:
+        if f == "learned" and model is None:
+            continue
+        tdt = torch.float32 if dt == api.OUT_F32 else torch.float64
+        if tdt not in bufs:
+            bufs[tdt] = torch.empty(elems, dtype=tdt, device=dev)
+        out = bufs[tdt]
+        kw = dict(mode=f, out_dtype=dt, out=out, model=model)
+        for _ in range(max(1, a.warmup)):
+            api.matern_tiles(lx, ly, 1.0, beta, nu, ts, 1, **kw)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        steps = max(1, min(a.steps, 5))
+        ev0.record()
+        for _ in range(steps):
+            api.matern_tiles(lx, ly, 1.0, beta, nu, ts, 1, **kw)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        res["nu=%g/%s" % (nu, f)] = {"ms": round(ms, 3), "entries_per_s": elems / (ms * 1e-3),
+                                     "write_gbps": elems * out.element_size() / (ms * 1e-3) / 1e9,
+                                     "out_dtype": str(tdt).replace("torch.", "")}
+    line = {"metric": "Matern entries/s", "workload": a.workload, "n": n, "tile": ts, "entries": elems,
+            "beta": beta, "results": res}
     print(json.dumps(line), flush=True)
 
 

@@ -44,9 +44,10 @@ typedef enum {
  *                  cancellation, exponentials in FP32, Kahan-compensated FP32 sum,
  *                  FP64 prefactor. Looser window (relative error ~1e-7 class).
  *  BK_LEARNED    : a 2-64-64-3 MLP on (log10 x, nu) predicts the window and node
- *                  count in place of the solve; terms as in BK_MIXED_F32C; entries
- *                  outside the model's training box, or failing the tail and
- *                  step-halving checks, are recomputed with BK_MIXED_F32C. */
+ *                  count in place of the solve (the count is raised to the
+ *                  strip-bound rule's if lower); terms as in BK_MIXED_F32C; entries
+ *                  outside the model's training box, or whose window fails the
+ *                  tail check, are recomputed with BK_MIXED_F32C. */
 typedef enum { BK_PLAIN_F64 = 0, BK_MIXED_F32C = 1, BK_LEARNED = 2 } bk_mode;
 
 /* Matern output element type. */
@@ -62,7 +63,8 @@ enum {
     BK_STAT_NODES = 1,        /* sum over entries of (N + 1) trapezoid nodes    */
     BK_STAT_FB_RANGE = 2,     /* learned: (nu, x) outside the training box      */
     BK_STAT_FB_TAIL = 3,      /* learned: an end node carried too much weight   */
-    BK_STAT_FB_STEP = 4,      /* learned: step-halving estimate above tolerance */
+    BK_STAT_NODE_RAISED = 4,  /* learned: predicted N below the strip-bound rule
+                                 for the predicted window, raised (not a fallback) */
     BK_STAT_FB_NONFINITE = 5, /* learned: non-finite prediction or sum          */
     BK_STATS_LEN = 8
 };

@@ -22,7 +22,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 PLAIN_F64, MIXED_F32C, LEARNED = 0, 1, 2
 RESULT_K, RESULT_SCALED, RESULT_LOG = 0, 1, 2
 OUT_F64, OUT_F32 = 0, 1
-STAT_ENTRIES, STAT_NODES, STAT_FB_RANGE, STAT_FB_TAIL, STAT_FB_STEP, STAT_FB_NONFINITE = range(6)
+STAT_ENTRIES, STAT_NODES, STAT_FB_RANGE, STAT_FB_TAIL, STAT_NODE_RAISED, STAT_FB_NONFINITE = range(6)
 STATS_LEN = 8
 MLP_NPARAM = 4547
 MODES = {"plain": PLAIN_F64, "mixed": MIXED_F32C, "learned": LEARNED}

@@ -1,37 +1,1097 @@
-// bk_mlp.hip - window-predicting MLP: model handle, training and inference kernels,
-// and the learned evaluation form.
+// bk_mlp.hip - the window-predicting MLP (2 -> 64 -> 64 -> 3, ReLU): model handle,
+// FP32 training kernels (forward/backward, weight-gradient reduction, Adam), FP16
+// matrix-core inference, and the learned evaluation form of K_nu and of the
+// Matern tiles.
+//
+// The learned form replaces the per-entry peak/window solve of Sec. IV-B with a
+// prediction of [t_lo, t_hi] and the node count N from (log10 x, nu). The node
+// sum is taken relative to t_lo (the first node), so every node lies at or
+// right of the reference and the outward recurrences of bk_math.hpp apply. Node
+// exponents can then be large and positive; the FP32 exponential is split as
+// 2^k 2^f with k integer and f in [-1/2, 1/2] formed in FP64, so FP32 rounding
+// only touches f. The node count is the predicted one, raised if needed to what
+// the strip-bound rule asks for the predicted window (a few dozen FP64 operations,
+// the same rule the plain solver uses), so the step is always admissible. An entry
+// is accepted only if (a) it lies inside the model's training box and (b) the
+// integral beyond each end of the window, bounded through the concavity of g
+// from the two end nodes, is below a tolerance; otherwise it is recomputed with
+// the plain FP64 solver and FP32-compensated node terms.
 #include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <random>
+#include <vector>
+
 #include "../../include/besselk.h"
 #include "bk_internal.hpp"
 
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
 namespace bk {
-int bk_besselk_learned(const double*, const double*, double*, int64_t, const bk_params* prm, double, double, hipStream_t)
-{
-    return prm->model ? BK_EINVAL : BK_ENOMODEL;
-}
-int bk_matern_learned(const bk_locs*, const bk_params* prm, int32_t, int32_t, void*, double, double, hipStream_t)
-{
-    return prm->model ? BK_EINVAL : BK_ENOMODEL;
-}
+
+constexpr int kH = 64;                 // hidden width
+constexpr int kOffW1 = 0;              // offsets into the flat parameter vector
+constexpr int kOffB1 = kOffW1 + kH * 2;
+constexpr int kOffW2 = kOffB1 + kH;
+constexpr int kOffB2 = kOffW2 + kH * kH;
+constexpr int kOffW3 = kOffB2 + kH;
+constexpr int kOffB3 = kOffW3 + 3 * kH;
+constexpr int kNParam = kOffB3 + 3;
+static_assert(kNParam == BK_MLP_NPARAM, "parameter count");
+
+// Acceptance tolerance of the learned form: extrapolated tail beyond an end node,
+// relative to the sum.
+constexpr float kTailTol = 1e-7f;
+constexpr int kTableSize = 1024;       // Matern: MLP tabulated over log10 x at fixed nu
+
+// Device-side constants of a model for inference.
+struct MlpDev {
+    const half4_t* a1;   // [4 mt][64 lanes]      layer-1 A operand (W1 | b1 | 0)
+    const half4_t* a2;   // [4 mt][4 ks][64]      layer-2 A operand (W2)
+    const half4_t* a3;   // [4 ks][64]            layer-3 A operand (W3, rows >= 3 zero)
+    const float* b2;     // [64]
+    const float* b3;     // [3]
+    float cx, sx, cnu, snu, st, sn;     // normalisation
+    float lx_lo, lx_hi, nu_lo, nu_hi;   // training box
+    float d_lo, d_hi, eta, n_add;       // margins
+};
+
 }  // namespace bk
 
-struct bk_model { int dummy; };
-extern "C" {
-int bk_model_create(bk_model** m) { if (!m) return BK_EINVAL; *m = new bk_model(); return BK_OK; }
-void bk_model_destroy(bk_model* m) { delete m; }
-int bk_model_load(bk_model*, const char*) { return BK_EIO; }
-int bk_model_save(const bk_model*, const char*) { return BK_EIO; }
-int bk_model_train(bk_model*, const double*, const double*, int64_t, const bk_train_cfg*, float*, hipStream_t) { return BK_EINVAL; }
-int bk_model_set_margins(bk_model*, double, double, double, double) { return BK_EINVAL; }
-int bk_model_get_params(const bk_model*, float*) { return BK_EINVAL; }
-int bk_model_set_params(bk_model*, const float*) { return BK_EINVAL; }
-int bk_model_get_norm(const bk_model*, double*) { return BK_EINVAL; }
-int bk_model_set_norm(bk_model*, const double*) { return BK_EINVAL; }
-int bk_model_get_box(const bk_model*, double*) { return BK_EINVAL; }
-int bk_model_set_box(bk_model*, const double*) { return BK_EINVAL; }
-int bk_mlp_infer(const bk_model*, const float*, float*, int64_t, hipStream_t) { return BK_EINVAL; }
-int bk_mlp_grad(const float*, const float*, const float*, const float*, int64_t, float*, float*, void*, size_t, hipStream_t) { return BK_EINVAL; }
-size_t bk_mlp_grad_scratch_bytes(int64_t) { return 0; }
-int bk_adam_step(float*, const float*, float*, float*, int64_t, int32_t, float, float, float, float, hipStream_t) { return BK_EINVAL; }
-size_t bk_workspace_bytes(int64_t n) { return n > 0 ? (size_t)n * 8 + 256 : 256; }
+struct bk_model {
+    float* params = nullptr;      // device FP32 master parameters [kNParam]
+    half4_t* pack = nullptr;      // device FP16 operand pack (a1, a2, a3)
+    float* bias = nullptr;        // device b2 (64) and b3 (3)
+    float* table = nullptr;       // device Matern window table [kTableSize][4]
+    double norm[8] = {-0.5, 3.5, 5.005, 4.995, 8.0, 32.0, 0.0, 0.0};
+    double box[4] = {-4.0, 3.0, 0.01, 10.0};
+    double margins[4] = {0.05, 0.05, 0.05, 1.0};
+    double train_L[2] = {16.0, 15.4};
+    bool trained = false;
+    int device = 0;
+};
+
+namespace bk {
+
+static int hip_ok(hipError_t e) { return e == hipSuccess ? BK_OK : BK_EHIP; }
+
+static MlpDev make_dev(const bk_model* m)
+{
+    MlpDev d;
+    d.a1 = m->pack;
+    d.a2 = m->pack + 4 * 64;
+    d.a3 = m->pack + 20 * 64;
+    d.b2 = m->bias;
+    d.b3 = m->bias + 64;
+    d.cx = (float)m->norm[0]; d.sx = (float)m->norm[1];
+    d.cnu = (float)m->norm[2]; d.snu = (float)m->norm[3];
+    d.st = (float)m->norm[4]; d.sn = (float)m->norm[5];
+    d.lx_lo = (float)m->box[0]; d.lx_hi = (float)m->box[1];
+    d.nu_lo = (float)m->box[2]; d.nu_hi = (float)m->box[3];
+    d.d_lo = (float)m->margins[0]; d.d_hi = (float)m->margins[1];
+    d.eta = (float)m->margins[2]; d.n_add = (float)m->margins[3];
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// Inference on matrix cores. Layers are computed transposed, H^T = W H_in^T, so
+// that with v_mfma_f32_16x16x16f16 the accumulator layout of one layer (lane
+// holds rows 4q..4q+3 of column r, q = lane/16, r = lane%16) is exactly the B
+// operand layout of the next (lane holds k = 4q..4q+3 of column r). A wave
+// evaluates its 64 entries as four column tiles of 16; all 64 lanes must be
+// active.
+// ---------------------------------------------------------------------------
+// ReLU as a clamp to [0, FLT_MAX] (one v_med3_f32, no NaN canonicalisation),
+// then packed conversion to FP16.
+__device__ __forceinline__ half4_t relu_h4(float4_t v)
+{
+    half4_t h;
+    h[0] = (_Float16)__builtin_amdgcn_fmed3f(v[0], 0.0f, 3.0e38f);
+    h[1] = (_Float16)__builtin_amdgcn_fmed3f(v[1], 0.0f, 3.0e38f);
+    h[2] = (_Float16)__builtin_amdgcn_fmed3f(v[2], 0.0f, 3.0e38f);
+    h[3] = (_Float16)__builtin_amdgcn_fmed3f(v[3], 0.0f, 3.0e38f);
+    return h;
+}
+
+__device__ inline void mlp_wave(const MlpDev& M, float u0, float u1, float& y0, float& y1, float& y2)
+{
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    half4_t A1[4], A3[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        A1[i] = M.a1[i * 64 + lane];
+        A3[i] = M.a3[i * 64 + lane];
+    }
+    float4_t B2[4], B3;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int it = 0; it < 4; ++it) B2[mt][it] = M.b2[16 * mt + 4 * q + it];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) B3[it] = (q == 0 && it < 3) ? M.b3[it] : 0.0f;
+    const float4_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    y0 = y1 = y2 = 0.0f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        float e0 = __shfl(u0, 16 * nt + r, 64);
+        float e1 = __shfl(u1, 16 * nt + r, 64);
+        half4_t b0;
+        b0[0] = (_Float16)(q == 0 ? e0 : 0.0f);
+        b0[1] = (_Float16)(q == 0 ? e1 : 0.0f);
+        b0[2] = (_Float16)(q == 0 ? 1.0f : 0.0f);
+        b0[3] = (_Float16)0.0f;
+        half4_t h1[4], h2[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            h1[mt] = relu_h4(__builtin_amdgcn_mfma_f32_16x16x16f16(A1[mt], b0, zero, 0, 0, 0));
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            float4_t acc = B2[mt];
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(M.a2[(mt * 4 + ks) * 64 + lane], h1[ks], acc, 0, 0, 0);
+            h2[mt] = relu_h4(acc);
+        }
+        float4_t o = B3;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) o = __builtin_amdgcn_mfma_f32_16x16x16f16(A3[ks], h2[ks], o, 0, 0, 0);
+        // outputs of entry 16 nt + r sit in lane r (q == 0), items 0..2
+        float s0 = __shfl(o[0], r, 64), s1 = __shfl(o[1], r, 64), s2 = __shfl(o[2], r, 64);
+        if (q == nt) { y0 = s0; y1 = s1; y2 = s2; }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_infer(MlpDev M, const float* __restrict__ u, float* __restrict__ y, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float u0 = 0.0f, u1 = 0.0f;
+    if (i < n) { u0 = u[2 * i]; u1 = u[2 * i + 1]; }
+    float y0, y1, y2;
+    mlp_wave(M, u0, u1, y0, y1, y2);
+    if (i < n) { y[3 * i] = y0; y[3 * i + 1] = y1; y[3 * i + 2] = y2; }
+}
+
+// ---------------------------------------------------------------------------
+// Learned node sum. Reference t_ref = t_lo (node 0), outward walk only.
+// ---------------------------------------------------------------------------
+struct LearnedOut {
+    double hs;      // h * S (trapezoid value of the scaled integral)
+    double delta;   // log prefactor Delta at t_ref
+    int reason;     // 0 accepted, else a BK_STAT_FB_* index
+};
+
+__device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double thi, int N)
+{
+    LearnedOut o;
+    o.reason = 0;
+    Plan p;
+    p.t0 = tlo;
+    p.tref = tlo;
+    p.mc = 0;
+    p.N = N;
+    p.h = (thi - tlo) / (double)N;
+    double ch, sh;
+    cosh_sinh(tlo, ch, sh);
+    double em = expm1(0.5 * tlo);
+    double sh2 = em * (em + 2.0) / (2.0 * (em + 1.0));
+    o.delta = nu * tlo - kLn2 - 2.0 * x * sh2 * sh2;
+    const double A = 0.5 * x * ch, B = 0.5 * x * sh;
+    Walk w = walk_begin(nu, p);
+    float s = 0.0f, c = 0.0f;
+    float e0 = 0.0f, e1 = 0.0f, eprev = 0.0f, elast = 0.0f;
+    for (int m = 0; m <= N; ++m) {
+        double d = walk_exponent(w, m, nu, A, B) * kLog2e;
+        double kf = rint(d);
+        float f = (float)(d - kf);
+        float term = __builtin_amdgcn_exp2f(f) * (float)(1.0 + w.P);
+        term = ldexpf(term, (int)fmax(fmin(kf, 300.0), -300.0));
+        float yk = term - c;
+        float tk = s + yk;
+        c = (tk - s) - yk;
+        s = tk;
+        if (m == 0) e0 = term;
+        if (m == 1) e1 = term;
+        eprev = elast;
+        elast = term;
+        w.k += 1.0;
+        w.Bw *= w.q;
+        w.Bb *= w.qi;
+        w.P *= w.rho;
+        w.V = fma(w.V, w.q, w.qm1);
+    }
+    const float ends = e0 + elast;
+    const float S = (s - c) - 0.5f * ends;
+    o.hs = p.h * (double)S;
+    if (!(S > 0.0f) || !isfinite(S)) { o.reason = BK_STAT_FB_NONFINITE; return o; }
+    // Tails beyond the ends. Right of the peak g is concave, so past the last node
+    // the integrand lies below the exponential with slope g'(t_N), and the tail
+    // integral is at most f(t_N) / |g'(t_N)|; the secant slope of the last two
+    // nodes is no steeper than g'(t_N), so using it keeps the bound. In units of
+    // the sum S (integral / h): e_N / |log(e_N / e_{N-1})|. The same bound on the
+    // left (g concave where nu t is not small) is e_0 / log(e_1 / e_0).
+    const float lr = __builtin_amdgcn_logf(elast / eprev) * 0.69314718f;
+    if (!(elast < eprev) || elast > -lr * kTailTol * S) { o.reason = BK_STAT_FB_TAIL; return o; }
+    if (tlo > 0.0) {
+        const float ll = __builtin_amdgcn_logf(e1 / e0) * 0.69314718f;
+        if (!(e0 < e1) || e0 > ll * kTailTol * S) { o.reason = BK_STAT_FB_TAIL; return o; }
+    }
+    return o;
+}
+
+// Window from a prediction (normalised outputs y), with the model's margins; the
+// node count is the prediction or the strip-bound rule's count for this window,
+// whichever is larger (raised says which).
+__device__ __forceinline__ void decode_window(const MlpDev& M, float y0, float y1, float y2, double nu, double x,
+                                              double Lq, const RuleTable& R, double& tlo, double& thi, int& N,
+                                              bool& raised)
+{
+    tlo = fmax(0.0, (double)(y0 * M.st - M.d_lo));
+    thi = (double)(y1 * M.st + M.d_hi);
+    float nf = ceilf(y2 * M.sn * (1.0f + M.eta) + M.n_add);
+    if (!(nf >= (float)kNodeMin)) nf = (float)kNodeMin;
+    if (nf > (float)kNodeMax) nf = (float)kNodeMax;
+    const int Nr = node_count(thi - tlo, node_step(nu, x, Lq, R));
+    raised = Nr > (int)nf;
+    N = raised ? Nr : (int)nf;
+}
+
+__device__ __forceinline__ bool in_box(const MlpDev& M, float lx, float v)
+{
+    return lx >= M.lx_lo && lx <= M.lx_hi && v >= M.nu_lo && v <= M.nu_hi;
+}
+
+__device__ __forceinline__ double assemble_k(double z, double delta, double hs, int result)
+{
+    if (result == BK_RESULT_SCALED) return exp(delta) * hs;
+    if (result == BK_RESULT_LOG) return (delta - z) + log(hs);
+    if (z < 708.0) return exp(-z) * exp(delta) * hs;
+    return exp((delta - z) + log(hs));
+}
+
+__device__ __forceinline__ bool special_k(double v, double z, int result, double& r)
+{
+    if (isnan(v) || isnan(z) || z < 0.0) { r = __builtin_nan(""); return true; }
+    if (z == 0.0 || isinf(v)) { r = __builtin_inf(); return true; }
+    if (isinf(z)) { r = (result == BK_RESULT_LOG) ? -__builtin_inf() : 0.0; return true; }
+    return false;
+}
+
+__device__ void block_stats(unsigned long long* stats, const unsigned long long* v, int nv)
+{
+    __shared__ unsigned long long red[4][8];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = 0; k < nv; ++k) {
+        unsigned long long a = v[k];
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+        if (lane == 0) red[wid][k] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        unsigned long long t = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        if (t) atomicAdd(stats + threadIdx.x, t);
+    }
+}
+
+// Workspace: [0] fallback count (uint32), queue of uint32 indices from byte 256.
+__global__ void k_zero_u32(unsigned int* p) { if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 0u; }
+
+__global__ __launch_bounds__(256) void k_besselk_learned(MlpDev M, const double* __restrict__ nu,
+                                                         const double* __restrict__ x, double* __restrict__ out,
+                                                         int64_t n, int result, double Lq, RuleTable R,
+                                                         unsigned int* __restrict__ qcount,
+                                                         unsigned int* __restrict__ queue,
+                                                         unsigned long long* __restrict__ stats)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool live = i < n;
+    double v = 0.0, z = 1.0;
+    if (live) { v = fabs(nu[i]); z = x[i]; }
+    const float lx = (float)log10(z > 0.0 ? z : 1.0);
+    const float u0 = (lx - M.cx) / M.sx, u1 = ((float)v - M.cnu) / M.snu;
+    float y0, y1, y2;
+    mlp_wave(M, u0, u1, y0, y1, y2);          // whole wave participates
+    unsigned long long cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (live) {
+        double r;
+        if (!special_k(v, z, result, r)) {
+            int reason = 0;
+            if (!in_box(M, lx, (float)v)) {
+                reason = BK_STAT_FB_RANGE;
+            } else {
+                double tlo, thi;
+                int N;
+                bool raised;
+                decode_window(M, y0, y1, y2, v, z, Lq, R, tlo, thi, N, raised);
+                cnt[BK_STAT_NODE_RAISED] = raised ? 1 : 0;
+                if (!(thi > tlo) || !isfinite(thi)) {
+                    reason = BK_STAT_FB_NONFINITE;
+                } else {
+                    LearnedOut lo = learned_sum(v, z, tlo, thi, N);
+                    reason = lo.reason;
+                    cnt[BK_STAT_NODES] = (unsigned long long)(N + 1);
+                    cnt[BK_STAT_ENTRIES] = 1;
+                    if (reason == 0) r = assemble_k(z, lo.delta, lo.hs, result);
+                }
+            }
+            if (reason != 0) {
+                cnt[reason] = 1;
+                unsigned int slot = atomicAdd(qcount, 1u);
+                queue[slot] = (unsigned int)i;
+            } else {
+                out[i] = r;
+            }
+        } else {
+            out[i] = r;
+        }
+    }
+    if (stats) block_stats(stats, cnt, 6);
+}
+
+// Fallback: plain FP64 solve with FP32-compensated node terms, over the queue.
+__global__ __launch_bounds__(256) void k_besselk_fallback(const double* __restrict__ nu, const double* __restrict__ x,
+                                                          double* __restrict__ out, int result,
+                                                          const unsigned int* __restrict__ qcount,
+                                                          const unsigned int* __restrict__ queue, double L, double Lq,
+                                                          RuleTable R, unsigned long long* __restrict__ stats)
+{
+    const unsigned int cnt = *qcount;
+    unsigned long long nodes = 0, ents = 0;
+    for (unsigned int j = blockIdx.x * 256 + threadIdx.x; j < cnt; j += gridDim.x * 256) {
+        const unsigned int i = queue[j];
+        const double v = fabs(nu[i]), z = x[i];
+        Solved s = plain_solve(v, z, L, Lq, R);
+        const double S = sum_mixed(v, s.p, s.A, s.B);
+        out[i] = assemble_k(z, s.delta, s.p.h * S, result);
+        nodes += (unsigned long long)(s.p.N + 1);
+        ents += 1;
+    }
+    if (stats) {
+        unsigned long long c[2] = {ents, nodes};
+        block_stats(stats, c, 2);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Matern, learned form: the MLP is tabulated once per launch over log10 x on
+// kTableSize points of the training box at the launch's nu; an entry takes the
+// conservative union of the two bracketing predictions. Entries that fail the
+// acceptance checks fall back inside the kernel.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_matern_table(MlpDev M, float nu, float* __restrict__ table)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const float lx = M.lx_lo + (M.lx_hi - M.lx_lo) * (float)min(i, kTableSize - 1) / (float)(kTableSize - 1);
+    float y0, y1, y2;
+    mlp_wave(M, (lx - M.cx) / M.sx, (nu - M.cnu) / M.snu, y0, y1, y2);
+    if (i < kTableSize) {
+        table[4 * i] = y0;
+        table[4 * i + 1] = y1;
+        table[4 * i + 2] = y2;
+        table[4 * i + 3] = 0.0f;
+    }
+}
+
+struct TileGeomL {
+    int64_t n;
+    int32_t ts, T, lower;
+    int32_t rb_per_tile, cb_per_tile;
+};
+
+__host__ __device__ inline int64_t tile_offset_l(int64_t n, int64_t ts, int64_t T, int lower, int64_t I, int64_t J)
+{
+    int64_t nJ = (J == T - 1) ? n - J * ts : ts;
+    if (lower) return ts * (J * n - ts * (J * (J - 1) / 2)) + nJ * (I - J) * ts;
+    return J * ts * n + nJ * I * ts;
+}
+
+__device__ inline void tile_of_l(int64_t p, const TileGeomL& g, int64_t& I, int64_t& J)
+{
+    int64_t T = g.T;
+    if (!g.lower) { J = p / T; I = p - J * T; return; }
+    double b = 2.0 * (double)T + 1.0;
+    int64_t j = (int64_t)floor((b - sqrt(fmax(b * b - 8.0 * (double)p, 0.0))) * 0.5);
+    if (j < 0) j = 0;
+    if (j > T - 1) j = T - 1;
+    while (j > 0 && j * T - j * (j - 1) / 2 > p) --j;
+    while (j + 1 <= T - 1 && (j + 1) * T - (j + 1) * j / 2 <= p) ++j;
+    J = j;
+    I = J + (p - (J * T - J * (J - 1) / 2));
+}
+
+template <typename OutT>
+__global__ __launch_bounds__(256) void k_matern_learned(MlpDev M, const float* __restrict__ table,
+                                                        const double* __restrict__ lx_, const double* __restrict__ ly_,
+                                                        TileGeomL g, int64_t tile_base, double sigma2,
+                                                        double inv_beta, double nu, double pref, double L, double Lq,
+                                                        RuleTable R, OutT* __restrict__ out)
+{
+    constexpr int kColsPerWave = 8, kColsPerGroup = 32;
+    const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
+    const int64_t p = tile_base + (int64_t)blockIdx.x / wg_per_tile;
+    const int64_t local = (int64_t)blockIdx.x % wg_per_tile;
+    const int rb = (int)(local % g.rb_per_tile), cb = (int)(local / g.rb_per_tile);
+    int64_t I, J;
+    tile_of_l(p, g, I, J);
+    const int64_t mI = min((int64_t)g.ts, g.n - I * g.ts);
+    const int64_t nJ = min((int64_t)g.ts, g.n - J * g.ts);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t il = (int64_t)rb * 64 + lane;
+    const int64_t jl0 = (int64_t)cb * kColsPerGroup + (int64_t)wave * kColsPerWave;
+    if (il >= mI || jl0 >= nJ) return;
+    const int64_t base = tile_offset_l(g.n, g.ts, g.T, g.lower, I, J);
+    const double xi = lx_[I * g.ts + il], yi = ly_[I * g.ts + il];
+    const int cend = (int)min((int64_t)kColsPerWave, nJ - jl0);
+    const float tscale = (float)(kTableSize - 1) / (M.lx_hi - M.lx_lo);
+    const bool nu_ok = (float)nu >= M.nu_lo && (float)nu <= M.nu_hi;
+    for (int c = 0; c < cend; ++c) {
+        const int64_t jl = jl0 + c;
+        const double dx = lx_[J * g.ts + jl] - xi, dy = ly_[J * g.ts + jl] - yi;
+        const double rr = sqrt(dx * dx + dy * dy);
+        double val;
+        if (rr == 0.0) {
+            val = sigma2;
+        } else {
+            const double z = rr * inv_beta;
+            const float lz = (float)log10(z);
+            bool ok = nu_ok && lz >= M.lx_lo && lz <= M.lx_hi;
+            double hs = 0.0, delta = 0.0;
+            if (ok) {
+                float fpos = (lz - M.lx_lo) * tscale;
+                int k0 = min(max((int)fpos, 0), kTableSize - 2);
+                const float* t0 = table + 4 * k0;
+                const float* t1 = t0 + 4;
+                double tlo, thi;
+                int N;
+                bool raised;
+                decode_window(M, fminf(t0[0], t1[0]), fmaxf(t0[1], t1[1]), fmaxf(t0[2], t1[2]), nu, z, Lq, R, tlo,
+                              thi, N, raised);
+                if (thi > tlo && isfinite(thi)) {
+                    LearnedOut lo = learned_sum(nu, z, tlo, thi, N);
+                    ok = lo.reason == 0;
+                    hs = lo.hs;
+                    delta = lo.delta;
+                } else {
+                    ok = false;
+                }
+            }
+            if (!ok) {
+                Solved s = plain_solve(nu, z, L, Lq, R);
+                hs = s.p.h * sum_mixed(nu, s.p, s.A, s.B);
+                delta = s.delta;
+            }
+            val = sigma2 * exp(pref + nu * log(z) + (delta - z)) * hs;
+        }
+        out[base + il + jl * mI] = (OutT)val;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Training kernels (FP32, one lane per sample)
+// ---------------------------------------------------------------------------
+// Targets and inputs from the plain-solver window: u = normalised (log10 x, nu),
+// target = (t_lo / st, t_hi / st, N / sn).
+__global__ __launch_bounds__(256) void k_make_targets(const double* __restrict__ nu, const double* __restrict__ x,
+                                                      const double* __restrict__ tlo, const double* __restrict__ thi,
+                                                      const int32_t* __restrict__ nodes, int64_t n, float cx, float sx,
+                                                      float cnu, float snu, float st, float sn,
+                                                      float* __restrict__ u, float* __restrict__ tgt)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    u[2 * i] = ((float)log10(x[i]) - cx) / sx;
+    u[2 * i + 1] = ((float)fabs(nu[i]) - cnu) / snu;
+    tgt[3 * i] = (float)tlo[i] / st;
+    tgt[3 * i + 1] = (float)thi[i] / st;
+    tgt[3 * i + 2] = (float)nodes[i] / sn;
+}
+
+// Forward and backward of one sample per lane. Stores, feature-major ([feature][B]),
+// the tensors the weight gradients need: u, h1, h2, gh1, gh2, gy; accumulates the loss.
+// Sample b of the batch is row perm(b) = (pa * (start + b) + pb) mod n of the data.
+__global__ __launch_bounds__(256) void k_fwd_bwd(const float* __restrict__ P, const float* __restrict__ U,
+                                                 const float* __restrict__ T, const float* __restrict__ tau, int64_t B,
+                                                 int64_t n, uint64_t pa, uint64_t pb, int64_t start,
+                                                 float* __restrict__ scr, float* __restrict__ loss)
+{
+    __shared__ float sP[kNParam];
+    __shared__ float red[4];
+    for (int k = threadIdx.x; k < kNParam; k += 256) sP[k] = P[k];
+    __syncthreads();
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float l = 0.0f;
+    if (b < B) {
+        uint64_t row = (uint64_t)(start + b);
+        if (n > 0) row = (pa * row + pb) % (uint64_t)n;      // pa, row < n < 2^31: no overflow
+        float* su = scr;                 // [2][B]
+        float* sh1 = su + 2 * B;         // [64][B]
+        float* sh2 = sh1 + 64 * B;       // [64][B]
+        float* sg1 = sh2 + 64 * B;       // [64][B]
+        float* sg2 = sg1 + 64 * B;       // [64][B]
+        float* sgy = sg2 + 64 * B;       // [3][B]
+        const float u0 = U[2 * row], u1 = U[2 * row + 1];
+        su[b] = u0;
+        su[B + b] = u1;
+        float h1[kH], z2[kH];
+#pragma unroll
+        for (int j = 0; j < kH; ++j) {
+            float z = fmaf(sP[kOffW1 + 2 * j], u0, fmaf(sP[kOffW1 + 2 * j + 1], u1, sP[kOffB1 + j]));
+            h1[j] = fmaxf(z, 0.0f);
+            sh1[j * B + b] = h1[j];
+        }
+        float y[3] = {sP[kOffB3], sP[kOffB3 + 1], sP[kOffB3 + 2]};
+        for (int i2 = 0; i2 < kH; ++i2) {
+            float z = sP[kOffB2 + i2];
+#pragma unroll
+            for (int j = 0; j < kH; ++j) z = fmaf(sP[kOffW2 + i2 * kH + j], h1[j], z);
+            z2[i2] = z;
+            const float h = fmaxf(z, 0.0f);
+            sh2[i2 * B + b] = h;
+#pragma unroll
+            for (int o = 0; o < 3; ++o) y[o] = fmaf(sP[kOffW3 + o * kH + i2], h, y[o]);
+        }
+        float gy[3];
+        const float invB = 1.0f / (float)B;
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            const float e = T[3 * row + o] - y[o];
+            const float w = e < 0.0f ? 1.0f - tau[o] : tau[o];
+            l += w * e * e;
+            gy[o] = -2.0f * w * e * invB;
+            sgy[o * B + b] = gy[o];
+        }
+        float g2[kH];
+#pragma unroll
+        for (int i2 = 0; i2 < kH; ++i2) {
+            float g = sP[kOffW3 + i2] * gy[0] + sP[kOffW3 + kH + i2] * gy[1] + sP[kOffW3 + 2 * kH + i2] * gy[2];
+            g2[i2] = z2[i2] > 0.0f ? g : 0.0f;
+            sg2[i2 * B + b] = g2[i2];
+        }
+        for (int j = 0; j < kH; ++j) {
+            float g = 0.0f;
+#pragma unroll
+            for (int i2 = 0; i2 < kH; ++i2) g = fmaf(sP[kOffW2 + i2 * kH + j], g2[i2], g);
+            sg1[j * B + b] = h1[j] > 0.0f ? g : 0.0f;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss, (red[0] + red[1] + red[2] + red[3]) / (float)B);
+}
+
+// Weight gradients: one workgroup per parameter group row, reduction over the batch.
+// Parameter k is sum_b A[b] * Bv[b] for two feature rows (or sum_b A[b] for biases).
+__global__ __launch_bounds__(256) void k_wgrad(const float* __restrict__ scr, int64_t B, float* __restrict__ grad)
+{
+    __shared__ float red[4];
+    const int k = blockIdx.x;                 // parameter index
+    const float* su = scr;
+    const float* sh1 = su + 2 * B;
+    const float* sh2 = sh1 + 64 * B;
+    const float* sg1 = sh2 + 64 * B;
+    const float* sg2 = sg1 + 64 * B;
+    const float* sgy = sg2 + 64 * B;
+    const float* a;
+    const float* bv = nullptr;
+    if (k < kOffB1) { int j = k / 2, c = k % 2; a = sg1 + (int64_t)j * B; bv = su + (int64_t)c * B; }
+    else if (k < kOffW2) { a = sg1 + (int64_t)(k - kOffB1) * B; }
+    else if (k < kOffB2) { int i2 = (k - kOffW2) / kH, j = (k - kOffW2) % kH; a = sg2 + (int64_t)i2 * B; bv = sh1 + (int64_t)j * B; }
+    else if (k < kOffW3) { a = sg2 + (int64_t)(k - kOffB2) * B; }
+    else if (k < kOffB3) { int o = (k - kOffW3) / kH, i2 = (k - kOffW3) % kH; a = sgy + (int64_t)o * B; bv = sh2 + (int64_t)i2 * B; }
+    else { a = sgy + (int64_t)(k - kOffB3) * B; }
+    float s = 0.0f;
+    if (bv) { for (int64_t b = threadIdx.x; b < B; b += 256) s = fmaf(a[b], bv[b], s); }
+    else { for (int64_t b = threadIdx.x; b < B; b += 256) s += a[b]; }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) grad[k] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_zero_f32(float* p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                                              float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Residuals of the inference-path predictions against the targets (for margins):
+// r[0] = pred t_lo - t_lo, r[1] = t_hi - pred t_hi, r[2] = N / pred N - 1 (all in absolute units).
+__global__ __launch_bounds__(256) void k_residuals(MlpDev M, const float* __restrict__ U, const float* __restrict__ T,
+                                                   int64_t n, float* __restrict__ res)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float u0 = 0.0f, u1 = 0.0f;
+    if (i < n) { u0 = U[2 * i]; u1 = U[2 * i + 1]; }
+    float y0, y1, y2;
+    mlp_wave(M, u0, u1, y0, y1, y2);
+    if (i < n) {
+        res[3 * i] = (y0 - T[3 * i]) * M.st;
+        res[3 * i + 1] = (T[3 * i + 1] - y1) * M.st;
+        res[3 * i + 2] = T[3 * i + 2] / fmaxf(y2, 1e-3f) - 1.0f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+// FP16 operand pack from the FP32 master parameters (host arrays).
+static void pack_weights(const float* P, std::vector<_Float16>& pack, std::vector<float>& bias)
+{
+    pack.assign((size_t)24 * 64 * 4, (_Float16)0.0f);
+    for (int mt = 0; mt < 4; ++mt)
+        for (int lane = 0; lane < 64; ++lane) {
+            const int r = lane & 15, q = lane >> 4, j = 16 * mt + r;
+            _Float16* a1 = &pack[((size_t)mt * 64 + lane) * 4];
+            if (q == 0) {
+                a1[0] = (_Float16)P[kOffW1 + 2 * j];
+                a1[1] = (_Float16)P[kOffW1 + 2 * j + 1];
+                a1[2] = (_Float16)P[kOffB1 + j];
+            }
+            for (int ks = 0; ks < 4; ++ks) {
+                _Float16* a2 = &pack[((size_t)(4 + mt * 4 + ks) * 64 + lane) * 4];
+                for (int it = 0; it < 4; ++it) a2[it] = (_Float16)P[kOffW2 + j * kH + 16 * ks + 4 * q + it];
+            }
+        }
+    for (int ks = 0; ks < 4; ++ks)
+        for (int lane = 0; lane < 64; ++lane) {
+            const int r = lane & 15, q = lane >> 4;
+            _Float16* a3 = &pack[((size_t)(20 + ks) * 64 + lane) * 4];
+            if (r < 3)
+                for (int it = 0; it < 4; ++it) a3[it] = (_Float16)P[kOffW3 + r * kH + 16 * ks + 4 * q + it];
+        }
+    bias.assign(68, 0.0f);
+    for (int j = 0; j < kH; ++j) bias[j] = P[kOffB2 + j];
+    for (int o = 0; o < 3; ++o) bias[64 + o] = P[kOffB3 + o];
+}
+
+static int model_alloc(bk_model* m)
+{
+    if (m->params) return BK_OK;
+    if (hipGetDevice(&m->device) != hipSuccess) return BK_EHIP;
+    if (hipMalloc((void**)&m->params, sizeof(float) * kNParam) != hipSuccess) return BK_ENOMEM;
+    if (hipMalloc((void**)&m->pack, sizeof(_Float16) * 24 * 64 * 4) != hipSuccess) return BK_ENOMEM;
+    if (hipMalloc((void**)&m->bias, sizeof(float) * 68) != hipSuccess) return BK_ENOMEM;
+    if (hipMalloc((void**)&m->table, sizeof(float) * 4 * kTableSize) != hipSuccess) return BK_ENOMEM;
+    return BK_OK;
+}
+
+// Upload host parameters: master copy and inference pack (synchronous).
+static int model_upload(bk_model* m, const float* hostP)
+{
+    int st = model_alloc(m);
+    if (st) return st;
+    std::vector<_Float16> pack;
+    std::vector<float> bias;
+    pack_weights(hostP, pack, bias);
+    if (hipMemcpy(m->params, hostP, sizeof(float) * kNParam, hipMemcpyHostToDevice) != hipSuccess) return BK_EHIP;
+    if (hipMemcpy(m->pack, pack.data(), sizeof(_Float16) * pack.size(), hipMemcpyHostToDevice) != hipSuccess) return BK_EHIP;
+    if (hipMemcpy(m->bias, bias.data(), sizeof(float) * bias.size(), hipMemcpyHostToDevice) != hipSuccess) return BK_EHIP;
+    return BK_OK;
+}
+
+static size_t grad_scratch_floats(int64_t B) { return (size_t)B * (2 + 4 * 64 + 3); }
+
+static int launch_grad(const float* params, const float* u, const float* tgt, const float* tau, int64_t B,
+                       int64_t n, uint64_t pa, uint64_t pb, int64_t start, float* grad, float* loss, float* scr,
+                       hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((B + 255) / 256);
+    hipLaunchKernelGGL(k_fwd_bwd, dim3(blocks), dim3(256), 0, s, params, u, tgt, tau, B, n, pa, pb, start, scr, loss);
+    hipLaunchKernelGGL(k_wgrad, dim3(kNParam), dim3(256), 0, s, scr, B, grad);
+    return hipGetLastError() == hipSuccess ? BK_OK : BK_EHIP;
+}
+
+}  // namespace bk
+
+using namespace bk;
+
+// ---------------------------------------------------------------------------
+// Learned evaluation entry points (called from bk_kernels.hip)
+// ---------------------------------------------------------------------------
+namespace bk {
+
+int bk_besselk_learned(const double* nu, const double* x, double* out, int64_t n, const bk_params* prm, double L,
+                       double Lq, hipStream_t stream)
+{
+    const bk_model* m = prm->model;
+    if (!m || !m->params || !m->trained) return BK_ENOMODEL;
+    if (!prm->workspace || prm->workspace_bytes < bk_workspace_bytes(n)) return BK_ENOMEM;
+    if (n >= (int64_t)0xffffffffLL) return BK_EINVAL;
+    unsigned int* qcount = (unsigned int*)prm->workspace;
+    unsigned int* queue = (unsigned int*)((char*)prm->workspace + 256);
+    const MlpDev M = make_dev(m);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, qcount);
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_besselk_learned, dim3(blocks), dim3(256), 0, stream, M, nu, x, out, n, prm->result, Lq,
+                       rule_table(), qcount, queue, prm->stats);
+    hipLaunchKernelGGL(k_besselk_fallback, dim3(1024), dim3(256), 0, stream, nu, x, out, prm->result, qcount, queue, L,
+                       Lq, rule_table(), prm->stats);
+    return hipGetLastError() == hipSuccess ? BK_OK : BK_EHIP;
+}
+
+int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_size, int32_t lower_only, void* out,
+                      double L, double Lq, hipStream_t stream)
+{
+    const bk_model* m = prm->model;
+    if (!m || !m->params || !m->trained) return BK_ENOMODEL;
+    const MlpDev M = make_dev(m);
+    hipLaunchKernelGGL(k_matern_table, dim3((kTableSize + 255) / 256), dim3(256), 0, stream, M, (float)prm->nu,
+                       m->table);
+    TileGeomL g;
+    g.n = locs->n;
+    g.ts = tile_size;
+    g.T = (int32_t)((locs->n + tile_size - 1) / tile_size);
+    g.lower = lower_only ? 1 : 0;
+    g.rb_per_tile = (tile_size + 63) / 64;
+    g.cb_per_tile = (tile_size + 31) / 32;
+    const int64_t T = g.T;
+    const int64_t ntiles = g.lower ? T * (T + 1) / 2 : T * T;
+    const double nu = prm->nu;
+    const double pref = (1.0 - nu) * kLn2 - lgamma(nu);
+    const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
+    const int64_t max_wg = 1LL << 23;
+    const int64_t tiles_per_launch = max_wg / wg_per_tile > 0 ? max_wg / wg_per_tile : 1;
+    for (int64_t t0 = 0; t0 < ntiles; t0 += tiles_per_launch) {
+        const int64_t nt = ntiles - t0 < tiles_per_launch ? ntiles - t0 : tiles_per_launch;
+        if (prm->out_dtype == BK_OUT_F32)
+            hipLaunchKernelGGL(k_matern_learned<float>, dim3((unsigned)(nt * wg_per_tile)), dim3(256), 0, stream, M,
+                               m->table, locs->x, locs->y, g, t0, prm->sigma2, 1.0 / prm->beta, nu, pref, L, Lq,
+                               rule_table(), (float*)out);
+        else
+            hipLaunchKernelGGL(k_matern_learned<double>, dim3((unsigned)(nt * wg_per_tile)), dim3(256), 0, stream, M,
+                               m->table, locs->x, locs->y, g, t0, prm->sigma2, 1.0 / prm->beta, nu, pref, L, Lq,
+                               rule_table(), (double*)out);
+        if (hipGetLastError() != hipSuccess) return BK_EHIP;
+    }
+    return BK_OK;
+}
+
+}  // namespace bk
+
+// ---------------------------------------------------------------------------
+// C ABI: model, training and MLP primitives
+// ---------------------------------------------------------------------------
+extern "C" size_t bk_workspace_bytes(int64_t n)
+{
+    return 256 + (size_t)(n > 0 ? n : 0) * sizeof(unsigned int);
+}
+
+extern "C" int bk_model_create(bk_model** m)
+{
+    if (!m) return BK_EINVAL;
+    *m = new (std::nothrow) bk_model();
+    return *m ? BK_OK : BK_ENOMEM;
+}
+
+extern "C" void bk_model_destroy(bk_model* m)
+{
+    if (!m) return;
+    if (m->params) (void)hipFree(m->params);
+    if (m->pack) (void)hipFree(m->pack);
+    if (m->bias) (void)hipFree(m->bias);
+    if (m->table) (void)hipFree(m->table);
+    delete m;
+}
+
+static const char kMagic[8] = {'B', 'K', 'M', 'L', 'P', '0', '0', '1'};
+
+extern "C" int bk_model_save(const bk_model* m, const char* path)
+{
+    if (!m || !path || !m->params) return BK_EINVAL;
+    std::vector<float> P(kNParam);
+    if (hipMemcpy(P.data(), m->params, sizeof(float) * kNParam, hipMemcpyDeviceToHost) != hipSuccess) return BK_EHIP;
+    FILE* f = fopen(path, "wb");
+    if (!f) return BK_EIO;
+    double hdr[20] = {0};
+    for (int i = 0; i < 8; ++i) hdr[i] = m->norm[i];
+    for (int i = 0; i < 4; ++i) hdr[8 + i] = m->box[i];
+    for (int i = 0; i < 4; ++i) hdr[12 + i] = m->margins[i];
+    hdr[16] = m->train_L[0];
+    hdr[17] = m->train_L[1];
+    hdr[18] = (double)kNParam;
+    hdr[19] = m->trained ? 1.0 : 0.0;
+    bool ok = fwrite(kMagic, 1, 8, f) == 8 && fwrite(hdr, sizeof(double), 20, f) == 20 &&
+              fwrite(P.data(), sizeof(float), kNParam, f) == (size_t)kNParam;
+    ok = (fclose(f) == 0) && ok;
+    return ok ? BK_OK : BK_EIO;
+}
+
+extern "C" int bk_model_load(bk_model* m, const char* path)
+{
+    if (!m || !path) return BK_EINVAL;
+    FILE* f = fopen(path, "rb");
+    if (!f) return BK_EIO;
+    char mg[8];
+    double hdr[20];
+    std::vector<float> P(kNParam);
+    bool ok = fread(mg, 1, 8, f) == 8 && memcmp(mg, kMagic, 8) == 0 && fread(hdr, sizeof(double), 20, f) == 20 &&
+              hdr[18] == (double)kNParam && fread(P.data(), sizeof(float), kNParam, f) == (size_t)kNParam;
+    fclose(f);
+    if (!ok) return BK_EIO;
+    for (int i = 0; i < kNParam; ++i)
+        if (!std::isfinite(P[i])) return BK_EIO;
+    for (int i = 0; i < 8; ++i) m->norm[i] = hdr[i];
+    for (int i = 0; i < 4; ++i) m->box[i] = hdr[8 + i];
+    for (int i = 0; i < 4; ++i) m->margins[i] = hdr[12 + i];
+    m->train_L[0] = hdr[16];
+    m->train_L[1] = hdr[17];
+    int st = model_upload(m, P.data());
+    if (st) return st;
+    m->trained = hdr[19] != 0.0;
+    return BK_OK;
+}
+
+extern "C" int bk_model_set_margins(bk_model* m, double d_lo, double d_hi, double eta, double n_add)
+{
+    if (!m || !(d_lo >= 0) || !(d_hi >= 0) || !(eta >= 0) || !(n_add >= 0)) return BK_EINVAL;
+    m->margins[0] = d_lo;
+    m->margins[1] = d_hi;
+    m->margins[2] = eta;
+    m->margins[3] = n_add;
+    return BK_OK;
+}
+
+extern "C" int bk_model_get_params(const bk_model* m, float* host)
+{
+    if (!m || !host || !m->params) return BK_EINVAL;
+    return hip_ok(hipMemcpy(host, m->params, sizeof(float) * kNParam, hipMemcpyDeviceToHost));
+}
+
+extern "C" int bk_model_set_params(bk_model* m, const float* host)
+{
+    if (!m || !host) return BK_EINVAL;
+    for (int i = 0; i < kNParam; ++i)
+        if (!std::isfinite(host[i])) return BK_EINVAL;
+    int st = model_upload(m, host);
+    if (st == BK_OK) m->trained = true;
+    return st;
+}
+
+extern "C" int bk_model_get_norm(const bk_model* m, double* n8)
+{
+    if (!m || !n8) return BK_EINVAL;
+    memcpy(n8, m->norm, sizeof(m->norm));
+    return BK_OK;
+}
+
+extern "C" int bk_model_set_norm(bk_model* m, const double* n8)
+{
+    if (!m || !n8 || !(n8[1] > 0) || !(n8[3] > 0) || !(n8[4] > 0) || !(n8[5] > 0)) return BK_EINVAL;
+    memcpy(m->norm, n8, sizeof(m->norm));
+    return BK_OK;
+}
+
+extern "C" int bk_model_get_box(const bk_model* m, double* b4)
+{
+    if (!m || !b4) return BK_EINVAL;
+    memcpy(b4, m->box, sizeof(m->box));
+    return BK_OK;
+}
+
+extern "C" int bk_model_set_box(bk_model* m, const double* b4)
+{
+    if (!m || !b4 || !(b4[1] > b4[0]) || !(b4[3] > b4[2])) return BK_EINVAL;
+    memcpy(m->box, b4, sizeof(m->box));
+    return BK_OK;
+}
+
+extern "C" int bk_mlp_infer(const bk_model* m, const float* u, float* y, int64_t n, hipStream_t s)
+{
+    if (!m || n < 0) return BK_EINVAL;
+    if (n == 0) return BK_OK;
+    if (!u || !y) return BK_EINVAL;
+    if (!m->params) return BK_ENOMODEL;
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, make_dev(m), u, y, n);
+    return hipGetLastError() == hipSuccess ? BK_OK : BK_EHIP;
+}
+
+extern "C" size_t bk_mlp_grad_scratch_bytes(int64_t B)
+{
+    return B > 0 ? sizeof(float) * grad_scratch_floats(B) : 0;
+}
+
+extern "C" int bk_mlp_grad(const float* params, const float* u, const float* tgt, const float* tau, int64_t B,
+                           float* grad, float* loss, void* scratch, size_t scratch_bytes, hipStream_t s)
+{
+    if (!params || !u || !tgt || !tau || !grad || !loss || !scratch || B <= 0 || B > (1 << 20)) return BK_EINVAL;
+    if (scratch_bytes < bk_mlp_grad_scratch_bytes(B)) return BK_ENOMEM;
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, s, loss, (int64_t)1);
+    return launch_grad(params, u, tgt, tau, B, 0, 1, 0, 0, grad, loss, (float*)scratch, s);
+}
+
+extern "C" int bk_adam_step(float* p, const float* g, float* m, float* v, int64_t n, int32_t step, float lr,
+                            float beta1, float beta2, float eps, hipStream_t s)
+{
+    if (!p || !g || !m || !v || n < 0 || step < 1 || !(lr >= 0) || !(beta1 >= 0 && beta1 < 1) ||
+        !(beta2 >= 0 && beta2 < 1) || !(eps >= 0))
+        return BK_EINVAL;
+    if (n == 0) return BK_OK;
+    const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n, lr, beta1, beta2,
+                       eps, c1, c2);
+    return hipGetLastError() == hipSuccess ? BK_OK : BK_EHIP;
+}
+
+static uint64_t gcd_u64(uint64_t a, uint64_t b)
+{
+    while (b) { uint64_t t = a % b; a = b; b = t; }
+    return a;
+}
+
+extern "C" int bk_model_train(bk_model* m, const double* nu, const double* x, int64_t n, const bk_train_cfg* cfg,
+                              float* final_loss, hipStream_t s)
+{
+    if (!m || !nu || !x || !cfg || n < 1024 || cfg->epochs < 1 || cfg->batch < 1 || cfg->batch > 65536 ||
+        n >= ((int64_t)1 << 31) || !(cfg->lr > 0))
+        return BK_EINVAL;
+    int st = model_alloc(m);
+    if (st) return st;
+    double L, Lq;
+    resolve_thresholds(BK_MIXED_F32C, cfg->L_window, cfg->L_quad, &L, &Lq);
+    m->train_L[0] = L;
+    m->train_L[1] = Lq;
+    const int64_t B = cfg->batch;
+    // device buffers
+    double *tlo = nullptr, *thi = nullptr;
+    int32_t* nodes = nullptr;
+    float *U = nullptr, *T = nullptr, *scr = nullptr, *grad = nullptr, *mom = nullptr, *vel = nullptr, *loss = nullptr,
+          *tau = nullptr, *res = nullptr;
+    auto cleanup = [&]() {
+        void* bufs[] = {tlo, thi, nodes, U, T, scr, grad, mom, vel, loss, tau, res};
+        for (void* b : bufs)
+            if (b) (void)hipFree(b);
+    };
+    if (hipMalloc((void**)&tlo, 8 * n) || hipMalloc((void**)&thi, 8 * n) || hipMalloc((void**)&nodes, 4 * n) ||
+        hipMalloc((void**)&U, 8 * n) || hipMalloc((void**)&T, 12 * n) ||
+        hipMalloc((void**)&scr, sizeof(float) * grad_scratch_floats(B)) || hipMalloc((void**)&grad, 4 * kNParam) ||
+        hipMalloc((void**)&mom, 4 * kNParam) || hipMalloc((void**)&vel, 4 * kNParam) || hipMalloc((void**)&loss, 4) ||
+        hipMalloc((void**)&tau, 16) || hipMalloc((void**)&res, 12 * n)) {
+        cleanup();
+        return BK_ENOMEM;
+    }
+    // targets from the plain solver
+    st = bk_window(nu, x, tlo, thi, nodes, n, L, Lq, s);
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    const float cx = (float)m->norm[0], sx = (float)m->norm[1], cnu = (float)m->norm[2], snu = (float)m->norm[3];
+    const float stn = (float)m->norm[4], snn = (float)m->norm[5];
+    if (st == BK_OK)
+        hipLaunchKernelGGL(k_make_targets, dim3(nb), dim3(256), 0, s, nu, x, tlo, thi, nodes, n, cx, sx, cnu, snu, stn,
+                           snn, U, T);
+    // training box = range of the data
+    {
+        std::vector<double> hx(n), hn(n);
+        if (st == BK_OK && (hipMemcpyAsync(hx.data(), x, 8 * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                            hipMemcpyAsync(hn.data(), nu, 8 * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                            hipStreamSynchronize(s) != hipSuccess))
+            st = BK_EHIP;
+        if (st == BK_OK) {
+            double lo = 1e300, hi = -1e300, nlo = 1e300, nhi = -1e300;
+            for (int64_t i = 0; i < n; ++i) {
+                double lx = log10(hx[i]);
+                lo = std::min(lo, lx); hi = std::max(hi, lx);
+                nlo = std::min(nlo, fabs(hn[i])); nhi = std::max(nhi, fabs(hn[i]));
+            }
+            m->box[0] = lo; m->box[1] = hi; m->box[2] = nlo; m->box[3] = nhi;
+        }
+    }
+    // He initialisation from a seeded host generator
+    std::vector<float> P(kNParam, 0.0f);
+    {
+        std::mt19937_64 rng(cfg->seed);
+        std::normal_distribution<float> nd(0.0f, 1.0f);
+        for (int i = 0; i < kH * 2; ++i) P[kOffW1 + i] = nd(rng) * sqrtf(2.0f / 2.0f);
+        for (int i = 0; i < kH; ++i) P[kOffB1 + i] = 0.1f * nd(rng);
+        for (int i = 0; i < kH * kH; ++i) P[kOffW2 + i] = nd(rng) * sqrtf(2.0f / (float)kH);
+        for (int i = 0; i < 3 * kH; ++i) P[kOffW3 + i] = nd(rng) * sqrtf(1.0f / (float)kH);
+        P[kOffB3 + 0] = 0.2f; P[kOffB3 + 1] = 0.8f; P[kOffB3 + 2] = 0.5f;
+    }
+    const float htau[4] = {cfg->tau_lo, cfg->tau_hi, cfg->tau_n, 0.0f};
+    if (st == BK_OK && (hipMemcpyAsync(m->params, P.data(), 4 * kNParam, hipMemcpyHostToDevice, s) != hipSuccess ||
+                        hipMemcpyAsync(tau, htau, 16, hipMemcpyHostToDevice, s) != hipSuccess ||
+                        hipMemsetAsync(mom, 0, 4 * kNParam, s) != hipSuccess ||
+                        hipMemsetAsync(vel, 0, 4 * kNParam, s) != hipSuccess))
+        st = BK_EHIP;
+    std::mt19937_64 prng(cfg->seed ^ 0x9e3779b97f4a7c15ULL);
+    const int64_t steps_per_epoch = (n + B - 1) / B;
+    const int64_t total = steps_per_epoch * cfg->epochs;
+    int64_t step = 0;
+    float last = 0.0f;
+    for (int ep = 0; ep < cfg->epochs && st == BK_OK; ++ep) {
+        // a fresh affine permutation of the rows each epoch
+        uint64_t pa = prng() % (uint64_t)n;
+        while (pa == 0 || gcd_u64(pa, (uint64_t)n) != 1) pa = prng() % (uint64_t)n;
+        const uint64_t pb = prng() % (uint64_t)n;
+        hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, s, loss, (int64_t)1);
+        for (int64_t b0 = 0; b0 < n && st == BK_OK; b0 += B) {
+            const int64_t bs = std::min(B, n - b0);
+            ++step;
+            // cosine decay of the step size to 5% of its initial value
+            const double frac = (double)step / (double)total;
+            const float lr = (float)(cfg->lr * (0.05 + 0.95 * 0.5 * (1.0 + cos(M_PI * frac))));
+            st = launch_grad(m->params, U, T, tau, bs, n, pa, pb, b0, grad, loss, scr, s);
+            if (st == BK_OK) st = bk_adam_step(m->params, grad, mom, vel, kNParam, (int32_t)std::min<int64_t>(step, 1 << 30),
+                                               lr, cfg->beta1, cfg->beta2, cfg->eps, s);
+        }
+        float hl = 0.0f;
+        if (st == BK_OK && (hipMemcpyAsync(&hl, loss, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                            hipStreamSynchronize(s) != hipSuccess))
+            st = BK_EHIP;
+        last = hl / (float)steps_per_epoch;
+    }
+    // inference pack, then margins from the inference-path residuals on the training set
+    if (st == BK_OK) {
+        if (hipMemcpyAsync(P.data(), m->params, 4 * kNParam, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = BK_EHIP;
+        for (int i = 0; st == BK_OK && i < kNParam; ++i)
+            if (!std::isfinite(P[i])) st = BK_EINVAL;
+        if (st == BK_OK) st = model_upload(m, P.data());
+    }
+    if (st == BK_OK) {
+        hipLaunchKernelGGL(k_residuals, dim3(nb), dim3(256), 0, s, make_dev(m), U, T, n, res);
+        std::vector<float> hr(3 * n);
+        if (hipMemcpyAsync(hr.data(), res, 12 * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = BK_EHIP;
+        if (st == BK_OK) {
+            double mg[3];
+            std::vector<float> col(n);
+            for (int k = 0; k < 3; ++k) {
+                for (int64_t i = 0; i < n; ++i) col[i] = hr[3 * i + k];
+                const int64_t q = (int64_t)(0.998 * (double)(n - 1));
+                std::nth_element(col.begin(), col.begin() + q, col.end());
+                mg[k] = std::max(0.0, (double)col[q]);
+            }
+            m->margins[0] = mg[0] + 0.01;
+            m->margins[1] = mg[1] + 0.01;
+            m->margins[2] = mg[2] + 0.02;
+            m->margins[3] = 1.0;
+        }
+    }
+    cleanup();
+    if (st == BK_OK) m->trained = true;
+    if (final_loss) *final_loss = last;
+    return st;
 }

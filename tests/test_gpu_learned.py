@@ -1,0 +1,251 @@
+"""GPU tests of the window-predicting MLP: training kernels against the numpy
+float64 oracle, matrix-core inference, training, and the learned evaluation form
+against the CPU K_nu oracle (including forced fallbacks)."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+from gpu_util import TOL_MIXED, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2502_00356_amd import api
+    return api
+
+
+def _rand_params(seed, scale=0.4):
+    from oracle import MLP_SHAPES
+    rng = np.random.default_rng(seed)
+    return {k: rng.normal(0, scale, s) for k, s in MLP_SHAPES}
+
+
+def _flat(p):
+    from oracle import MLP_SHAPES
+    return np.concatenate([p[k].ravel() for k, _ in MLP_SHAPES])
+
+
+def _unflat(v):
+    from oracle import MLP_SHAPES
+    out, o = {}, 0
+    for k, s in MLP_SHAPES:
+        n = int(np.prod(s))
+        out[k] = v[o:o + n].reshape(s)
+        o += n
+    return out
+
+
+def test_gradient_kernels_match_oracle(api, orc):
+    """bk_mlp_grad (FP32) against the float64 oracle: loss and every gradient entry
+    within 1e-5 relative (plus 1e-6 of the largest gradient for near-zero entries)."""
+    import torch
+    p = _rand_params(3)
+    rng = np.random.default_rng(4)
+    B = 2048
+    u = rng.uniform(-1, 1, (B, 2))
+    tgt = rng.normal(0.5, 0.5, (B, 3))
+    tau = np.array([0.1, 0.9, 0.9])
+    # the GPU sees FP32-rounded parameters and data; the oracle gets the same values
+    pf = _flat(p).astype(np.float32)
+    uf, tf, tauf = u.astype(np.float32), tgt.astype(np.float32), tau.astype(np.float32)
+    loss, grad = api.mlp_grad(to_dev(pf), to_dev(uf), to_dev(tf), to_dev(tauf))
+    torch.cuda.synchronize()
+    p64 = _unflat(pf.astype(np.float64))
+    y, cache = orc.mlp_forward(p64, uf.astype(np.float64))
+    lref = orc.mlp_loss(y, tf.astype(np.float64), tauf.astype(np.float64))
+    gref = _flat(orc.mlp_backward(p64, cache, y, tf.astype(np.float64), tauf.astype(np.float64)))
+    g = grad.cpu().numpy().astype(np.float64)
+    assert abs(float(loss.cpu()[0]) - lref) <= 1e-5 * abs(lref)
+    assert np.all(np.abs(g - gref) <= 1e-5 * np.abs(gref) + 1e-6 * np.abs(gref).max())
+
+
+def test_adam_kernel_matches_oracle(api, orc):
+    import torch
+    rng = np.random.default_rng(5)
+    n = 4547
+    p = rng.normal(0, 1, n).astype(np.float32)
+    g = rng.normal(0, 1e-2, n).astype(np.float32)
+    m = rng.normal(0, 1e-3, n).astype(np.float32)
+    v = rng.uniform(0, 1e-4, n).astype(np.float32)
+    dp, dg, dm, dv = to_dev(p), to_dev(g), to_dev(m), to_dev(v)
+    api.adam_step(dp, dg, dm, dv, 7, 1e-3)
+    torch.cuda.synchronize()
+    P = {"a": p.astype(np.float64)}; G = {"a": g.astype(np.float64)}
+    M = {"a": m.astype(np.float64)}; V = {"a": v.astype(np.float64)}
+    orc.adam_step(P, G, M, V, 7, 1e-3)
+    # FP32 kernel vs float64 oracle: 1 - beta2 = 1e-3 carries a relative rounding
+    # error of ~1e-5 in FP32, which the new-gradient part of v inherits
+    assert np.allclose(dp.cpu().numpy(), P["a"], rtol=2e-6, atol=1e-7)
+    assert np.allclose(dm.cpu().numpy(), M["a"], rtol=2e-6, atol=1e-9)
+    assert np.allclose(dv.cpu().numpy(), V["a"], rtol=3e-5, atol=1e-12)
+
+
+def test_matrix_core_inference(api, orc):
+    """bk_mlp_infer (FP16 operands, FP32 accumulation) against the float64 forward of
+    the same FP32 parameters; FP16 rounding of weights and activations bounds the
+    difference (here 2e-2 absolute on outputs of size ~1)."""
+    import torch
+    p = _rand_params(6, scale=0.25)
+    m = api.Model()
+    m.set_params(torch.from_numpy(_flat(p).astype(np.float32)))
+    rng = np.random.default_rng(7)
+    for n in (1, 63, 64, 1000, 4096):
+        u = rng.uniform(-1, 1, (n, 2)).astype(np.float32)
+        y = m.infer(to_dev(u))
+        torch.cuda.synchronize()
+        yref, _ = orc.mlp_forward(_unflat(_flat(p).astype(np.float32).astype(np.float64)), u.astype(np.float64))
+        assert np.abs(y.cpu().numpy() - yref).max() <= 2e-2 * (1 + np.abs(yref).max()), n
+
+
+@pytest.fixture(scope="module")
+def trained(api, tmp_path_factory):
+    """A model trained on the GPU on 2^18 pairs of the standalone law (seed 4)."""
+    import torch
+    from paper_2502_00356_amd import workloads
+    nu, x = workloads.training_pairs(1 << 18, seed=4)
+    m = api.Model()
+    loss = m.train(to_dev(nu), to_dev(x), epochs=30, batch=4096, lr=3e-3, seed=11)
+    torch.cuda.synchronize()
+    assert np.isfinite(loss)
+    return m
+
+
+def test_training_reduces_loss(api):
+    import torch
+    from paper_2502_00356_amd import workloads
+    nu, x = workloads.training_pairs(1 << 14, seed=8)
+    m1 = api.Model(); m2 = api.Model()
+    l1 = m1.train(to_dev(nu), to_dev(x), epochs=1, batch=1024, seed=1)
+    l2 = m2.train(to_dev(nu), to_dev(x), epochs=20, batch=1024, seed=1)
+    assert l2 < 0.5 * l1
+
+
+def test_learned_parity(api, orc, trained):
+    """Learned form against the oracle on the standalone law: every entry within
+    2e-6 (accepted entries and fallbacks alike), fallback rate reported."""
+    import torch
+    from paper_2502_00356_amd import workloads
+    nu, x, hidx = workloads.grid_pairs(1 << 16, seed=12)
+    stats = torch.zeros(api.STATS_LEN, dtype=torch.int64, device="cuda")
+    out = api.besselk(to_dev(nu), to_dev(x), mode="learned", model=trained, result=api.RESULT_SCALED, stats=stats)
+    torch.cuda.synchronize()
+    _, _, ks = orc.besselk(nu, x)
+    e = rel_err(out.cpu().numpy(), ks)
+    s = stats.cpu().numpy()
+    fb = s[api.STAT_FB_RANGE] + s[api.STAT_FB_TAIL] + s[api.STAT_FB_NONFINITE]
+    print("learned: max rel %.3g, fallbacks %d of %d (range %d tail %d nonfinite %d), N raised %d" % (
+        e.max(), fb, nu.size, s[2], s[3], s[5], s[4]))
+    assert e.max() <= TOL_MIXED
+    assert fb < 0.02 * nu.size
+
+
+def test_learned_out_of_range_falls_back(api, orc, trained):
+    """Pairs outside the training box all take the plain-solver path and stay exact."""
+    import torch
+    from paper_2502_00356_amd import workloads
+    nu, x = workloads.out_of_range_pairs(1 << 12, seed=6)
+    stats = torch.zeros(api.STATS_LEN, dtype=torch.int64, device="cuda")
+    out = api.besselk(to_dev(nu), to_dev(x), mode="learned", model=trained, result=api.RESULT_SCALED, stats=stats)
+    torch.cuda.synchronize()
+    _, _, ks = orc.besselk(nu, x)
+    assert rel_err(out.cpu().numpy(), ks).max() <= TOL_MIXED
+    assert stats.cpu().numpy()[api.STAT_FB_RANGE] == nu.size
+
+
+def test_zero_weights_force_fallback(api, orc):
+    """A model whose weights are all zero predicts an empty window: every entry fails
+    the tail check, takes the fallback, and the result still meets the bar."""
+    import torch
+    from paper_2502_00356_amd import workloads
+    m = api.Model()
+    m.set_params(torch.zeros(api.MLP_NPARAM))
+    nu, x = workloads.small_pairs(3000, seed=9)
+    stats = torch.zeros(api.STATS_LEN, dtype=torch.int64, device="cuda")
+    out = api.besselk(to_dev(nu), to_dev(x), mode="learned", model=m, result=api.RESULT_SCALED, stats=stats)
+    torch.cuda.synchronize()
+    _, _, ks = orc.besselk(nu, x)
+    assert rel_err(out.cpu().numpy(), ks).max() <= TOL_MIXED
+    s = stats.cpu().numpy()
+    assert s[api.STAT_FB_TAIL] + s[api.STAT_FB_NONFINITE] == nu.size
+
+
+def test_halved_node_prediction_is_raised(api, orc, trained, tmp_path):
+    """Halving the predicted node count (through the output scale) leaves the step
+    too coarse; the strip-bound rule raises N for those entries and the bar holds."""
+    import torch
+    from paper_2502_00356_amd import workloads
+    path = str(tmp_path / "m.bin")
+    trained.save(path)
+    m = api.Model(path)
+    m.set_margins(0.05, 0.05, 0.0, 0.0)
+    params = m.get_params()
+    norm = m.get_norm().numpy().copy()
+    norm[5] *= 0.5                       # halve the node-count scale: predicted N is halved
+    m.set_norm(norm)
+    nu, x, _ = workloads.grid_pairs(1 << 14, seed=13)
+    stats = torch.zeros(api.STATS_LEN, dtype=torch.int64, device="cuda")
+    out = api.besselk(to_dev(nu), to_dev(x), mode="learned", model=m, result=api.RESULT_SCALED, stats=stats)
+    torch.cuda.synchronize()
+    _, _, ks = orc.besselk(nu, x)
+    assert rel_err(out.cpu().numpy(), ks).max() <= TOL_MIXED
+    assert stats.cpu().numpy()[api.STAT_NODE_RAISED] > nu.size // 2
+    assert params.shape[0] == api.MLP_NPARAM
+
+
+def test_save_load_roundtrip(api, trained, tmp_path):
+    import torch
+    path = str(tmp_path / "w.bin")
+    trained.save(path)
+    m = api.Model(path)
+    assert torch.equal(m.get_params(), trained.get_params())
+    assert torch.equal(m.get_box(), trained.get_box())
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"not a model")
+    with pytest.raises(api.BkError):
+        api.Model(str(bad))
+
+
+def test_learned_matern(api, orc, trained):
+    """Learned Matern tiles (MLP tabulated over log10 x at the launch's nu) against
+    the oracle, FP64 and FP32 output."""
+    from paper_2502_00356_amd import workloads as w
+    import torch
+    xy = w.uniform_locations(300, seed=51)
+    for nu, beta in ((0.8, 0.05), (2.3, 0.05), (3.7, 0.02)):
+        lx, ly = to_dev(xy[:, 0]), to_dev(xy[:, 1])
+        out = api.matern_tiles(lx, ly, 1.0, beta, nu, 128, 1, mode="learned", model=trained)
+        torch.cuda.synchronize()
+        A = api.unpack_tiles(out, 300, 128, 1).numpy()
+        R = orc.matern_full(xy, 1.0, beta, nu)
+        m = R > 1e-300
+        assert rel_err(A[m], R[m]).max() <= TOL_MIXED, nu
+
+
+def test_learned_gain_over_mixed(api, trained):
+    """What the trained network buys: on 2^22 pairs of the standalone law the learned
+    form is faster than the same FP32-compensated node sums behind the FP64 solve."""
+    import torch
+    from paper_2502_00356_amd import workloads
+    nu, x, _ = workloads.grid_pairs(1 << 22, seed=2)
+    dnu, dx = to_dev(nu), to_dev(x)
+    out = torch.empty_like(dx)
+    ws = torch.empty(api.workspace_bytes(dx.numel()), dtype=torch.uint8, device="cuda")
+    times = {}
+    for mode in ("mixed", "learned", "mixed", "learned"):
+        api.besselk(dnu, dx, out=out, mode=mode, model=trained, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            api.besselk(dnu, dx, out=out, mode=mode, model=trained, workspace=ws)
+        torch.cuda.synchronize()
+        times[mode] = (time.perf_counter() - t0) / 3
+    print("2^22 pairs: mixed %.3f ms, learned %.3f ms, gain %.2fx" % (
+        times["mixed"] * 1e3, times["learned"] * 1e3, times["mixed"] / times["learned"]))
+    assert times["learned"] < times["mixed"]
