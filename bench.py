@@ -25,9 +25,19 @@ sys.path.insert(0, ROOT)
 # quarter rate and count as 4 issue slots.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
-# VALU issue slots of one trapezoid node (the loop body of each form's node
-# walk in the gfx950 code object of libbesselk.so; exponentials inlined).
-NODE_SLOTS = {"plain": 48.0, "mixed": 39.0, "learned": 44.0}
+# VALU issue slots of one trapezoid node: the loop body of each form's node walk in
+# the gfx950 code of libbesselk.so, counted by the build (paper_2502_00356_amd/build.py
+# writes node_slots.json; quarter-rate transcendentals count 4).
+def load_node_slots():
+    path = os.path.join(ROOT, "paper_2502_00356_amd", "node_slots.json")
+    slots = {"plain": 50.0, "mixed": 39.0, "learned": 36.0}
+    if os.path.exists(path):
+        with open(path) as f:
+            slots.update({k: float(v) for k, v in json.load(f).items()})
+    return slots
+
+
+NODE_SLOTS = load_node_slots()
 
 # HBM bytes per launch of the learned kernel on the 2^24 grid, from the FETCH_SIZE and
 # WRITE_SIZE counter runs scaled by a plain 1 GiB copy (profiles/besselk_grid_2e24_hbm_traffic.txt),

@@ -47,8 +47,14 @@ typedef enum {
  *                  count in place of the solve (the count is raised to the
  *                  strip-bound rule's if lower); terms as in BK_MIXED_F32C; entries
  *                  outside the model's training box, or whose window fails the
- *                  tail check, are recomputed with BK_MIXED_F32C. */
-typedef enum { BK_PLAIN_F64 = 0, BK_MIXED_F32C = 1, BK_LEARNED = 2 } bk_mode;
+ *                  tail check, are recomputed with BK_MIXED_F32C.
+ *  BK_PAPER_REFINED: the paper's refined algorithm (Sec. IV-C, Alg. 2), FP64:
+ *                  for x < 0.1 Temme's series with the forward recurrence
+ *                  (Sec. IV-A); otherwise the fixed window [0, t_upper] (default
+ *                  9) with b bins (default 40), scaled by the largest node value.
+ *                  Its accuracy for x >= 0.1 is the paper's trade-off of b against
+ *                  x (large x needs many bins). */
+typedef enum { BK_PLAIN_F64 = 0, BK_MIXED_F32C = 1, BK_LEARNED = 2, BK_PAPER_REFINED = 3 } bk_mode;
 
 /* Matern output element type. */
 typedef enum { BK_OUT_F64 = 0, BK_OUT_F32 = 1 } bk_dtype;
@@ -73,9 +79,9 @@ typedef struct bk_model bk_model;
 
 /* Per-call options. Zero-initialise and set what you need.
  *  L_window : window threshold L of Sec. IV-B, [t0,t1] = {t : g(t) >= g(t_max) - L}.
- *             0 selects the form's default (38 for BK_PLAIN_F64, 16 otherwise).
+ *             0 selects the form's default (36 for BK_PLAIN_F64, 15 otherwise).
  *  L_quad   : node-count target: the step keeps the strip-bound discretisation
- *             error near exp(-L_quad). 0 selects 36.5 (plain) or 15.4 (others).
+ *             error near exp(-L_quad). 0 selects 35 (plain) or 14.5 (others).
  *  result   : bk_result, for bk_besselk_ex only.
  *  sigma2, beta, nu : Matern parameters theta = (sigma^2, beta, nu) of Sec. III-A
  *             (sigma2 >= 0, beta > 0, nu > 0), for bk_matern_tiles only.
@@ -88,7 +94,7 @@ typedef struct {
     int32_t mode;
     int32_t result;
     int32_t out_dtype;
-    int32_t reserved0;
+    int32_t bins;        /* BK_PAPER_REFINED: number of bins b (0 selects 40) */
     double L_window;
     double L_quad;
     double sigma2;
@@ -98,6 +104,7 @@ typedef struct {
     unsigned long long* stats;
     void* workspace;
     size_t workspace_bytes;
+    double t_upper;      /* BK_PAPER_REFINED: upper end of the window (0 selects 9) */
 } bk_params;
 
 /* Human-readable name of a status code (static string). */
@@ -161,7 +168,7 @@ int64_t bk_matern_tile_offset(int64_t n, int32_t tile_size, int32_t lower_only, 
  * and nodes = N, the trapezoid interval count for target exp(-L_quad).
  * These are the training targets of the window-predicting MLP.
  * nu, x : n doubles (device). t_lo, t_hi : n doubles, nodes : n int32 (device).
- * L_window, L_quad > 0 (0 selects 16 and 15.4). */
+ * L_window, L_quad >= 0 (0 selects 15 and 14.5). */
 int bk_window(const double* nu, const double* x, double* t_lo, double* t_hi, int32_t* nodes,
               int64_t n, double L_window, double L_quad, hipStream_t stream);
 
@@ -182,7 +189,7 @@ typedef struct {
     float eps;             /* Adam denominator offset                          */
     float tau_lo, tau_hi, tau_n; /* expectile levels of the three outputs      */
     uint64_t seed;         /* initialisation and shuffling seed                */
-    double L_window, L_quad; /* window targets (0 selects 16 and 15.4)         */
+    double L_window, L_quad; /* window targets (0 selects 15 and 14.5)         */
 } bk_train_cfg;
 
 /* Create an empty model (host handle; device memory owned by the model). */

@@ -42,6 +42,10 @@ def _load():
                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, _P]
         lib.oracle_window.restype = None
         lib.oracle_window.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_double, _P, _P, _P, _P]
+        lib.oracle_fixed_window.restype = None
+        lib.oracle_fixed_window.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int, ctypes.c_double, _P, _P]
+        lib.oracle_log_truncated.restype = ctypes.c_int64
+        lib.oracle_log_truncated.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_double, _P]
         lib.oracle_logintegrand.restype = None
         lib.oracle_logintegrand.argtypes = [_P, _P, _P, _P, ctypes.c_int64]
         _lib = lib
@@ -70,6 +74,45 @@ def besselk(nu, x):
     if bad:
         raise RuntimeError("oracle quadrature did not converge on %d entries" % bad)
     return k, lk, ks
+
+
+def fixed_window(nu, x, bins=40, T=9.0):
+    """Trapezoid sum of the paper's refined algorithm (Sec. IV-C, Alg. 2, x >= 0.1):
+    b bins on the fixed window [0, T]. Returns (S, log S)."""
+    nu, x = (a.ravel() for a in np.broadcast_arrays(_d(nu), _d(x)))
+    nu, x = _d(nu), _d(x)
+    ls, s = np.empty(x.size), np.empty(x.size)
+    _load().oracle_fixed_window(_ptr(nu), _ptr(x), x.size, int(bins), float(T), _ptr(ls), _ptr(s))
+    return s, ls
+
+
+def log_truncated(nu, x, L):
+    """log of int_0^L exp(-x cosh t) cosh(nu t) dt (RBK of the paper's Alg. 1)."""
+    nu, x = (a.ravel() for a in np.broadcast_arrays(_d(nu), _d(x)))
+    nu, x = _d(nu), _d(x)
+    out = np.empty(x.size)
+    bad = _load().oracle_log_truncated(_ptr(nu), _ptr(x), x.size, float(L), _ptr(out))
+    if bad:
+        raise RuntimeError("oracle quadrature did not converge on %d entries" % bad)
+    return out
+
+
+def empirical_upper_bound(x_grid, nu_grid, tol=1e-9, candidates=None):
+    """The paper's empirical upper-bound finder (Alg. 1) with this oracle in place of
+    the reference library: the smallest candidate L such that
+    max over the (x, nu) grid of |log K - log int_0^L| <= tol.
+    Returns (L, max abs error at L), or (None, error at the largest candidate)."""
+    X, V = np.meshgrid(np.asarray(x_grid, float), np.asarray(nu_grid, float), indexing="ij")
+    X, V = X.ravel(), V.ravel()
+    _, lk, _ = besselk(V, X)
+    if candidates is None:
+        candidates = np.arange(1.0, 20.01, 0.25)
+    err = None
+    for L in candidates:
+        err = float(np.max(np.abs(lk - log_truncated(V, X, L))))
+        if err <= tol:
+            return float(L), err
+    return None, err
 
 
 def logintegrand(nu, x, t):

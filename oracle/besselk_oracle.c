@@ -263,6 +263,65 @@ void oracle_window(const double* nu, const double* x, int64_t n, double L,
     }
 }
 
+/* Exported: log of the truncated integral int_0^L exp(-x cosh t) cosh(nu t) dt,
+ * the quantity RBK of the paper's empirical upper-bound finder (Alg. 1), by the
+ * same adaptive rule as oracle_besselk. Returns the count of non-converged entries. */
+int64_t oracle_log_truncated(const double* nu, const double* x, int64_t n, double L, double* out)
+{
+    int64_t bad = 0;
+#pragma omp parallel reduction(+ : bad)
+    {
+        orc_seg* seg = (orc_seg*)malloc(sizeof(orc_seg) * ORC_MAXSUB);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i) {
+            long double v = fabsl((long double)nu[i]), z = (long double)x[i], Lt = (long double)L;
+            orc_integrand f;
+            f.nu = v; f.x = z;
+            long double th = orc_tmax(v, z);
+            if (th > Lt) th = Lt;
+            f.that = th;
+            f.lcref = orc_logcosh(v * th);
+            int ok = 1;
+            long double I = 0.0L;
+            if (th > 0.0L) I += orc_adapt(&f, 0.0L, th, 1e-17L, seg, &ok);
+            if (Lt > th) I += orc_adapt(&f, th, Lt, 1e-17L, seg, &ok);
+            if (!ok) ++bad;
+            out[i] = (double)(orc_g(v, z, th) + logl(I));
+        }
+        free(seg);
+    }
+    return bad;
+}
+
+/* Exported: the fixed-window trapezoid sum of the paper's refined algorithm for
+ * x >= 0.1 (Sec. IV-C, Alg. 2, integral branch; Eq. "refined" with the weights
+ * c_m read as multiplicative trapezoid weights): with h = T / b and t_m = m h,
+ *   S = sum_{m=0}^{b} h c_m exp(-x cosh t_m) cosh(nu t_m),  c_0 = c_b = 1/2, else 1.
+ * The paper scales by the grid maximum before summing; that factor cancels, so
+ * the oracle is the sum itself, in long double. Output: log S and S (double). */
+void oracle_fixed_window(const double* nu, const double* x, int64_t n, int bins, double T,
+                         double* logs, double* s)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const long double v = fabsl((long double)nu[i]), z = (long double)x[i];
+        const long double h = (long double)T / (long double)bins;
+        long double gmax = -1e4000L;
+        for (int m = 0; m <= bins; ++m) {
+            long double g = orc_g(v, z, (long double)m * h);
+            if (g > gmax) gmax = g;
+        }
+        long double acc = 0.0L;
+        for (int m = 0; m <= bins; ++m) {
+            long double c = (m == 0 || m == bins) ? 0.5L : 1.0L;
+            acc += c * expl(orc_g(v, z, (long double)m * h) - gmax);
+        }
+        long double ls = gmax + logl(h * acc);
+        logs[i] = (double)ls;
+        s[i] = (double)expl(ls);
+    }
+}
+
 /* Exported: the log-integrand itself, for tests that pin the oracle's g. */
 void oracle_logintegrand(const double* nu, const double* x, const double* t, double* out, int64_t n)
 {

@@ -19,13 +19,13 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-PLAIN_F64, MIXED_F32C, LEARNED = 0, 1, 2
+PLAIN_F64, MIXED_F32C, LEARNED, PAPER_REFINED = 0, 1, 2, 3
 RESULT_K, RESULT_SCALED, RESULT_LOG = 0, 1, 2
 OUT_F64, OUT_F32 = 0, 1
 STAT_ENTRIES, STAT_NODES, STAT_FB_RANGE, STAT_FB_TAIL, STAT_NODE_RAISED, STAT_FB_NONFINITE = range(6)
 STATS_LEN = 8
 MLP_NPARAM = 4547
-MODES = {"plain": PLAIN_F64, "mixed": MIXED_F32C, "learned": LEARNED}
+MODES = {"plain": PLAIN_F64, "mixed": MIXED_F32C, "learned": LEARNED, "paper": PAPER_REFINED}
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -34,9 +34,10 @@ _dbl = ctypes.c_double
 
 
 class Params(ctypes.Structure):
-    _fields_ = [("mode", _i32), ("result", _i32), ("out_dtype", _i32), ("reserved0", _i32),
+    _fields_ = [("mode", _i32), ("result", _i32), ("out_dtype", _i32), ("bins", _i32),
                 ("L_window", _dbl), ("L_quad", _dbl), ("sigma2", _dbl), ("beta", _dbl), ("nu", _dbl),
-                ("model", _vp), ("stats", _vp), ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t)]
+                ("model", _vp), ("stats", _vp), ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t),
+                ("t_upper", _dbl)]
 
 
 class Locs(ctypes.Structure):
@@ -130,7 +131,7 @@ def workspace_bytes(n):
 
 
 def besselk(nu, x, out=None, mode="plain", result=RESULT_K, L_window=0.0, L_quad=0.0,
-            stats=None, model=None, workspace=None, stream=None):
+            stats=None, model=None, workspace=None, stream=None, bins=0, t_upper=0.0):
     """K_nu(x) (or e^x K, log K) for device float64 tensors nu, x of equal size."""
     n = x.numel()
     if nu.numel() != n:
@@ -143,6 +144,7 @@ def besselk(nu, x, out=None, mode="plain", result=RESULT_K, L_window=0.0, L_quad
     if m == LEARNED and workspace is None and n > 0:
         workspace = torch.empty(workspace_bytes(n), dtype=torch.uint8, device=x.device)
     p = Params(mode=m, result=int(result), L_window=float(L_window), L_quad=float(L_quad),
+               bins=int(bins), t_upper=float(t_upper),
                model=(model.handle if model is not None else None),
                stats=(_dev(stats, torch.int64) if stats is not None else None),
                workspace=(workspace.data_ptr() if workspace is not None else None),
@@ -179,7 +181,7 @@ def matern_tile_offset(n, tile_size, lower_only, I, J):
 
 
 def matern_tiles(lx, ly, sigma2, beta, nu, tile_size, lower_only, mode="plain", out_dtype=OUT_F64,
-                 out=None, model=None, L_window=0.0, L_quad=0.0, stream=None):
+                 out=None, model=None, L_window=0.0, L_quad=0.0, stream=None, bins=0, t_upper=0.0):
     """Tiled Matern covariance (packed tiles, see bk_matern_tiles)."""
     n = lx.numel()
     if ly.numel() != n:
@@ -192,7 +194,7 @@ def matern_tiles(lx, ly, sigma2, beta, nu, tile_size, lower_only, mode="plain", 
         raise ValueError("out too small or of the wrong dtype")
     locs = Locs(x=_dev(lx, torch.float64), y=_dev(ly, torch.float64), n=n)
     p = Params(mode=_mode(mode), out_dtype=int(out_dtype), sigma2=float(sigma2), beta=float(beta), nu=float(nu),
-               L_window=float(L_window), L_quad=float(L_quad),
+               L_window=float(L_window), L_quad=float(L_quad), bins=int(bins), t_upper=float(t_upper),
                model=(model.handle if model is not None else None))
     _check(_matern(ctypes.byref(locs), ctypes.byref(p), int(tile_size), int(lower_only), out.data_ptr(),
                    _stream(stream)))

@@ -15,6 +15,69 @@ SOURCES = ["bk_kernels.hip", "bk_mlp.hip"]
 ARCH = os.environ.get("BK_OFFLOAD_ARCH", "gfx950")
 
 
+TRANS_QUARTER = ("v_exp_f32", "v_log_f32", "v_rcp_f32", "v_rsq_f32", "v_sqrt_f32", "v_sin_f32", "v_cos_f32",
+                 "v_rcp_f64", "v_rsq_f64", "v_sqrt_f64", "v_exp_f16", "v_log_f16")
+
+
+def _loops(lines):
+    """(start, end) line spans of the loops of one function: a label and a later
+    branch back to it."""
+    import re
+    labels = {}
+    for i, l in enumerate(lines):
+        m = re.match(r"^(\.LBB\d+_\d+):", l)
+        if m:
+            labels[m.group(1)] = i
+    spans = []
+    for i, l in enumerate(lines):
+        m = re.search(r"s_cbranch_\w+\s+(\.LBB\d+_\d+)|s_branch\s+(\.LBB\d+_\d+)", l)
+        if m:
+            lab = m.group(1) or m.group(2)
+            if lab in labels and labels[lab] < i:
+                spans.append((labels[lab], i))
+    return spans
+
+
+def node_slots(asm_path):
+    """VALU issue slots of one trapezoid node per K_nu kernel, read from the gfx950
+    assembly of this build: the node loop is the innermost loop that evaluates the
+    node exponential (v_exp_f32 for the FP32-term forms; the inlined FP64 exp, one
+    v_ldexp_f64 without divisions or logarithms, for the plain form). Quarter-rate
+    transcendental instructions count four slots."""
+    text = open(asm_path).read().split("\n")
+    funcs = {}
+    cur = None
+    for l in text:
+        if l and not l.startswith((" ", "\t", ".", ";")) and l.endswith(":") or (l.startswith("_Z") and ": ;" in l):
+            cur = l.split(":")[0]
+            funcs[cur] = []
+        elif cur is not None:
+            funcs[cur].append(l)
+    want = {"plain": "k_besselkILi0", "mixed": "k_besselkILi1", "learned": "k_besselk_learned"}
+    out = {}
+    for form, key in want.items():
+        name = next((f for f in funcs if key in f), None)
+        if name is None:
+            continue
+        body = funcs[name]
+        best = None
+        for a, b in _loops(body):
+            seg = [x.strip() for x in body[a:b + 1]]
+            ops = [x.split()[0] for x in seg if x.startswith("v_")]
+            if form == "plain":
+                ok = ops.count("v_ldexp_f64") == 1 and "v_div_scale_f64" not in ops and "v_frexp_mant_f64_e32" not in ops
+            else:
+                ok = any(o.startswith("v_exp_f32") for o in ops) and "v_div_scale_f64" not in ops
+            if ok:
+                slots = sum(4 if o.split("_e32")[0].split("_e64")[0] in TRANS_QUARTER else 1
+                            for o in ops if not o.startswith("v_mfma"))
+                if best is None or (b - a) < best[0]:
+                    best = (b - a, slots)
+        if best is not None:
+            out[form] = best[1]
+    return out
+
+
 def build(verbose=False, jobs=None):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     flags = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
@@ -49,6 +112,22 @@ def build(verbose=False, jobs=None):
     os.replace(LIB + ".tmp", LIB)
     for o in objs:
         os.remove(o)
+    # node-loop issue slots of this build, for the benchmark's roofline accounting
+    try:
+        import json
+        slots = {}
+        for src in SOURCES:
+            asm = os.path.join(CSRC, src + ".s")
+            subprocess.check_call([hipcc] + flags + ["--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", asm],
+                                  stderr=subprocess.DEVNULL)
+            slots.update(node_slots(asm))
+            os.remove(asm)
+        with open(os.path.join(HERE, "node_slots.json"), "w") as f:
+            json.dump(slots, f)
+        if verbose:
+            print("node-loop issue slots:", slots, flush=True)
+    except Exception as e:  # the library is built; the slot table is an aid only
+        sys.stderr.write("node-slot count skipped: %s\n" % e)
     return LIB
 
 

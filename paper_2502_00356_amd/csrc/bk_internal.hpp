@@ -8,16 +8,26 @@
 
 namespace bk {
 
-// Default thresholds. Plain: L = -ln(2^-52) + 2 (Sec. IV-B takes the window at
-// machine epsilon; 2 nats of margin), node target e^-36.5. Mixed and learned:
-// L = 16, node target e^-15.4, sized for a 2e-6 relative error budget that also
-// holds the FP32 rounding of the node terms.
-constexpr double kDefaultLPlain = 38.0;
-constexpr double kDefaultLqPlain = 36.5;
-constexpr double kDefaultLMixed = 16.0;
-constexpr double kDefaultLqMixed = 15.4;
+// Default thresholds. Plain: L = 36 ~ -ln(2^-52) (Sec. IV-B takes the window at
+// machine epsilon), node target e^-35. Mixed and learned: L = 15, node target
+// e^-14.5; the quadrature error is then ~2.5e-7 at most over nu in [0.01, 10],
+// x in [1e-4, 1e3], leaving the rest of a 2e-6 relative budget to the FP32
+// rounding of the node terms.
+constexpr double kDefaultLPlain = 36.0;
+constexpr double kDefaultLqPlain = 35.0;
+constexpr double kDefaultLMixed = 15.0;
+constexpr double kDefaultLqMixed = 14.5;
+
+// The paper's refined algorithm: b = 40 bins on [0, 9] for x >= 0.1, Temme's
+// series below (Sec. IV-C, Alg. 2).
+constexpr int kPaperBins = 40;
+constexpr double kPaperT = 9.0;
+constexpr double kPaperTemmeX = 0.1;
 
 const RuleTable& rule_table();
+const RuleTable* rule_table_dev();
+const TemmeCoef& temme_coef();
+const TemmeCoef* temme_coef_dev();
 void resolve_thresholds(int mode, double L_in, double Lq_in, double* L, double* Lq);
 
 int bk_besselk_learned(const double* nu, const double* x, double* out, int64_t n, const bk_params* prm,

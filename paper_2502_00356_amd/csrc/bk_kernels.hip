@@ -13,6 +13,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/besselk.h"
 #include "bk_math.hpp"
 #include "bk_internal.hpp"
@@ -51,6 +53,79 @@ const RuleTable& rule_table()
     return R;
 }
 
+// Device copy of the rule table, one per GPU, made on first use and kept for the
+// life of the process (360 bytes). Kernels read it through a pointer, so its
+// values are scalar loads rather than 90 kernel-argument SGPRs.
+const RuleTable* rule_table_dev()
+{
+    static std::mutex mu;
+    static const RuleTable* dev_tab[64] = {nullptr};
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!dev_tab[d]) {
+        RuleTable* p = nullptr;
+        if (hipMalloc((void**)&p, sizeof(RuleTable)) != hipSuccess) return nullptr;
+        if (hipMemcpy(p, &rule_table(), sizeof(RuleTable), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(p);
+            return nullptr;
+        }
+        dev_tab[d] = p;
+    }
+    return dev_tab[d];
+}
+
+// Chebyshev coefficients of Temme's Gamma1 and Gamma2 (even in mu) in
+// u = 8 mu^2 - 1, by interpolation at kTemmeCheb Chebyshev nodes, in long double.
+const TemmeCoef& temme_coef()
+{
+    static TemmeCoef C = [] {
+        TemmeCoef c;
+        const int n = kTemmeCheb;
+        long double f1[kTemmeCheb], f2[kTemmeCheb];
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int k = 0; k < n; ++k) {
+            const long double u = cosl(pi * ((long double)k + 0.5L) / (long double)n);
+            const long double mu = sqrtl((u + 1.0L) / 8.0L);
+            const long double gm = 1.0L / tgammal(1.0L - mu), gp = 1.0L / tgammal(1.0L + mu);
+            f1[k] = (gm - gp) / (2.0L * mu);
+            f2[k] = 0.5L * (gm + gp);
+        }
+        for (int j = 0; j < n; ++j) {
+            long double a1 = 0.0L, a2 = 0.0L;
+            for (int k = 0; k < n; ++k) {
+                const long double w = cosl(pi * (long double)j * ((long double)k + 0.5L) / (long double)n);
+                a1 += f1[k] * w;
+                a2 += f2[k] * w;
+            }
+            const long double sc = (j == 0 ? 1.0L : 2.0L) / (long double)n;
+            c.g1[j] = (double)(a1 * sc);
+            c.g2[j] = (double)(a2 * sc);
+        }
+        return c;
+    }();
+    return C;
+}
+
+const TemmeCoef* temme_coef_dev()
+{
+    static std::mutex mu;
+    static const TemmeCoef* dev_tab[64] = {nullptr};
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!dev_tab[d]) {
+        TemmeCoef* p = nullptr;
+        if (hipMalloc((void**)&p, sizeof(TemmeCoef)) != hipSuccess) return nullptr;
+        if (hipMemcpy(p, &temme_coef(), sizeof(TemmeCoef), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(p);
+            return nullptr;
+        }
+        dev_tab[d] = p;
+    }
+    return dev_tab[d];
+}
+
 void resolve_thresholds(int mode, double L_in, double Lq_in, double* L, double* Lq)
 {
     bool plain = (mode == BK_PLAIN_F64);
@@ -58,15 +133,21 @@ void resolve_thresholds(int mode, double L_in, double Lq_in, double* L, double* 
     *Lq = Lq_in > 0.0 ? Lq_in : (plain ? kDefaultLqPlain : kDefaultLqMixed);
 }
 
-// Sum of a per-lane value over the workgroup, added once to a global counter.
-__device__ void block_count(unsigned long long* dst, unsigned long long v)
+// Sum of a per-lane value over a workgroup of nw wave64s (nw <= 16), added once to
+// a global counter.
+__device__ void block_count_w(unsigned long long* dst, unsigned long long v, int nw)
 {
-    __shared__ unsigned long long red[4];
+    __shared__ unsigned long long red[16];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
     if (lane == 0) red[wid] = v;
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(dst, red[0] + red[1] + red[2] + red[3]);
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < nw; ++w) t += red[w];
+        atomicAdd(dst, t);
+    }
 }
 
 // Special values shared by every form; returns true if handled.
@@ -87,29 +168,145 @@ __device__ __forceinline__ double assemble(double z, double delta, double hs, in
     return exp((delta - z) + log(hs));                   // subnormal range: one rounding
 }
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_besselk(const double* __restrict__ nu,
-                                                 const double* __restrict__ x,
-                                                 double* __restrict__ out, int64_t n, int result,
-                                                 double L, double Lq, RuleTable R,
-                                                 unsigned long long* __restrict__ stats)
+// Counting sort of a block's lanes by a small key (0..63): returns the lane's slot
+// in key order. Equal keys keep no particular order; results do not depend on it,
+// since every entry is computed by one lane from its own inputs.
+template <int NB>
+__device__ unsigned int block_sort_slot(int key, unsigned int* hist)
 {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int tid = threadIdx.x;
+    if (tid < 64) hist[tid] = 0u;
+    __syncthreads();
+    const unsigned int rank = atomicAdd(&hist[key], 1u);
+    __syncthreads();
+    if (tid < 64) {
+        const unsigned int h = hist[tid];
+        unsigned int incl = h;
+        for (int d = 1; d < 64; d <<= 1) {
+            const unsigned int up = __shfl_up(incl, d, 64);
+            if (tid >= d) incl += up;
+        }
+        hist[tid] = incl - h;
+    }
+    __syncthreads();
+    const unsigned int slot = hist[key] + rank;
+    __syncthreads();   // hist may be reused by the caller after this
+    return slot;
+}
+
+// Plain and mixed K_nu. A block of kSolveBlock entries is processed in three
+// phases, with the lanes re-sorted between them through LDS so that each wave
+// holds entries that take the same branches and loop counts:
+//  1. entry order: special values; key = peak regime (0: nu^2 <= x, t* = 0;
+//     1: interior peak, window from t = 0; 2: interior peak with a left root
+//     likely, estimated by nu asinh(nu/x) > L);
+//  2. regime order: the FP64 peak / window solve and node count;
+//  3. node-count order: the node walk, the prefactor and the store to the
+//     entry's own index.
+constexpr int kSolveBlock = 512;
+
+template <int MODE>
+__global__ __launch_bounds__(kSolveBlock) void k_besselk(const double* __restrict__ nu,
+                                                         const double* __restrict__ x,
+                                                         double* __restrict__ out, int64_t n, int result,
+                                                         double L, double Lq, const RuleTable* __restrict__ Rp,
+                                                         unsigned long long* __restrict__ stats)
+{
+    __shared__ unsigned int hist[64];
+    __shared__ double s_d[8][kSolveBlock];
+    __shared__ int s_i[3][kSolveBlock];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kSolveBlock + tid;
+    double v = 0.0, z = 1.0;
+    bool work = false;
+    if (i < n) {
+        v = fabs(nu[i]);
+        z = x[i];
+        double r;
+        if (special_value(v, z, result, r)) out[i] = r;
+        else work = true;
+    }
+    int key = 0;
+    if (work && v * v > z) key = ((float)v * asinhf((float)(v / z)) > (float)L) ? 2 : 1;
+    // phase 1 -> 2: sort by regime
+    unsigned int slot = block_sort_slot<kSolveBlock>(work ? key : 3, hist);
+    s_d[0][slot] = v;
+    s_d[1][slot] = z;
+    s_i[0][slot] = work ? (int)(i - (int64_t)blockIdx.x * kSolveBlock) : -1;
+    __syncthreads();
+    const int li = s_i[0][tid];
+    const double v2 = s_d[0][tid], z2 = s_d[1][tid];
+    __syncthreads();
+    Solved sv;
+    sv.p.N = -1;
+    if (li >= 0) sv = plain_solve(v2, z2, L, Lq, *Rp);
+    // phase 2 -> 3: sort by node count
+    const int nkey = li < 0 ? 0 : (sv.p.N < 63 ? sv.p.N : 63);
+    slot = block_sort_slot<kSolveBlock>(nkey, hist);
+    s_d[0][slot] = v2;
+    s_d[1][slot] = z2;
+    s_d[2][slot] = sv.p.tref;
+    s_d[3][slot] = sv.p.t0;
+    s_d[4][slot] = sv.p.h;
+    s_d[5][slot] = sv.delta;
+    s_d[6][slot] = sv.A;
+    s_d[7][slot] = sv.B;
+    s_i[0][slot] = li;
+    s_i[1][slot] = sv.p.N;
+    s_i[2][slot] = sv.p.mc;
+    __syncthreads();
+    const int l3 = s_i[0][tid];
+    unsigned long long nodes = 0, ents = 0;
+    if (l3 >= 0) {
+        const double v3 = s_d[0][tid], z3 = s_d[1][tid];
+        Plan p;
+        p.tref = s_d[2][tid];
+        p.t0 = s_d[3][tid];
+        p.h = s_d[4][tid];
+        p.N = s_i[1][tid];
+        p.mc = s_i[2][tid];
+        const double A = s_d[6][tid], B = s_d[7][tid];
+        const double S = (MODE == BK_PLAIN_F64) ? sum_f64(v3, p, A, B) : sum_mixed(v3, p, A, B);
+        out[(int64_t)blockIdx.x * kSolveBlock + l3] = assemble(z3, s_d[5][tid], p.h * S, result);
+        nodes = (unsigned long long)(p.N + 1);
+        ents = 1;
+    }
+    if (stats) {
+        block_count_w(stats + BK_STAT_NODES, nodes, kSolveBlock / 64);
+        block_count_w(stats + BK_STAT_ENTRIES, ents, kSolveBlock / 64);
+    }
+}
+
+// The paper's refined algorithm (Alg. 2), one lane per entry, FP64: Temme's
+// series with the forward recurrence for x < 0.1, the fixed-window sum otherwise.
+__global__ __launch_bounds__(256) void k_besselk_paper(const double* __restrict__ nu, const double* __restrict__ x,
+                                                       double* __restrict__ out, int64_t n, int result, int bins,
+                                                       double T, const TemmeCoef* __restrict__ Cp,
+                                                       unsigned long long* __restrict__ stats)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long nodes = 0, ents = 0;
     if (i < n) {
-        double v = fabs(nu[i]), z = x[i], r;
+        const double v = fabs(nu[i]), z = x[i];
+        double r;
         if (!special_value(v, z, result, r)) {
-            Solved s = plain_solve(v, z, L, Lq, R);
-            double S = (MODE == BK_PLAIN_F64) ? sum_f64(v, s.p, s.A, s.B) : sum_mixed(v, s.p, s.A, s.B);
-            r = assemble(z, s.delta, s.p.h * S, result);
-            nodes = (unsigned long long)(s.p.N + 1);
-            ents = 1;
+            if (z < kPaperTemmeX) {
+                // K directly; written as exp(-z) exp(0) (e^z K) for the shared assembly
+                r = assemble(z, 0.0, temme_k(v, z, *Cp) * exp(z), result);
+            } else {
+                const FixedOut f = paper_fixed(v, z, bins, T);
+                // K = exp(g(t_lmax)) h S, written through Delta = g(t_lmax) + z so that
+                // the shared assembly (exp(-z) exp(Delta) h S) applies
+                r = assemble(z, f.gmax + z, f.hs, result);
+                nodes = (unsigned long long)(bins + 1);
+                ents = 1;
+            }
         }
         out[i] = r;
     }
     if (stats) {
-        block_count(stats + BK_STAT_NODES, nodes);
-        block_count(stats + BK_STAT_ENTRIES, ents);
+        block_count_w(stats + BK_STAT_NODES, nodes, 4);
+        block_count_w(stats + BK_STAT_ENTRIES, ents, 4);
     }
 }
 
@@ -117,7 +314,7 @@ __global__ __launch_bounds__(256) void k_window(const double* __restrict__ nu,
                                                 const double* __restrict__ x,
                                                 double* __restrict__ tlo, double* __restrict__ thi,
                                                 int32_t* __restrict__ nodes, int64_t n, double L,
-                                                double Lq, RuleTable R)
+                                                double Lq, const RuleTable* __restrict__ Rp)
 {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
@@ -126,7 +323,7 @@ __global__ __launch_bounds__(256) void k_window(const double* __restrict__ nu,
         tlo[i] = __builtin_nan(""); thi[i] = __builtin_nan(""); nodes[i] = 0;
         return;
     }
-    Solved s = plain_solve(v, z, L, Lq, R);
+    Solved s = plain_solve(v, z, L, Lq, *Rp);
     tlo[i] = s.p.t0;
     thi[i] = s.t1;
     nodes[i] = s.p.N;
@@ -172,7 +369,8 @@ __global__ __launch_bounds__(256) void k_matern(const double* __restrict__ lx,
                                                 const double* __restrict__ ly, TileGeom g,
                                                 int64_t tile_base, double sigma2, double inv_beta,
                                                 double nu, double pref, double L, double Lq,
-                                                RuleTable R, OutT* __restrict__ out)
+                                                const RuleTable* __restrict__ Rp, int bins, double T,
+                                                const TemmeCoef* __restrict__ Cp, OutT* __restrict__ out)
 {
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
     const int64_t p = tile_base + (int64_t)blockIdx.x / wg_per_tile;
@@ -200,9 +398,18 @@ __global__ __launch_bounds__(256) void k_matern(const double* __restrict__ lx,
             val = sigma2;
         } else {
             const double z = r * inv_beta;
-            Solved s = plain_solve(nu, z, L, Lq, R);
-            double S = (MODE == BK_PLAIN_F64) ? sum_f64(nu, s.p, s.A, s.B) : sum_mixed(nu, s.p, s.A, s.B);
-            val = sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * (s.p.h * S);
+            if (MODE == BK_PAPER_REFINED) {
+                if (z < kPaperTemmeX) {
+                    val = sigma2 * exp(pref + nu * log(z)) * temme_k(nu, z, *Cp);
+                } else {
+                    const FixedOut f = paper_fixed(nu, z, bins, T);
+                    val = sigma2 * exp(pref + nu * log(z) + f.gmax) * f.hs;
+                }
+            } else {
+                Solved s = plain_solve(nu, z, L, Lq, *Rp);
+                double S = (MODE == BK_PLAIN_F64) ? sum_f64(nu, s.p, s.A, s.B) : sum_mixed(nu, s.p, s.A, s.B);
+                val = sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * (s.p.h * S);
+            }
         }
         out[base + il + jl * mI] = (OutT)val;
     }
@@ -250,20 +457,31 @@ extern "C" int bk_besselk_ex(const double* nu, const double* x, double* out, int
     if (prm->L_window < 0.0 || prm->L_quad < 0.0) return BK_EINVAL;
     double L, Lq;
     resolve_thresholds(prm->mode, prm->L_window, prm->L_quad, &L, &Lq);
-    const int64_t blocks = (n + 255) / 256;
+    const int64_t blocks = (n + kSolveBlock - 1) / kSolveBlock;
     if (blocks > 0x7fffffffLL) return BK_EINVAL;
-    const RuleTable& R = rule_table();
+    const RuleTable* R = rule_table_dev();
+    if (!R) return BK_EHIP;
     switch (prm->mode) {
     case BK_PLAIN_F64:
-        hipLaunchKernelGGL(k_besselk<BK_PLAIN_F64>, dim3((unsigned)blocks), dim3(256), 0, stream,
+        hipLaunchKernelGGL(k_besselk<BK_PLAIN_F64>, dim3((unsigned)blocks), dim3(kSolveBlock), 0, stream,
                            nu, x, out, n, prm->result, L, Lq, R, prm->stats);
         return launch_status();
     case BK_MIXED_F32C:
-        hipLaunchKernelGGL(k_besselk<BK_MIXED_F32C>, dim3((unsigned)blocks), dim3(256), 0, stream,
+        hipLaunchKernelGGL(k_besselk<BK_MIXED_F32C>, dim3((unsigned)blocks), dim3(kSolveBlock), 0, stream,
                            nu, x, out, n, prm->result, L, Lq, R, prm->stats);
         return launch_status();
     case BK_LEARNED:
         return bk_besselk_learned(nu, x, out, n, prm, L, Lq, stream);
+    case BK_PAPER_REFINED: {
+        if (prm->bins < 0 || prm->bins > 100000 || prm->t_upper < 0.0) return BK_EINVAL;
+        const TemmeCoef* Cp = temme_coef_dev();
+        if (!Cp) return BK_EHIP;
+        const int64_t b256 = (n + 255) / 256;
+        hipLaunchKernelGGL(k_besselk_paper, dim3((unsigned)b256), dim3(256), 0, stream, nu, x, out, n, prm->result,
+                           prm->bins > 0 ? prm->bins : kPaperBins, prm->t_upper > 0.0 ? prm->t_upper : kPaperT, Cp,
+                           prm->stats);
+        return launch_status();
+    }
     default:
         return BK_EINVAL;
     }
@@ -279,8 +497,10 @@ extern "C" int bk_window(const double* nu, const double* x, double* t_lo, double
     resolve_thresholds(BK_MIXED_F32C, L_window, L_quad, &L, &Lq);
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7fffffffLL) return BK_EINVAL;
+    const RuleTable* R = rule_table_dev();
+    if (!R) return BK_EHIP;
     hipLaunchKernelGGL(k_window, dim3((unsigned)blocks), dim3(256), 0, stream, nu, x, t_lo, t_hi, nodes,
-                       n, L, Lq, rule_table());
+                       n, L, Lq, R);
     return launch_status();
 }
 
@@ -311,12 +531,15 @@ static int launch_matern(const bk_locs* locs, const bk_params* prm, const TileGe
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
     const int64_t max_wg = 1LL << 23;                      // keeps a launch below 2^31 work-items
     const int64_t tiles_per_launch = max_wg / wg_per_tile > 0 ? max_wg / wg_per_tile : 1;
-    const RuleTable& R = rule_table();
+    const RuleTable* R = rule_table_dev();
+    const TemmeCoef* Cp = temme_coef_dev();
+    if (!R || !Cp) return BK_EHIP;
     for (int64_t t0 = 0; t0 < ntiles; t0 += tiles_per_launch) {
         int64_t nt = ntiles - t0 < tiles_per_launch ? ntiles - t0 : tiles_per_launch;
         hipLaunchKernelGGL((k_matern<MODE, OutT>), dim3((unsigned)(nt * wg_per_tile)), dim3(256), 0, stream,
                            locs->x, locs->y, g, t0, prm->sigma2, 1.0 / prm->beta, nu, pref, L, Lq, R,
-                           (OutT*)out);
+                           prm->bins > 0 ? prm->bins : kPaperBins, prm->t_upper > 0.0 ? prm->t_upper : kPaperT,
+                           Cp, (OutT*)out);
         int st = launch_status();
         if (st != BK_OK) return st;
     }
@@ -354,6 +577,10 @@ extern "C" int bk_matern_tiles(const bk_locs* locs, const bk_params* prm, int32_
                    : launch_matern<BK_MIXED_F32C, double>(locs, prm, g, ntiles, L, Lq, out, stream);
     case BK_LEARNED:
         return bk_matern_learned(locs, prm, tile_size, lower_only, out, L, Lq, stream);
+    case BK_PAPER_REFINED:
+        if (prm->bins < 0 || prm->bins > 100000 || prm->t_upper < 0.0) return BK_EINVAL;
+        return f32 ? launch_matern<BK_PAPER_REFINED, float>(locs, prm, g, ntiles, L, Lq, out, stream)
+                   : launch_matern<BK_PAPER_REFINED, double>(locs, prm, g, ntiles, L, Lq, out, stream);
     default:
         return BK_EINVAL;
     }

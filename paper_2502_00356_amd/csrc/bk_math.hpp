@@ -298,4 +298,125 @@ __device__ inline double sum_mixed(double nu, const Plan& p, double A, double B)
     return (double)s - (double)c - 0.5 * (double)ends;
 }
 
+// ---------------------------------------------------------------------------
+// The paper's refined algorithm, integral branch (Sec. IV-C, Alg. 2): fixed
+// window [0, T], b bins, nodes t_m = m h (h = T / b), weights 1/2 at both ends,
+// scaled by the largest node value g(t_lmax). Since g is unimodal on t >= 0,
+// the largest node is found by bisection on the sign of g(t_{m+1}) - g(t_m)
+// (about log2(b) + 1 pairs of evaluations) instead of a pass over all nodes.
+// Each node evaluates g directly in FP64.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double g_direct(double nu, double x, double t)
+{
+    double ch, sh;
+    cosh_sinh(t, ch, sh);
+    return nu * t + log1p(exp(-2.0 * nu * t)) - kLn2 - x * ch;
+}
+
+struct FixedOut {
+    double gmax;   // g(t_lmax)
+    double hs;     // h * sum_m c_m exp(g(t_m) - g(t_lmax))
+};
+
+__device__ inline FixedOut paper_fixed(double nu, double x, int bins, double T)
+{
+    const double h = T / (double)bins;
+    int lo = 0, hi = bins;            // the largest node lies in [lo, hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (g_direct(nu, x, (double)(mid + 1) * h) > g_direct(nu, x, (double)mid * h)) lo = mid + 1;
+        else hi = mid;
+    }
+    const double glo = g_direct(nu, x, (double)lo * h), ghi = g_direct(nu, x, (double)hi * h);
+    FixedOut o;
+    o.gmax = fmax(glo, ghi);
+    double S = 0.0;
+    for (int m = 0; m <= bins; ++m) {
+        const double c = (m == 0 || m == bins) ? 0.5 : 1.0;
+        S += c * exp(g_direct(nu, x, (double)m * h) - o.gmax);
+    }
+    o.hs = h * S;
+    return o;
+}
+
+// ---------------------------------------------------------------------------
+// Temme's series for small x (Sec. IV-A, Eqs. "temme_main", "temme_initpq",
+// "temme_initf") with Campbell's forward recurrence (Eq. "recurrence"), the
+// paper's branch for x < 0.1 (Alg. 2). With nu = mu + M, M = floor(nu + 1/2),
+// mu in [-1/2, 1/2):
+//   K_mu = sum_k c_k f_k,  K_{mu+1} = (2/x) sum_k c_k h_k,  c_k = (x^2/4)^k / k!,
+//   h_k = p_k - k f_k,  p_k = p_{k-1} / (k - mu),  q_k = q_{k-1} / (k + mu),
+//   f_k = (k f_{k-1} + p_{k-1} + q_{k-1}) / (k^2 - mu^2),
+//   p_0 = (x/2)^-mu Gamma(1+mu) / 2,  q_0 = (x/2)^mu Gamma(1-mu) / 2,
+//   f_0 = (mu pi / sin(mu pi)) (cosh(s) Gamma1 + sinh(s)/s ln(2/x) Gamma2),
+//   s = mu ln(2/x), Gamma1 = (1/Gamma(1-mu) - 1/Gamma(1+mu)) / (2 mu),
+//   Gamma2 = (1/Gamma(1-mu) + 1/Gamma(1+mu)) / 2,
+// then K_{eta+1} = (2 eta / x) K_eta + K_{eta-1} up to nu. Gamma1 and Gamma2 are
+// even entire functions of mu; they are evaluated from Chebyshev coefficients in
+// 8 mu^2 - 1, computed once on the host in long double. The series stops when a
+// term falls below 2^-53 of the sum (the paper caps it at 15000 terms).
+// ---------------------------------------------------------------------------
+constexpr int kTemmeCheb = 14;
+
+struct TemmeCoef {
+    double g1[kTemmeCheb];
+    double g2[kTemmeCheb];
+};
+
+__device__ __forceinline__ double cheb_eval(const double* c, double u)
+{
+    double b1 = 0.0, b2 = 0.0;
+    for (int j = kTemmeCheb - 1; j >= 1; --j) {
+        const double t = fma(2.0 * u, b1, c[j] - b2);
+        b2 = b1;
+        b1 = t;
+    }
+    return fma(u, b1, c[0] - b2);
+}
+
+// K_nu(x) for 0 < x (intended for x < 0.1, where the series converges in a few
+// terms); returns K (not scaled).
+__device__ inline double temme_k(double nu, double x, const TemmeCoef& C)
+{
+    const double M = floor(nu + 0.5);
+    const double mu = nu - M;
+    const double u = 8.0 * mu * mu - 1.0;
+    const double G1 = cheb_eval(C.g1, u), G2 = cheb_eval(C.g2, u);
+    const double rgp = G2 - mu * G1;                   // 1 / Gamma(1 + mu)
+    const double rgm = G2 + mu * G1;                   // 1 / Gamma(1 - mu)
+    const double lx = log(2.0 / x);
+    const double sg = mu * lx;
+    const double pimu = 3.14159265358979323846 * mu;
+    const double fact = fabs(pimu) < 1e-8 ? 1.0 + pimu * pimu / 6.0 : pimu / sin(pimu);
+    const double esg = exp(sg);
+    const double chs = 0.5 * (esg + 1.0 / esg);
+    const double shs_s = fabs(sg) < 1e-4 ? 1.0 + sg * sg / 6.0 : 0.5 * (esg - 1.0 / esg) / sg;
+    double f = fact * (G1 * chs + G2 * shs_s * lx);
+    double p = 0.5 * esg / rgp;                        // (x/2)^-mu Gamma(1+mu) / 2
+    double q = 0.5 / (esg * rgm);                      // (x/2)^mu Gamma(1-mu) / 2
+    const double d = 0.25 * x * x;
+    double c = 1.0, sum = f, sum1 = p;
+    for (int k = 1; k < 200; ++k) {
+        const double kk = (double)k;
+        f = (kk * f + p + q) / (kk * kk - mu * mu);
+        c *= d / kk;
+        p /= (kk - mu);
+        q /= (kk + mu);
+        const double del = c * f;
+        sum += del;
+        sum1 += c * (p - kk * f);
+        if (fabs(del) < 1.1102230246251565e-16 * fabs(sum)) break;
+    }
+    double km = sum;                                   // K_mu
+    double kp = sum1 * 2.0 / x;                        // K_{mu+1}
+    // forward recurrence K_{eta+1} = (2 eta / x) K_eta + K_{eta-1}, eta = mu + 1, ..., nu - 1
+    for (int j = 1; j < (int)M; ++j) {
+        const double eta = mu + (double)j;
+        const double kn = fma(2.0 * eta / x, kp, km);
+        km = kp;
+        kp = kn;
+    }
+    return M >= 1.0 ? kp : km;
+}
+
 }  // namespace bk

@@ -1,8 +1,8 @@
 """Train the window-predicting MLP on the GPU and save it.
 
 Training set: 2^20 (nu, x) pairs, nu ~ U[0.01, 10], x log-uniform on [1e-4, 1e3]
-(seed 4); targets are the plain solver's windows at L = 16 and node counts for
-exp(-15.4) (bk_window). Training runs in the library's own kernels (forward /
+(seed 4); targets are the plain solver's windows at L = 15 and node counts for
+exp(-14.5) (bk_window). Training runs in the library's own kernels (forward /
 backward / Adam, bk_model_train); this script only marshals arguments.
 
 Usage: python -m paper_2502_00356_amd.train_window_mlp [--out PATH] [--n N] [--epochs E]

@@ -285,3 +285,42 @@ def test_adam_first_step_is_signed_lr(orc):
     m = {"a": np.zeros(3)}; v = {"a": np.zeros(3)}
     orc.adam_step(p, g, m, v, 1, lr=0.01, eps=0.0)
     assert np.allclose(p["a"], np.array([1.0, -2.0, 3.0]) - 0.01 * np.sign(g["a"]), rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- paper's fixed window and Alg. 1
+def test_fixed_window_sum_converges_to_k(orc):
+    """The fixed-window trapezoid sum tends to K_nu as the bins grow and the window
+    covers the integrand (pinned to mpmath's K_nu through the main oracle)."""
+    nu = np.array([0.3, 1.3, 4.7, 12.0]); x = np.array([0.2, 3.0, 40.0, 1.5])
+    k, _, _ = orc.besselk(nu, x)
+    s, _ = orc.fixed_window(nu, x, 8000, 16.0)
+    assert rel(s, k).max() < 1e-13
+    # with b = 1 the rule is h (f(0) + f(T)) / 2 exactly
+    s1, _ = orc.fixed_window(np.array([1.0]), np.array([2.0]), 1, 3.0)
+    f = lambda t: math.exp(-2.0 * math.cosh(t)) * math.cosh(t)
+    assert abs(s1[0] - 1.5 * (f(0.0) + f(3.0))) <= 1e-16
+
+
+def test_truncated_integral(orc):
+    """int_0^L grows with L and reaches K_nu; at L = 0 it vanishes (log -> -inf is
+    avoided by a tiny L) and small L matches the integrand times L."""
+    nu = np.array([2.5]); x = np.array([0.7])
+    vals = [orc.log_truncated(nu, x, L)[0] for L in (0.5, 1.0, 2.0, 4.0, 8.0, 16.0)]
+    assert all(b > a for a, b in zip(vals[:4], vals[1:4]))
+    assert all(b >= a for a, b in zip(vals, vals[1:]))
+    _, lk, _ = orc.besselk(nu, x)
+    assert abs(vals[-1] - lk[0]) < 1e-14
+    L = 1e-6
+    approx = math.log(L * math.exp(-0.7))          # f(0) = e^{-x}
+    assert abs(orc.log_truncated(nu, x, L)[0] - approx) < 1e-9
+
+
+def test_empirical_upper_bound_replay(orc):
+    """Alg. 1 replayed with the oracle as the reference: over x in [0.1, 140] (the
+    integral branch) and nu in (0, 20] the smallest bound reaching 1e-9 absolute in
+    log K is at most the paper's t1 = 9 (Sec. IV-C)."""
+    xs = np.geomspace(0.1, 140.0, 16)
+    nus = np.linspace(0.05, 20.0, 16)
+    L, err = orc.empirical_upper_bound(xs, nus, tol=1e-9)
+    print("replayed upper bound: %s (max abs error %.3g)" % (L, err))
+    assert L is not None and 5.0 <= L <= 9.0
