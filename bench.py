@@ -65,7 +65,8 @@ def parse():
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2502_00356_amd", "models", "window_mlp.bin"))
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="grid", choices=["grid", "matern-medium", "matern-large"],
+    ap.add_argument("--workload", default="grid", choices=["grid", "matern-medium", "matern-large", "deriv-grid",
+                                                           "matern-grad-medium"],
                     help="grid: the headline standalone workload; matern-*: tiled covariance generation")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device-to-device copy instead (HBM reference for counters)")
@@ -126,6 +127,9 @@ def main():
         copy_probe(torch)
         return
     from paper_2502_00356_amd import api, workloads
+    if a.workload in ("deriv-grid", "matern-grad-medium"):
+        deriv_bench(a, torch, api, workloads)
+        return
     if a.workload != "grid":
         matern_bench(a, torch, api, workloads)
         return
@@ -264,6 +268,67 @@ def matern_bench(a, torch, api, workloads):
                                      "out_dtype": str(tdt).replace("torch.", "")}
     line = {"metric": "Matern entries/s", "workload": a.workload, "n": n, "tile": ts, "entries": elems,
             "beta": beta, "results": res}
+    print(json.dumps(line), flush=True)
+
+
+def _event_ms(torch, fn, steps, warmup):
+    for _ in range(max(1, warmup)):
+        fn()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def deriv_bench(a, torch, api, workloads):
+    """Derivatives (one JSON line). deriv-grid: K, dK/dx, dK/dnu (e^x-scaled, FP64)
+    on the 2^24-pair grid, beside plain K alone. matern-grad-medium: Matern tiles
+    with dC/dbeta and dC/dnu for n = 40,000 uniform points (seed 3), beta = 0.05,
+    nu in {0.8, 2.3}, lower 960-tiles, FP64, beside the plain tiles alone."""
+    dev = torch.device("cuda:0")
+    res = {}
+    if a.workload == "deriv-grid":
+        nu_h, x_h, _ = workloads.grid_pairs(a.n, seed=2)
+        nu = torch.from_numpy(nu_h).to(dev)
+        x = torch.from_numpy(x_h).to(dev)
+        outs = {k: torch.empty_like(x) for k in ("k", "dx", "dnu")}
+        steps = max(1, a.steps)
+        ms = _event_ms(torch, lambda: api.besselk_deriv(nu, x, result=api.RESULT_SCALED, out=outs), steps, a.warmup)
+        ms_k = _event_ms(torch, lambda: api.besselk(nu, x, out=outs["k"], mode="plain", result=api.RESULT_SCALED),
+                         steps, a.warmup)
+        st = torch.zeros(api.STATS_LEN, dtype=torch.int64, device=dev)
+        api.besselk_deriv(nu, x, result=api.RESULT_SCALED, out=outs, stats=st)
+        torch.cuda.synchronize()
+        st = st.cpu().numpy()
+        res = {"deriv": {"ms": round(ms, 4), "evals_per_s": a.n / (ms * 1e-3),
+                         "nodes_per_entry": float(st[api.STAT_NODES]) / max(1, int(st[api.STAT_ENTRIES]))},
+               "plain_k": {"ms": round(ms_k, 4), "evals_per_s": a.n / (ms_k * 1e-3)},
+               "cost_ratio_vs_k": ms / ms_k}
+        line = {"metric": "K_nu with dK/dx and dK/dnu, evals/s", "workload": a.workload, "n": a.n,
+                "dtype": "f64", "results": res}
+    else:
+        c = workloads.MATERN_MEDIUM
+        xy = workloads.uniform_locations(c["n"], c["seed"])
+        n, ts, beta = xy.shape[0], c["tile"], c["beta"]
+        lx = torch.from_numpy(np.ascontiguousarray(xy[:, 0])).to(dev)
+        ly = torch.from_numpy(np.ascontiguousarray(xy[:, 1])).to(dev)
+        elems = api.matern_out_elems(n, ts, 1)
+        bufs = {k: torch.empty(elems, dtype=torch.float64, device=dev) for k in ("c", "dbeta", "dnu")}
+        steps = max(1, min(a.steps, 3))
+        for nu in c["nus"]:
+            ms = _event_ms(torch, lambda: api.matern_grad_tiles(lx, ly, 1.0, beta, nu, ts, 1, out=bufs), steps,
+                           a.warmup)
+            ms_c = _event_ms(torch, lambda: api.matern_tiles(lx, ly, 1.0, beta, nu, ts, 1, out=bufs["c"]), steps,
+                             a.warmup)
+            res["nu=%g" % nu] = {"ms": round(ms, 3), "entries_per_s": elems / (ms * 1e-3),
+                                 "write_gbps": 3 * 8 * elems / (ms * 1e-3) / 1e9,
+                                 "plain_tiles_ms": round(ms_c, 3), "cost_ratio_vs_tiles": ms / ms_c}
+        line = {"metric": "Matern entries/s with dC/dbeta and dC/dnu", "workload": a.workload, "n": n, "tile": ts,
+                "entries": elems, "beta": beta, "dtype": "f64", "results": res}
     print(json.dumps(line), flush=True)
 
 

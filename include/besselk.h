@@ -33,7 +33,8 @@ typedef enum {
     BK_EHIP = 2,     /* a HIP runtime call or kernel launch failed */
     BK_ENOMEM = 3,   /* workspace too small or allocation failed */
     BK_ENOMODEL = 4, /* BK_LEARNED without a trained model */
-    BK_EIO = 5       /* model file could not be read or written, or is malformed */
+    BK_EIO = 5,      /* model file could not be read or written, or is malformed */
+    BK_ENOTPD = 6    /* covariance matrix not positive definite (Cholesky failed) */
 } bk_status;
 
 /* Evaluation form.
@@ -171,6 +172,56 @@ int64_t bk_matern_tile_offset(int64_t n, int32_t tile_size, int32_t lower_only, 
  * L_window, L_quad >= 0 (0 selects 15 and 14.5). */
 int bk_window(const double* nu, const double* x, double* t_lo, double* t_hi, int32_t* nodes,
               int64_t n, double L_window, double L_quad, hipStream_t stream);
+
+/* K_nu(x) and its partial derivatives in x and nu, FP64 (plain solve), for n pairs.
+ * Defines (derivatives are the paper's future work, Sec. VI; both come from
+ * differentiating the integral of Sec. IV-B under the integral sign):
+ *   dK/dx  = -int_0^inf cosh t cosh(nu t) exp(-x cosh t) dt = -(K_{nu-1} + (nu/x) K_nu)
+ *   dK/dnu =  int_0^inf t sinh(nu t) exp(-x cosh t) dt  (sign of nu for nu < 0)
+ * nu, x : n doubles (device). k, dk_dx, dk_dnu : n doubles each (device) or NULL
+ * to skip that output (at least one must be given).
+ * params may be NULL (defaults); otherwise mode must be BK_PLAIN_F64, result
+ * BK_RESULT_K or BK_RESULT_SCALED (all three outputs multiplied by e^x), and
+ * L_window, L_quad, stats are honoured. Special values: x == 0 gives +inf, -inf
+ * and +-inf (0 for nu == 0); x == +inf gives 0, -0, 0; NaN or x < 0 gives NaN. */
+int bk_besselk_deriv(const double* nu, const double* x, double* k, double* dk_dx, double* dk_dnu,
+                     int64_t n, const bk_params* params, hipStream_t stream);
+
+/* Matern covariance tiles and their partial derivatives in beta and nu (the
+ * Sec. III-A formula differentiated; inputs of gradient-based likelihood
+ * maximisation). With z = r / beta and c = 2^(1-nu) / Gamma(nu):
+ *   C        = sigma2 c z^nu K_nu(z)
+ *   dC/dbeta = sigma2 c z^(nu+1) K_{nu-1}(z) / beta
+ *   dC/dnu   = C (ln z - ln 2 - psi(nu)) + sigma2 c z^nu dK_nu/dnu(z)
+ * and C = sigma2, dC/dbeta = dC/dnu = 0 at r == 0 (dC/dsigma2 is C / sigma2).
+ * Same tiling, layout and element type (params->out_dtype) as bk_matern_tiles;
+ * params->mode must be BK_PLAIN_F64. c, dc_dbeta, dc_dnu : device buffers of
+ * bk_matern_out_elems(...) elements each, or NULL to skip (at least one given). */
+int bk_matern_grad_tiles(const bk_locs* locs, const bk_params* params, int32_t tile_size, int32_t lower_only,
+                         void* c, void* dc_dbeta, void* dc_dnu, hipStream_t stream);
+
+/* Gaussian log-likelihood of observations z (n doubles, device) at the locations
+ * under the Matern covariance Sigma of bk_matern_tiles (Sec. III-A; the matrix the
+ * paper generates is the covariance of this likelihood):
+ *   l = -1/2 z^T Sigma^-1 z - 1/2 log det Sigma - n/2 log(2 pi),
+ * by Sigma = L L^T (rocSOLVER potrf) and a = Sigma^-1 z (potrs). With with_grad != 0
+ * also the gradient, from bk_matern_grad_tiles and Sigma^-1 (potri):
+ *   dl/dtheta = 1/2 a^T (dSigma/dtheta) a - 1/2 tr(Sigma^-1 dSigma/dtheta),
+ * theta = (sigma2, beta, nu); dSigma/dsigma2 = Sigma / sigma2.
+ * result : HOST array, result[0] = l and, with the gradient, result[1..3] =
+ *          dl/dsigma2, dl/dbeta, dl/dnu.
+ * params : sigma2 > 0, beta > 0, nu > 0; mode selects the form that builds Sigma
+ *          (BK_LEARNED needs a model); the gradient needs BK_PLAIN_F64.
+ * workspace : device scratch of bk_matern_loglik_workspace_bytes(n, with_grad)
+ *          bytes (the n x n matrices: 8 n^2 bytes each, three with the gradient).
+ * 1 <= n <= 46340. Synchronises the stream (the results are host values).
+ * Returns BK_ENOTPD if the Cholesky factorisation fails. Calls on one device are
+ * serialised (one rocBLAS handle per device, kept for the life of the process). */
+int bk_matern_loglik(const bk_locs* locs, const double* z, const bk_params* params, int32_t with_grad,
+                     double* result, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Workspace bytes bk_matern_loglik needs (0 if n is out of range). */
+size_t bk_matern_loglik_workspace_bytes(int64_t n, int32_t with_grad);
 
 /* ---------------------------------------------------------------------------
  * Window-predicting MLP (2 -> 64 -> 64 -> 3, ReLU).

@@ -10,6 +10,12 @@ Contents
                             Gauss-Kronrod in long double (besselk_oracle.c)
   matern_entries(...)       selected Matern entries, same quadrature
   matern_full(...)          a whole small matrix
+  besselk_deriv(nu, x)      dK/dx and dK/dnu, the integrals differentiated under
+                            the integral sign, same quadrature
+  matern_grad_entries(...)  Matern entries with their beta and nu derivatives
+  digamma(v)                psi(v) in long double
+  matern_loglik(...)        Gaussian log-likelihood of observations under the
+                            Matern covariance, and its gradient (numpy / scipy)
   window(nu, x, L)          t_max, g(t_max), [t0, t1] by bisection
   node_count(...)           node-count rule for a per-entry window
   mlp_*                     numpy float64 forward / loss / backward / Adam
@@ -48,6 +54,13 @@ def _load():
         lib.oracle_log_truncated.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_double, _P]
         lib.oracle_logintegrand.restype = None
         lib.oracle_logintegrand.argtypes = [_P, _P, _P, _P, ctypes.c_int64]
+        lib.oracle_besselk_deriv.restype = ctypes.c_int64
+        lib.oracle_besselk_deriv.argtypes = [_P, _P, ctypes.c_int64, _P, _P, _P, _P]
+        lib.oracle_digamma.restype = None
+        lib.oracle_digamma.argtypes = [_P, _P, ctypes.c_int64]
+        lib.oracle_matern_grad.restype = ctypes.c_int64
+        lib.oracle_matern_grad.argtypes = [_P, _P, _P, _P, _PI64, _PI64, ctypes.c_int64,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P, _P]
         _lib = lib
     return _lib
 
@@ -74,6 +87,97 @@ def besselk(nu, x):
     if bad:
         raise RuntimeError("oracle quadrature did not converge on %d entries" % bad)
     return k, lk, ks
+
+
+def besselk_deriv(nu, x):
+    """Partial derivatives of K_nu(x), by differentiating the integral of Sec. IV-B
+    under the integral sign (derivatives are the paper's future work, Sec. VI):
+        dK/dx  = -int_0^inf cosh t exp(-x cosh t) cosh(nu t) dt
+        dK/dnu =  int_0^inf t sinh(nu t) exp(-x cosh t) dt      (sign of nu for nu < 0)
+    Returns a dict of float64 arrays, for x > 0:
+      dx, dnu        the derivatives
+      log_mdx        log(-dK/dx);       log_dnu   log|dK/dnu|
+      scaled_dx      e^x dK/dx;         scaled_dnu e^x dK/dnu  (exponentiated in long double)"""
+    nu, x = (a.ravel() for a in np.broadcast_arrays(_d(nu), _d(x)))
+    nu, x = _d(nu), _d(x)
+    lmdx, ldnu, smdx, sdnu = (np.empty(x.size) for _ in range(4))
+    bad = _load().oracle_besselk_deriv(_ptr(nu), _ptr(x), x.size, _ptr(lmdx), _ptr(ldnu), _ptr(smdx), _ptr(sdnu))
+    if bad:
+        raise RuntimeError("oracle quadrature did not converge on %d entries" % bad)
+    sg = np.sign(nu)
+    return {"dx": -np.exp(lmdx), "dnu": sg * np.exp(ldnu), "log_mdx": lmdx, "log_dnu": ldnu,
+            "scaled_dx": -smdx, "scaled_dnu": sg * sdnu}
+
+
+def digamma(v):
+    """psi(v) = Gamma'(v) / Gamma(v) for v > 0, long double."""
+    v = _d(v).ravel()
+    out = np.empty(v.size)
+    _load().oracle_digamma(_ptr(v), _ptr(out), v.size)
+    return out
+
+
+def matern_grad_entries(row_xy, col_xy, ri, ci, sigma2, beta, nu):
+    """Matern entries M (Sec. III-A) and dM/dbeta, dM/dnu at entries (ri[e], ci[e]).
+    Returns (M, dM/dbeta, dM/dnu)."""
+    rx, ry = _d(row_xy[:, 0]), _d(row_xy[:, 1])
+    cx, cy = _d(col_xy[:, 0]), _d(col_xy[:, 1])
+    ri = np.ascontiguousarray(ri, dtype=np.int64)
+    ci = np.ascontiguousarray(ci, dtype=np.int64)
+    m, db, dn = np.empty(ri.size), np.empty(ri.size), np.empty(ri.size)
+    bad = _load().oracle_matern_grad(_ptr(rx), _ptr(ry), _ptr(cx), _ptr(cy),
+                                     ri.ctypes.data_as(_PI64), ci.ctypes.data_as(_PI64), ri.size,
+                                     float(sigma2), float(beta), float(nu), _ptr(m), _ptr(db), _ptr(dn))
+    if bad:
+        raise RuntimeError("oracle quadrature did not converge on %d entries" % bad)
+    return m, db, dn
+
+
+def matern_full_grad(xy, sigma2, beta, nu):
+    """Whole n x n Matern matrix and its beta and nu derivative matrices."""
+    n = xy.shape[0]
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    m, db, dn = matern_grad_entries(xy, xy, ii.ravel(), jj.ravel(), sigma2, beta, nu)
+    return m.reshape(n, n), db.reshape(n, n), dn.reshape(n, n)
+
+
+def matern_loglik(xy, z, sigma2, beta, nu, grad=False, details=False):
+    """Gaussian log-likelihood of observations z (n) at locations xy (n x 2) under
+    the Matern covariance Sigma (Sec. III-A; the likelihood the paper maximises):
+        l = -1/2 z^T Sigma^-1 z - 1/2 log det Sigma - n/2 log(2 pi),
+    by a Cholesky factorisation Sigma = L L^T (log det Sigma = 2 sum log L_ii).
+    With grad=True also returns (dl/dsigma2, dl/dbeta, dl/dnu) from
+        dl/dtheta = 1/2 a^T (dSigma/dtheta) a - 1/2 tr(Sigma^-1 dSigma/dtheta),
+    a = Sigma^-1 z, and dSigma/dsigma2 = Sigma / sigma2. details=True returns a dict
+    with the parts (quad, logdet, cond, and per parameter the two gradient terms)."""
+    import scipy.linalg as sl
+    z = np.asarray(z, np.float64)
+    n = z.size
+    if grad:
+        S, dB, dN = matern_full_grad(xy, sigma2, beta, nu)
+    else:
+        S = matern_full(xy, sigma2, beta, nu)
+    L = np.linalg.cholesky(S)
+    w = sl.solve_triangular(L, z, lower=True)
+    quad = float(w @ w)
+    logdet = 2.0 * float(np.sum(np.log(np.diag(L))))
+    ll = -0.5 * quad - 0.5 * logdet - 0.5 * n * math.log(2.0 * math.pi)
+    info = {"ll": ll, "quad": quad, "logdet": logdet}
+    if details:
+        info["cond"] = float(np.linalg.cond(S))
+    if not grad:
+        return info if details else ll
+    a = sl.cho_solve((L, True), z)
+    Sinv = sl.cho_solve((L, True), np.eye(n))
+    g, t1, t2 = [], [], []
+    for dS in (S / sigma2, dB, dN):
+        t1.append(0.5 * float(a @ dS @ a))
+        t2.append(0.5 * float(np.sum(Sinv * dS)))
+        g.append(t1[-1] - t2[-1])
+    if details:
+        info.update(grad=np.array(g), t_quad=np.array(t1), t_trace=np.array(t2))
+        return info
+    return ll, np.array(g)
 
 
 def fixed_window(nu, x, bins=40, T=9.0):

@@ -21,6 +21,13 @@
  *
  * A second, separate routine reproduces the integration window of Sec. IV-B
  * ({t : g(t) >= g(t_max) - L}) by bisection, for checking the GPU window export.
+ *
+ * Derivatives (the paper lists them as future work, Sec. VI) are the integrals
+ * obtained by differentiating under the integral sign:
+ *   dK/dx  = -int_0^inf cosh t exp(-x cosh t) cosh(nu t) dt
+ *   dK/dnu =  int_0^inf t sinh(nu t) exp(-x cosh t) dt
+ * evaluated by the same adaptive rule; and the gradient of the Matern covariance
+ * in (beta, nu) written out with the chain rule.
  */
 #include <math.h>
 #include <stdint.h>
@@ -63,7 +70,17 @@ static long double orc_tmax(long double nu, long double x)
     return 0.5L * (a + b);
 }
 
-typedef struct { long double nu, x, that, lcref; } orc_integrand;
+/* Integrand kinds: 0 is the K integrand exp(g(t)); 1 multiplies it by cosh t
+ * (-dK/dx); 2 by t tanh(nu t), so that the product is t sinh(nu t) exp(-x cosh t)
+ * (dK/dnu). log of the extra factor: */
+static long double orc_lfac(int kind, long double nu, long double t)
+{
+    if (kind == 1) return orc_logcosh(t);
+    if (kind == 2) return logl(t) + logl(tanhl(nu * t));
+    return 0.0L;
+}
+
+typedef struct { long double nu, x, that, lcref; int kind; long double lfref; } orc_integrand;
 
 /* exp(g(t) - g(t_hat)). The difference is formed without cancellation:
  *   log cosh(nu t) - log cosh(nu t_hat) - 2 x sinh((t + t_hat)/2) sinh((t - t_hat)/2),
@@ -74,6 +91,7 @@ static long double orc_phi(const orc_integrand* f, long double t)
 {
     long double d = orc_logcosh(f->nu * t) - f->lcref
                     - 2.0L * f->x * sinhl(0.5L * (t + f->that)) * sinhl(0.5L * (t - f->that));
+    if (f->kind != 0) d += orc_lfac(f->kind, f->nu, t) - f->lfref;
     return expl(d);
 }
 
@@ -133,6 +151,7 @@ static long double orc_logk(long double nu, long double x, orc_seg* seg, int* ok
     nu = fabsl(nu);
     orc_integrand f;
     f.nu = nu; f.x = x;
+    f.kind = 0; f.lfref = 0.0L;
     long double th = orc_tmax(nu, x);
     f.that = th;
     f.lcref = orc_logcosh(nu * th);
@@ -277,6 +296,7 @@ int64_t oracle_log_truncated(const double* nu, const double* x, int64_t n, doubl
             long double v = fabsl((long double)nu[i]), z = (long double)x[i], Lt = (long double)L;
             orc_integrand f;
             f.nu = v; f.x = z;
+            f.kind = 0; f.lfref = 0.0L;
             long double th = orc_tmax(v, z);
             if (th > Lt) th = Lt;
             f.that = th;
@@ -327,4 +347,142 @@ void oracle_logintegrand(const double* nu, const double* x, const double* t, dou
 {
     for (int64_t i = 0; i < n; ++i)
         out[i] = (double)orc_g(fabsl((long double)nu[i]), (long double)x[i], (long double)t[i]);
+}
+
+/* Maximiser over t >= 0 of the log of a derivative integrand (kinds 1 and 2),
+ * g(t) + log F(t). Both are unimodal: for kind 1 the slope is
+ * nu tanh(nu t) + tanh t - x sinh t, and (nu tanh(nu t) + tanh t) / sinh t
+ * decreases; kind 2 is log-concave (log t, log sinh(nu t) and -x cosh t all
+ * are). At the maximiser x sinh t equals nu tanh(nu t) + tanh t < nu + 1
+ * (kind 1), or 1/t + nu coth(nu t) <= 2/t + nu (kind 2), so it lies below
+ * asinh((nu + 2)/x) + 1; golden-section search on [0, that bound]. */
+static long double orc_targmax(int kind, long double nu, long double x)
+{
+    const long double ginv = 0.618033988749894848204586834365638118L;
+    long double a = 0.0L, b = asinhl((nu + 2.0L) / x) + 1.0L;
+    long double c = b - ginv * (b - a), d = a + ginv * (b - a);
+    long double gc = orc_g(nu, x, c) + orc_lfac(kind, nu, c);
+    long double gd = orc_g(nu, x, d) + orc_lfac(kind, nu, d);
+    for (int it = 0; it < 300 && (b - a) > 1e-16L * b; ++it) {
+        if (gc > gd) { b = d; d = c; gd = gc; c = b - ginv * (b - a); gc = orc_g(nu, x, c) + orc_lfac(kind, nu, c); }
+        else         { a = c; c = d; gc = gd; d = a + ginv * (b - a); gd = orc_g(nu, x, d) + orc_lfac(kind, nu, d); }
+    }
+    return 0.5L * (a + b);
+}
+
+/* log of int_0^inf exp(-x cosh t) cosh(nu t) F(t) dt for kind 1 or 2 (nu >= 0,
+ * x > 0; kind 2 needs nu > 0), by the adaptive rule of orc_logk around the
+ * integrand's own maximiser. */
+static long double orc_logderiv(int kind, long double nu, long double x, orc_seg* seg, int* ok)
+{
+    orc_integrand f;
+    f.nu = nu; f.x = x; f.kind = kind;
+    const long double th = orc_targmax(kind, nu, x);
+    f.that = th;
+    f.lcref = orc_logcosh(nu * th);
+    f.lfref = orc_lfac(kind, nu, th);
+    const long double lref = orc_g(nu, x, th) + f.lfref;
+    long double step = 1.0L, T = th + step;
+    while (logl(orc_phi(&f, T)) > -64.0L && step < 1e4L) { step *= 2.0L; T = th + step; }
+    const long double tol = 1e-17L;
+    long double I = 0.0L;
+    if (th > 0.0L) I += orc_adapt(&f, 0.0L, th, tol, seg, ok);
+    I += orc_adapt(&f, th, T, tol, seg, ok);
+    return lref + logl(I);
+}
+
+/* Exported: partial derivatives of K_nu(x) for n pairs (x > 0):
+ *   lmdx[i] = log(-dK/dx),  ldnu[i] = log|dK/dnu|  (-inf at nu == 0)
+ *   smdx[i] = -e^x dK/dx,   sdnu[i] = e^x |dK/dnu|  (formed in long double)
+ * dK/dx < 0 always; dK/dnu has the sign of nu (K is even in nu). Entries with
+ * x <= 0 or NaN inputs give NaN. Returns the count of non-converged entries. */
+int64_t oracle_besselk_deriv(const double* nu, const double* x, int64_t n, double* lmdx, double* ldnu,
+                             double* smdx, double* sdnu)
+{
+    int64_t bad = 0;
+#pragma omp parallel reduction(+ : bad)
+    {
+        orc_seg* seg = (orc_seg*)malloc(sizeof(orc_seg) * ORC_MAXSUB);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i) {
+            const long double v = fabsl((long double)nu[i]), z = (long double)x[i];
+            if (isnan(nu[i]) || isnan(x[i]) || !(x[i] > 0.0)) {
+                lmdx[i] = ldnu[i] = smdx[i] = sdnu[i] = NAN;
+                continue;
+            }
+            int ok = 1;
+            const long double a = orc_logderiv(1, v, z, seg, &ok);
+            const long double b = v == 0.0L ? -INFINITY : orc_logderiv(2, v, z, seg, &ok);
+            if (!ok) ++bad;
+            lmdx[i] = (double)a;
+            ldnu[i] = (double)b;
+            smdx[i] = (double)expl(a + z);
+            sdnu[i] = (double)expl(b + z);
+        }
+        free(seg);
+    }
+    return bad;
+}
+
+/* Digamma psi(v) for v > 0 in long double: psi(v) = psi(v + 1) - 1/v up to
+ * v >= 20, then the asymptotic series
+ *   psi(v) ~ ln v - 1/(2v) - sum_k B_2k / (2k v^2k)
+ * through B_14 (Abramowitz & Stegun 6.3.18). */
+static long double orc_digamma(long double v)
+{
+    long double acc = 0.0L;
+    while (v < 20.0L) { acc -= 1.0L / v; v += 1.0L; }
+    const long double r = 1.0L / (v * v);
+    const long double ser =
+        r * (1.0L / 12 - r * (1.0L / 120 - r * (1.0L / 252 - r * (1.0L / 240 - r * (1.0L / 132
+        - r * (691.0L / 32760 - r * (1.0L / 12)))))));
+    return acc + logl(v) - 0.5L / v - ser;
+}
+
+/* Exported: digamma for tests. */
+void oracle_digamma(const double* v, double* out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = (double)orc_digamma((long double)v[i]);
+}
+
+/* Exported: Matern covariance entries and their partial derivatives in beta and
+ * nu (Sec. III-A formula, differentiated). With z = r / beta and
+ * M = sigma2 2^(1-nu) / Gamma(nu) z^nu K_nu(z):
+ *   dM/dbeta = (dM/dz)(-z / beta), and d/dz [z^nu K_nu(z)] = -z^nu K_{nu-1}(z)
+ *              (DLMF 10.29.4), so dM/dbeta = sigma2 2^(1-nu)/Gamma(nu) z^(nu+1) K_{nu-1}(z) / beta;
+ *   dM/dnu   = M (ln z - ln 2 - psi(nu)) + sigma2 2^(1-nu)/Gamma(nu) z^nu dK_nu/dnu(z).
+ * K_{nu-1} = K_{|nu-1|} comes from the K integral, dK/dnu from the kind-2
+ * integral. An exact zero distance gives M = sigma2 and zero derivatives.
+ * Returns the count of non-converged quadratures. */
+int64_t oracle_matern_grad(const double* rx, const double* ry, const double* cx, const double* cy,
+                           const int64_t* ri, const int64_t* ci, int64_t n_entries,
+                           double sigma2, double beta, double nu, double* m, double* dbeta, double* dnu)
+{
+    int64_t bad = 0;
+    const long double lnu = (long double)nu, lb = (long double)beta, s2 = (long double)sigma2;
+    const long double pre = (1.0L - lnu) * ORC_LN2 - lgammal(lnu);
+    const long double psi = orc_digamma(lnu);
+#pragma omp parallel reduction(+ : bad)
+    {
+        orc_seg* seg = (orc_seg*)malloc(sizeof(orc_seg) * ORC_MAXSUB);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t e = 0; e < n_entries; ++e) {
+            long double dx = (long double)cx[ci[e]] - (long double)rx[ri[e]];
+            long double dy = (long double)cy[ci[e]] - (long double)ry[ri[e]];
+            long double r = sqrtl(dx * dx + dy * dy);
+            if (r == 0.0L) { m[e] = sigma2; dbeta[e] = 0.0; dnu[e] = 0.0; continue; }
+            const long double z = r / lb, lz = logl(z);
+            int ok = 1;
+            const long double lk = orc_logk(lnu, z, seg, &ok);
+            const long double lk1 = orc_logk(fabsl(lnu - 1.0L), z, seg, &ok);
+            const long double ld = orc_logderiv(2, lnu, z, seg, &ok);
+            if (!ok) ++bad;
+            const long double mv = s2 * expl(pre + lnu * lz + lk);
+            m[e] = (double)mv;
+            dbeta[e] = (double)(s2 / lb * expl(pre + (lnu + 1.0L) * lz + lk1));
+            dnu[e] = (double)(mv * (lz - ORC_LN2 - psi) + s2 * expl(pre + lnu * lz + ld));
+        }
+        free(seg);
+    }
+    return bad;
 }

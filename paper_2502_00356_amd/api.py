@@ -67,6 +67,12 @@ _matern = _sig("bk_matern_tiles", ctypes.c_int, [ctypes.POINTER(Locs), ctypes.PO
 _out_elems = _sig("bk_matern_out_elems", _i64, [_i64, _i32, _i32])
 _tile_off = _sig("bk_matern_tile_offset", _i64, [_i64, _i32, _i32, _i32, _i32])
 _window = _sig("bk_window", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _dbl, _dbl, _vp])
+_loglik = _sig("bk_matern_loglik", ctypes.c_int, [ctypes.POINTER(Locs), _vp, ctypes.POINTER(Params), _i32, _vp,
+                                                  _vp, ctypes.c_size_t, _vp])
+_loglik_ws = _sig("bk_matern_loglik_workspace_bytes", ctypes.c_size_t, [_i64, _i32])
+_deriv = _sig("bk_besselk_deriv", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(Params), _vp])
+_matern_grad = _sig("bk_matern_grad_tiles", ctypes.c_int, [ctypes.POINTER(Locs), ctypes.POINTER(Params), _i32, _i32,
+                                                           _vp, _vp, _vp, _vp])
 _m_create = _sig("bk_model_create", ctypes.c_int, [ctypes.POINTER(_vp)])
 _m_destroy = _sig("bk_model_destroy", None, [_vp])
 _m_load = _sig("bk_model_load", ctypes.c_int, [_vp, ctypes.c_char_p])
@@ -199,6 +205,81 @@ def matern_tiles(lx, ly, sigma2, beta, nu, tile_size, lower_only, mode="plain", 
     _check(_matern(ctypes.byref(locs), ctypes.byref(p), int(tile_size), int(lower_only), out.data_ptr(),
                    _stream(stream)))
     return out
+
+
+def besselk_deriv(nu, x, want=("k", "dx", "dnu"), result=RESULT_K, L_window=0.0, L_quad=0.0, stats=None,
+                  stream=None, out=None):
+    """K_nu(x), dK/dx and dK/dnu (bk_besselk_deriv) for device float64 tensors.
+    Returns a dict with the requested outputs among "k", "dx", "dnu"; out may give
+    preallocated tensors for them."""
+    n = x.numel()
+    if nu.numel() != n:
+        raise ValueError("nu and x differ in size")
+    if any(k not in ("k", "dx", "dnu") for k in want):
+        raise ValueError("unknown output")
+    outs = {k: (out[k] if out is not None and k in out else torch.empty_like(x)) for k in want}
+    for t in outs.values():
+        if t.numel() != n:
+            raise ValueError("output of the wrong size")
+    p = Params(mode=PLAIN_F64, result=int(result), L_window=float(L_window), L_quad=float(L_quad),
+               stats=(_dev(stats, torch.int64) if stats is not None else None))
+    ptr = lambda k: outs[k].data_ptr() if k in outs else None
+    _check(_deriv(_dev(nu, torch.float64), _dev(x, torch.float64), ptr("k"), ptr("dx"), ptr("dnu"), n,
+                  ctypes.byref(p), _stream(stream)))
+    return outs
+
+
+def matern_grad_tiles(lx, ly, sigma2, beta, nu, tile_size, lower_only, out_dtype=OUT_F64,
+                      want=("c", "dbeta", "dnu"), L_window=0.0, L_quad=0.0, stream=None, out=None):
+    """Matern tiles and their beta and nu derivatives (bk_matern_grad_tiles), packed
+    like matern_tiles. Returns a dict with the requested outputs among "c", "dbeta",
+    "dnu"; out may give preallocated buffers for them."""
+    n = lx.numel()
+    if ly.numel() != n:
+        raise ValueError("lx and ly differ in size")
+    if any(k not in ("c", "dbeta", "dnu") for k in want):
+        raise ValueError("unknown output")
+    elems = matern_out_elems(n, tile_size, lower_only)
+    dt = torch.float32 if int(out_dtype) == OUT_F32 else torch.float64
+    outs = {k: (out[k] if out is not None and k in out else torch.empty(max(elems, 0), dtype=dt, device=lx.device))
+            for k in want}
+    for t in outs.values():
+        if t.numel() < elems or t.dtype != dt:
+            raise ValueError("output too small or of the wrong dtype")
+    locs = Locs(x=_dev(lx, torch.float64), y=_dev(ly, torch.float64), n=n)
+    p = Params(mode=PLAIN_F64, out_dtype=int(out_dtype), sigma2=float(sigma2), beta=float(beta), nu=float(nu),
+               L_window=float(L_window), L_quad=float(L_quad))
+    ptr = lambda k: outs[k].data_ptr() if k in outs else None
+    _check(_matern_grad(ctypes.byref(locs), ctypes.byref(p), int(tile_size), int(lower_only), ptr("c"),
+                        ptr("dbeta"), ptr("dnu"), _stream(stream)))
+    return outs
+
+
+def matern_loglik(lx, ly, z, sigma2, beta, nu, grad=False, mode="plain", model=None, workspace=None,
+                  L_window=0.0, L_quad=0.0, stream=None):
+    """Gaussian log-likelihood of z under the Matern covariance (bk_matern_loglik).
+    Returns l, or (l, [dl/dsigma2, dl/dbeta, dl/dnu]) with grad=True. Synchronises."""
+    n = lx.numel()
+    if ly.numel() != n or z.numel() != n:
+        raise ValueError("lx, ly and z differ in size")
+    need = int(_loglik_ws(n, 1 if grad else 0))
+    if need == 0:
+        raise ValueError("n out of range")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=lx.device)
+    locs = Locs(x=_dev(lx, torch.float64), y=_dev(ly, torch.float64), n=n)
+    p = Params(mode=_mode(mode), sigma2=float(sigma2), beta=float(beta), nu=float(nu), L_window=float(L_window),
+               L_quad=float(L_quad), model=(model.handle if model is not None else None))
+    res = (ctypes.c_double * 4)()
+    _check(_loglik(ctypes.byref(locs), _dev(z, torch.float64), ctypes.byref(p), 1 if grad else 0, res,
+                   workspace.data_ptr(), workspace.numel() * workspace.element_size(), _stream(stream)))
+    if grad:
+        return res[0], [res[1], res[2], res[3]]
+    return res[0]
+
+
+def matern_loglik_workspace_bytes(n, grad=False):
+    return int(_loglik_ws(int(n), 1 if grad else 0))
 
 
 def unpack_tiles(packed, n, tile_size, lower_only):

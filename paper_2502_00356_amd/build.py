@@ -11,7 +11,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbesselk.so")
-SOURCES = ["bk_kernels.hip", "bk_mlp.hip"]
+SOURCES = ["bk_kernels.hip", "bk_mlp.hip", "bk_mle.hip"]
+# rocSOLVER (Cholesky, triangular solves, inverse) and the rocBLAS handle it runs on
+LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
 ARCH = os.environ.get("BK_OFFLOAD_ARCH", "gfx950")
 
 
@@ -105,7 +107,7 @@ def build(verbose=False, jobs=None):
             sys.stderr.write(msg + "\n")
     if failed:
         raise RuntimeError("HIP build failed")
-    cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs + LIBS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
@@ -116,7 +118,7 @@ def build(verbose=False, jobs=None):
     try:
         import json
         slots = {}
-        for src in SOURCES:
+        for src in SOURCES[:2]:
             asm = os.path.join(CSRC, src + ".s")
             subprocess.check_call([hipcc] + flags + ["--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", asm],
                                   stderr=subprocess.DEVNULL)

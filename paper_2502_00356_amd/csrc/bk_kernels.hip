@@ -329,6 +329,73 @@ __global__ __launch_bounds__(256) void k_window(const double* __restrict__ nu,
     nodes[i] = s.p.N;
 }
 
+// e^x-scaled value s to the requested result (K or e^x K).
+__device__ __forceinline__ double unscale(double z, double s, int result)
+{
+    if (result == BK_RESULT_SCALED) return s;
+    if (z < 708.0) return exp(-z) * s;
+    return exp(log(s) - z);
+}
+
+// K_nu(x), dK/dx and dK/dnu, one lane per entry, FP64: the K integral at orders
+// nu and |nu - 1| and the dK/dnu integral, each with its own plain solve. NULL
+// outputs are skipped (dK/dx still evaluates K_nu). dK/dnu carries the sign of nu.
+__global__ __launch_bounds__(256) void k_besselk_deriv(const double* __restrict__ nu, const double* __restrict__ x,
+                                                       double* __restrict__ k, double* __restrict__ dkdx,
+                                                       double* __restrict__ dkdnu, int64_t n, int result, double L,
+                                                       double Lq, const RuleTable* __restrict__ Rp,
+                                                       unsigned long long* __restrict__ stats)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    unsigned long long nodes = 0, ents = 0;
+    if (i < n) {
+        const double nr = nu[i], z = x[i], v = fabs(nr);
+        double rk, rx, rn;
+        if (isnan(nr) || isnan(z) || z < 0.0) {
+            rk = rx = rn = __builtin_nan("");
+        } else if (z == 0.0 || isinf(v)) {
+            rk = __builtin_inf();
+            rx = -__builtin_inf();
+            rn = v == 0.0 ? 0.0 : copysign(__builtin_inf(), nr);
+        } else if (isinf(z)) {
+            rk = 0.0;
+            rx = -0.0;
+            rn = copysign(0.0, nr);
+        } else {
+            const RuleTable& R = *Rp;
+            const Solved s0 = plain_solve(v, z, L, Lq, R);
+            const double hs0 = s0.p.h * sum_f64(v, s0.p, s0.A, s0.B);
+            rk = assemble(z, s0.delta, hs0, result);
+            nodes += (unsigned long long)(s0.p.N + 1);
+            rx = 0.0;
+            if (dkdx) {
+                const double v1 = fabs(v - 1.0);
+                const Solved s1 = plain_solve(v1, z, L, Lq, R);
+                const double hs1 = s1.p.h * sum_f64(v1, s1.p, s1.A, s1.B);
+                nodes += (unsigned long long)(s1.p.N + 1);
+                rx = -unscale(z, exp(s1.delta) * hs1 + (v / z) * (exp(s0.delta) * hs0), result);
+            }
+            rn = 0.0;
+            if (dkdnu && v > 0.0) {
+                const Solved sd = dnu_solve(v, z, s0.p.t0, L, Lq, R);
+                const double hsd = sd.p.h * sum_dnu_f64(v, sd.p, sd.A, sd.B);
+                nodes += (unsigned long long)(sd.p.N + 1);
+                rn = copysign(assemble(z, sd.delta, hsd, result), nr);
+            } else if (dkdnu) {
+                rn = copysign(0.0, nr);
+            }
+            ents = 1;
+        }
+        if (k) k[i] = rk;
+        if (dkdx) dkdx[i] = rx;
+        if (dkdnu) dkdnu[i] = rn;
+    }
+    if (stats) {
+        block_count_w(stats + BK_STAT_NODES, nodes, 4);
+        block_count_w(stats + BK_STAT_ENTRIES, ents, 4);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Matern tiles
 // ---------------------------------------------------------------------------
@@ -415,6 +482,66 @@ __global__ __launch_bounds__(256) void k_matern(const double* __restrict__ lx,
     }
 }
 
+// Matern covariance and its partial derivatives in beta and nu (Sec. III-A
+// formula, differentiated), FP64, same tiling and lane mapping as k_matern. With
+// z = r / beta and c(nu) = 2^(1-nu) / Gamma(nu):
+//   M       = sigma2 c z^nu K_nu(z)
+//   dM/dbeta = sigma2 c z^(nu+1) K_{nu-1}(z) / beta     (d/dz z^nu K_nu = -z^nu K_{nu-1})
+//   dM/dnu   = M (ln z - ln 2 - psi(nu)) + sigma2 c z^nu dK_nu/dnu(z)
+// pref = ln c and psi = psi(nu) come from the host. A NULL output is skipped.
+template <typename OutT>
+__global__ __launch_bounds__(256) void k_matern_grad(const double* __restrict__ lx, const double* __restrict__ ly,
+                                                     TileGeom g, int64_t tile_base, double sigma2, double inv_beta,
+                                                     double nu, double pref, double psi, double L, double Lq,
+                                                     const RuleTable* __restrict__ Rp, OutT* __restrict__ oc,
+                                                     OutT* __restrict__ ob, OutT* __restrict__ on)
+{
+    const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
+    const int64_t p = tile_base + (int64_t)blockIdx.x / wg_per_tile;
+    const int64_t local = (int64_t)blockIdx.x % wg_per_tile;
+    const int rb = (int)(local % g.rb_per_tile), cb = (int)(local / g.rb_per_tile);
+    int64_t I, J;
+    tile_of(p, g, I, J);
+    const int64_t mI = min((int64_t)g.ts, g.n - I * g.ts);
+    const int64_t nJ = min((int64_t)g.ts, g.n - J * g.ts);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t il = (int64_t)rb * kRowsPerWave + lane;
+    const int64_t jl0 = (int64_t)cb * kColsPerGroup + (int64_t)wave * kColsPerWave;
+    if (il >= mI || jl0 >= nJ) return;
+    const int64_t base = tile_offset(g.n, g.ts, g.T, g.lower, I, J);
+    const double xi = lx[I * g.ts + il], yi = ly[I * g.ts + il];
+    const int cend = (int)min((int64_t)kColsPerWave, nJ - jl0);
+    const double nu1 = fabs(nu - 1.0);
+    for (int c = 0; c < cend; ++c) {
+        const int64_t jl = jl0 + c;
+        const double xj = lx[J * g.ts + jl], yj = ly[J * g.ts + jl];
+        const double dx = xj - xi, dy = yj - yi;
+        const double r = sqrt(dx * dx + dy * dy);
+        double vc = sigma2, vb = 0.0, vn = 0.0;
+        if (r != 0.0) {
+            const RuleTable& R = *Rp;
+            const double z = r * inv_beta, lz = log(z);
+            const Solved s0 = plain_solve(nu, z, L, Lq, R);
+            vc = sigma2 * exp(pref + nu * lz + (s0.delta - z)) * (s0.p.h * sum_f64(nu, s0.p, s0.A, s0.B));
+            if (ob) {
+                const Solved s1 = plain_solve(nu1, z, L, Lq, R);
+                vb = sigma2 * inv_beta * exp(pref + (nu + 1.0) * lz + (s1.delta - z)) *
+                     (s1.p.h * sum_f64(nu1, s1.p, s1.A, s1.B));
+            }
+            if (on) {
+                const Solved sd = dnu_solve(nu, z, s0.p.t0, L, Lq, R);
+                vn = vc * (lz - kLn2 - psi) +
+                     sigma2 * exp(pref + nu * lz + (sd.delta - z)) * (sd.p.h * sum_dnu_f64(nu, sd.p, sd.A, sd.B));
+            }
+        }
+        const int64_t o = base + il + jl * mI;
+        if (oc) oc[o] = (OutT)vc;
+        if (ob) ob[o] = (OutT)vb;
+        if (on) on[o] = (OutT)vn;
+    }
+}
+
 }  // namespace bk
 
 using namespace bk;
@@ -431,6 +558,7 @@ extern "C" const char* bk_status_str(int status)
     case BK_ENOMEM: return "BK_ENOMEM: workspace too small or allocation failed";
     case BK_ENOMODEL: return "BK_ENOMODEL: learned form requested without a trained model";
     case BK_EIO: return "BK_EIO: model file error";
+    case BK_ENOTPD: return "BK_ENOTPD: covariance matrix not positive definite";
     default: return "unknown bk_status";
     }
 }
@@ -584,4 +712,99 @@ extern "C" int bk_matern_tiles(const bk_locs* locs, const bk_params* prm, int32_
     default:
         return BK_EINVAL;
     }
+}
+
+// Digamma psi(v), v > 0, on the host in long double: shift up with
+// psi(v) = psi(v + 1) - 1/v until v >= 12, then the asymptotic expansion
+// ln v - 1/(2v) - 1/(12 v^2) + 1/(120 v^4) - 1/(252 v^6) + 1/(240 v^8) - 1/(132 v^10)
+// + 691/(32760 v^12) (Abramowitz & Stegun 6.3.18); the first omitted term,
+// 1/(12 v^14), is below 3e-17 of psi(12).
+static double digamma_host(double v)
+{
+    long double t = v, acc = 0.0L;
+    for (; t < 12.0L; t += 1.0L) acc -= 1.0L / t;
+    const long double w = 1.0L / (t * t);
+    const long double tail =
+        w * (1.0L / 12 - w * (1.0L / 120 - w * (1.0L / 252 - w * (1.0L / 240 - w * (1.0L / 132 - w * (691.0L / 32760))))));
+    return (double)(acc + logl(t) - 0.5L / t - tail);
+}
+
+static int check_deriv_params(const bk_params* prm, bk_params* use)
+{
+    if (prm) *use = *prm;
+    else memset(use, 0, sizeof(*use));
+    if (use->mode != BK_PLAIN_F64) return BK_EINVAL;
+    if (use->result != BK_RESULT_K && use->result != BK_RESULT_SCALED) return BK_EINVAL;
+    if (use->L_window < 0.0 || use->L_quad < 0.0) return BK_EINVAL;
+    return BK_OK;
+}
+
+extern "C" int bk_besselk_deriv(const double* nu, const double* x, double* k, double* dk_dx, double* dk_dnu,
+                                int64_t n, const bk_params* prm, hipStream_t stream)
+{
+    bk_params p;
+    if (n < 0) return BK_EINVAL;
+    int st = check_deriv_params(prm, &p);
+    if (st != BK_OK) return st;
+    if (n == 0) return BK_OK;
+    if (!nu || !x || (!k && !dk_dx && !dk_dnu)) return BK_EINVAL;
+    double L, Lq;
+    resolve_thresholds(BK_PLAIN_F64, p.L_window, p.L_quad, &L, &Lq);
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffffLL) return BK_EINVAL;
+    const RuleTable* R = rule_table_dev();
+    if (!R) return BK_EHIP;
+    hipLaunchKernelGGL(k_besselk_deriv, dim3((unsigned)blocks), dim3(256), 0, stream, nu, x, k, dk_dx, dk_dnu, n,
+                       p.result, L, Lq, R, p.stats);
+    return launch_status();
+}
+
+template <typename OutT>
+static int launch_matern_grad(const bk_locs* locs, const bk_params* prm, const TileGeom& g, int64_t ntiles,
+                              double L, double Lq, void* c, void* db, void* dn, hipStream_t stream)
+{
+    const double nu = prm->nu;
+    const double pref = (1.0 - nu) * kLn2 - lgamma(nu);
+    const double psi = digamma_host(nu);
+    const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
+    const int64_t max_wg = 1LL << 23;
+    const int64_t tiles_per_launch = max_wg / wg_per_tile > 0 ? max_wg / wg_per_tile : 1;
+    const RuleTable* R = rule_table_dev();
+    if (!R) return BK_EHIP;
+    for (int64_t t0 = 0; t0 < ntiles; t0 += tiles_per_launch) {
+        const int64_t nt = ntiles - t0 < tiles_per_launch ? ntiles - t0 : tiles_per_launch;
+        hipLaunchKernelGGL((k_matern_grad<OutT>), dim3((unsigned)(nt * wg_per_tile)), dim3(256), 0, stream, locs->x,
+                           locs->y, g, t0, prm->sigma2, 1.0 / prm->beta, nu, pref, psi, L, Lq, R, (OutT*)c, (OutT*)db,
+                           (OutT*)dn);
+        const int st = launch_status();
+        if (st != BK_OK) return st;
+    }
+    return BK_OK;
+}
+
+extern "C" int bk_matern_grad_tiles(const bk_locs* locs, const bk_params* prm, int32_t tile_size, int32_t lower_only,
+                                    void* c, void* dc_dbeta, void* dc_dnu, hipStream_t stream)
+{
+    if (!locs || !prm || tile_size <= 0 || locs->n < 0) return BK_EINVAL;
+    if (prm->mode != BK_PLAIN_F64) return BK_EINVAL;
+    if (!(prm->beta > 0.0) || !(prm->nu > 0.0) || !(prm->sigma2 >= 0.0) || isinf(prm->nu) || isinf(prm->beta))
+        return BK_EINVAL;
+    if (prm->out_dtype != BK_OUT_F64 && prm->out_dtype != BK_OUT_F32) return BK_EINVAL;
+    if (prm->L_window < 0.0 || prm->L_quad < 0.0) return BK_EINVAL;
+    if (locs->n == 0) return BK_OK;
+    if (!locs->x || !locs->y || (!c && !dc_dbeta && !dc_dnu)) return BK_EINVAL;
+    TileGeom g;
+    g.n = locs->n;
+    g.ts = tile_size;
+    g.T = (int32_t)((locs->n + tile_size - 1) / tile_size);
+    g.lower = lower_only ? 1 : 0;
+    g.rb_per_tile = (tile_size + kRowsPerWave - 1) / kRowsPerWave;
+    g.cb_per_tile = (tile_size + kColsPerGroup - 1) / kColsPerGroup;
+    const int64_t T = g.T;
+    const int64_t ntiles = g.lower ? T * (T + 1) / 2 : T * T;
+    double L, Lq;
+    resolve_thresholds(BK_PLAIN_F64, prm->L_window, prm->L_quad, &L, &Lq);
+    if (prm->out_dtype == BK_OUT_F32)
+        return launch_matern_grad<float>(locs, prm, g, ntiles, L, Lq, c, dc_dbeta, dc_dnu, stream);
+    return launch_matern_grad<double>(locs, prm, g, ntiles, L, Lq, c, dc_dbeta, dc_dnu, stream);
 }

@@ -180,23 +180,16 @@ struct Solved {
     double t1;
 };
 
-__device__ inline Solved plain_solve(double nu, double x, double L, double Lq, const RuleTable& R)
+// Node grid on [t0, t1] with step at most h0, reference node nearest tpk, and
+// the prefactor constants for the node walk.
+__device__ inline Solved plan_window(double nu, double x, double t0, double t1, double tpk, double h0)
 {
     Solved s;
-    double tstar = 0.0;
-    if (nu * nu > x) tstar = peak_solve(nu, x);
-    double chs, shs;
-    cosh_sinh(tstar, chs, shs);
-    double gstar = logcosh_pos(nu * tstar) - x * chs;
-    double t1 = window_right(nu, x, tstar, chs, gstar, L);
-    double t0 = 0.0;
-    if (-x < gstar - L) t0 = window_left(nu, x, tstar, gstar, L);
-    double h0 = node_step(nu, x, Lq, R);
     int N = node_count(t1 - t0, h0);
     double h = (t1 - t0) / (double)N;
     int mc = 0;
-    if (tstar > t0) {
-        double r = rint((tstar - t0) / h);
+    if (tpk > t0) {
+        double r = rint((tpk - t0) / h);
         mc = (int)fmin(fmax(r, 0.0), (double)N);
     }
     double tref = t0 + (double)mc * h;
@@ -212,8 +205,23 @@ __device__ inline Solved plain_solve(double nu, double x, double L, double Lq, c
     s.delta = nu * tref - kLn2 - 2.0 * x * sh2 * sh2;
     s.A = 0.5 * x * ch;
     s.B = 0.5 * x * sh;
-    s.gstar = gstar;
+    s.gstar = 0.0;
     s.t1 = t1;
+    return s;
+}
+
+__device__ inline Solved plain_solve(double nu, double x, double L, double Lq, const RuleTable& R)
+{
+    double tstar = 0.0;
+    if (nu * nu > x) tstar = peak_solve(nu, x);
+    double chs, shs;
+    cosh_sinh(tstar, chs, shs);
+    double gstar = logcosh_pos(nu * tstar) - x * chs;
+    double t1 = window_right(nu, x, tstar, chs, gstar, L);
+    double t0 = 0.0;
+    if (-x < gstar - L) t0 = window_left(nu, x, tstar, gstar, L);
+    Solved s = plan_window(nu, x, t0, t1, tstar, node_step(nu, x, Lq, R));
+    s.gstar = gstar;
     return s;
 }
 
@@ -296,6 +304,116 @@ __device__ inline double sum_mixed(double nu, const Plan& p, double A, double B)
         walk_step(w, m);
     }
     return (double)s - (double)c - 0.5 * (double)ends;
+}
+
+// ---------------------------------------------------------------------------
+// Derivatives of K_nu(x), FP64 (the paper names them as future work, Sec. VI).
+// Differentiating the integral of Sec. IV-B under the integral sign:
+//   dK/dx  = -int_0^inf cosh t cosh(nu t) e^(-x cosh t) dt,
+//   dK/dnu =  int_0^inf t sinh(nu t) e^(-x cosh t) dt =: D.
+// Since cosh t cosh(nu t) = (cosh((nu+1)t) + cosh((nu-1)t)) / 2, the first is
+// -(K_{nu+1} + K_{nu-1}) / 2 = -(K_{nu-1} + (nu/x) K_nu) (three-term recurrence);
+// a sum of two positive integrals of the K kind, so it costs one more K solve at
+// order |nu - 1| and no cancellation.
+// D has its own window. Its log-integrand
+//   d(t) = log t + log sinh(nu t) - x cosh t
+// is strictly concave on t > 0 (each term is), tends to -inf at 0 and has one
+// maximiser t_d, the zero of d'(t) = 1/t + nu coth(nu t) - x sinh t. At t_d,
+// x sinh t_d = 1/t_d + nu coth(nu t_d), which lies in [max(nu, 2/t_d), 2/t_d + nu]
+// (coth y >= 1/y, coth y <= 1 + 1/y), so with sinh t <= 1.1752 t on [0, 1]:
+//   t_d >= lo = max(asinh(nu/x), min(1, sqrt(1.70/x))),  t_d <= asinh((2/lo + nu)/x).
+// Its window is [t0, t1]: t0 is the left end of K's window (left of it the factor
+// t tanh(nu t) is below its value at K's peak, so D's integrand is below e^-L of
+// its maximum there; when K's window starts at 0 so does D's, and D's integrand
+// is even in t, so the trapezoid keeps its accuracy from t = 0), and t1 > t_d the
+// root of d(t) = d(t_d) - L. Node terms reuse the K walk: with P = e^(-2 nu t),
+//   t sinh(nu t) e^(-x cosh t) = e^(-x) e^Delta e^(nu u - xterm) t (1 - P),
+// and Q = 1 - P follows Q' = Q rho + (1 - rho) (rho = e^(-2 nu h)), a recurrence
+// that never amplifies Q's relative error.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void dnu_log_and_slope(double nu, double x, double t, double& d, double& dp)
+{
+    const double omp = -expm1(-2.0 * nu * t);        // 1 - e^(-2 nu t)
+    double ch, sh;
+    cosh_sinh(t, ch, sh);
+    d = log(t) + nu * t + log(omp) - kLn2 - x * ch;
+    dp = 1.0 / t + nu * (2.0 - omp) / omp - x * sh;
+}
+
+__device__ inline double dnu_peak(double nu, double x)
+{
+    double lo = fmax(asinh(nu / x), fmin(1.0, sqrt(1.70 / x)));
+    double hi = asinh((2.0 / lo + nu) / x);
+    double t = 0.5 * (lo + hi);
+    for (int it = 0; it < 100; ++it) {
+        const double omp = -expm1(-2.0 * nu * t);
+        const double p = 1.0 - omp;
+        double ch, sh;
+        cosh_sinh(t, ch, sh);
+        const double f = 1.0 / t + nu * (1.0 + p) / omp - x * sh;
+        const double fp = -1.0 / (t * t) - 4.0 * nu * nu * p / (omp * omp) - x * ch;
+        if (f > 0.0) lo = t; else hi = t;
+        double tn = t - f / fp;
+        if (fabs(tn - t) <= 1e-14 * t) { t = fmin(fmax(tn, lo), hi); break; }
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        t = tn;
+        if (hi - lo <= 1e-15 * hi) break;
+    }
+    return t;
+}
+
+// Root t1 > t_d of d(t) = dstar - L. Start at acosh(cosh t_d + L/x), where the
+// x term alone has dropped by L while log t + log sinh(nu t) grew, so the start is
+// left of the root; d is concave, so the first Newton step lands right of the root
+// and Newton then decreases monotonically onto it.
+__device__ inline double dnu_window_right(double nu, double x, double td, double chd, double dstar, double L)
+{
+    double t = acosh(chd + L / x);
+    const double tcap = td + 4.0 * (t - td) + 1.0;
+    for (int it = 0; it < 64; ++it) {
+        double d, dp;
+        dnu_log_and_slope(nu, x, t, d, dp);
+        double tn = fmin(t - (d - dstar + L) / dp, tcap);
+        if (!(tn > td)) tn = 0.5 * (t + td);
+        const bool done = fabs(tn - t) <= 1e-14 * t;
+        t = tn;
+        if (done) break;
+    }
+    return t;
+}
+
+// Plan for D given K's window start t0 (nu > 0, 0 < x < inf). The node step uses
+// the strip bound of K with the extra factor of D's integrand on the strip,
+// |t + i a| |sinh(nu (t + i a))| / (t sinh(nu t)) <= (1 + a/t) coth(nu t),
+// taken at the maximiser with a = pi/2.
+__device__ inline Solved dnu_solve(double nu, double x, double t0, double L, double Lq, const RuleTable& R)
+{
+    const double td = dnu_peak(nu, x);
+    double d, dp;
+    dnu_log_and_slope(nu, x, td, d, dp);
+    double chd, shd;
+    cosh_sinh(td, chd, shd);
+    const double t1 = dnu_window_right(nu, x, td, chd, d, L);
+    const double extra = log1p(1.5707963267948966 / td) - log(tanh(nu * td));
+    return plan_window(nu, x, t0, t1, td, node_step(nu, x, Lq + extra, R));
+}
+
+// FP64 trapezoid sum of D's node terms e^(nu u - xterm) t (1 - P).
+__device__ inline double sum_dnu_f64(double nu, const Plan& p, double A, double B)
+{
+    Walk w = walk_begin(nu, p);
+    double Q = -expm1(-2.0 * nu * p.t0);
+    const double omr = -expm1(-2.0 * nu * p.h);
+    double S = 0.0, ends = 0.0;
+    for (int m = 0; m <= p.N; ++m) {
+        const double t = fma((double)m, p.h, p.t0);
+        const double term = exp(walk_exponent(w, m, nu, A, B)) * t * Q;
+        S += term;
+        if (m == 0 || m == p.N) ends += term;
+        walk_step(w, m);
+        Q = fma(Q, w.rho, omr);
+    }
+    return S - 0.5 * ends;
 }
 
 // ---------------------------------------------------------------------------

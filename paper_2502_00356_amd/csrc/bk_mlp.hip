@@ -125,22 +125,11 @@ __device__ inline void mlp_wave(const MlpDev& M, float u0, float u1, float& y0, 
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
     const float4_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
-    float4_t B3;
+    // Layer 1 for the wave's four 16-entry column tiles (bias folded in through the
+    // constant-1 input row).
+    half4_t h1[4][4];
 #pragma unroll
-    for (int it = 0; it < 4; ++it) B3[it] = (q == 0 && it < 3) ? M.b3[it] : 0.0f;
-    y0 = y1 = y2 = 0.0f;
-    // One 16-entry column tile at a time; layer 2 is consumed by layer 3 as each
-    // 16-unit row block completes, so at most one h2 block is live. Operands are
-    // read where used (they stay in L1/L2: the whole pack is 12 KB).
-#pragma unroll 1
     for (int nt = 0; nt < 4; ++nt) {
-        // Opaque copies of the operand pointers: keeps the compiler from hoisting the
-        // 24 operand loads out of this loop (which would hold ~50 more VGPRs live).
-        const half4_t* a1 = M.a1;
-        const half4_t* a2 = M.a2;
-        const half4_t* a3 = M.a3;
-        const float* b2 = M.b2;
-        asm volatile("" : "+s"(a1), "+s"(a2), "+s"(a3), "+s"(b2));
         const float e0 = __shfl(u0, 16 * nt + r, 64);
         const float e1 = __shfl(u1, 16 * nt + r, 64);
         half4_t b0;
@@ -148,23 +137,39 @@ __device__ inline void mlp_wave(const MlpDev& M, float u0, float u1, float& y0, 
         b0[1] = (_Float16)(q == 0 ? e1 : 0.0f);
         b0[2] = (_Float16)(q == 0 ? 1.0f : 0.0f);
         b0[3] = (_Float16)0.0f;
-        half4_t h1[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
-            h1[mt] = relu_h4(__builtin_amdgcn_mfma_f32_16x16x16f16(a1[mt * 64 + lane], b0, zero, 0, 0, 0));
-        float4_t o = B3;
+            h1[nt][mt] = relu_h4(__builtin_amdgcn_mfma_f32_16x16x16f16(M.a1[mt * 64 + lane], b0, zero, 0, 0, 0));
+    }
+    // Layers 2 and 3, one 16-unit row block of layer 2 at a time: each weight
+    // fragment is read once per wave and applied to the four column tiles, which
+    // are four independent accumulation chains.
+    float4_t o[4];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            float4_t acc;
+    for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-            for (int it = 0; it < 4; ++it) acc[it] = b2[16 * mt + 4 * q + it];
+        for (int it = 0; it < 4; ++it) o[nt][it] = (q == 0 && it < 3) ? M.b3[it] : 0.0f;
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks)
-                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a2[(mt * 4 + ks) * 64 + lane], h1[ks], acc, 0, 0, 0);
-            o = __builtin_amdgcn_mfma_f32_16x16x16f16(a3[mt * 64 + lane], relu_h4(acc), o, 0, 0, 0);
+    for (int mt = 0; mt < 4; ++mt) {
+        const float4_t bias = *reinterpret_cast<const float4_t*>(M.b2 + 16 * mt + 4 * q);
+        float4_t acc[4] = {bias, bias, bias, bias};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const half4_t a = M.a2[(mt * 4 + ks) * 64 + lane];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, h1[nt][ks], acc[nt], 0, 0, 0);
         }
-        // outputs of entry 16 nt + r sit in lane r (q == 0), items 0..2
-        const float s0 = __shfl(o[0], r, 64), s1 = __shfl(o[1], r, 64), s2 = __shfl(o[2], r, 64);
+        const half4_t a3 = M.a3[mt * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+            o[nt] = __builtin_amdgcn_mfma_f32_16x16x16f16(a3, relu_h4(acc[nt]), o[nt], 0, 0, 0);
+    }
+    // outputs of entry 16 nt + r sit in lane r (q == 0) of tile nt, items 0..2
+    y0 = y1 = y2 = 0.0f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const float s0 = __shfl(o[nt][0], r, 64), s1 = __shfl(o[nt][1], r, 64), s2 = __shfl(o[nt][2], r, 64);
         if (q == nt) { y0 = s0; y1 = s1; y2 = s2; }
     }
 }

@@ -94,6 +94,19 @@ def jittered_grid_locations(side=316, seed=7, jitter=0.4, morton=True):
 
 
 # Workload parameter sets (sigma2, beta, nu) of the Matern configurations.
+def gp_observations(xy, seed, length=0.05):
+    """Observations for the likelihood workloads: one draw z ~ N(0, R) with the
+    exponential correlation R_ij = exp(-|l_i - l_j| / length) (a closed form, not
+    the K_nu path), standard normal noise through numpy's Cholesky factor. It gives
+    z the spatial structure of the paper's synthetic fields; the likelihood itself
+    is defined for any z."""
+    r = np.sqrt(((xy[:, None, :] - xy[None, :, :]) ** 2).sum(-1))
+    L = np.linalg.cholesky(np.exp(-r / length) + 1e-12 * np.eye(xy.shape[0]))
+    return L @ np.random.default_rng(seed).standard_normal(xy.shape[0])
+
+
 MATERN_SMALL = dict(n=1024, seed=0, sigma2=1.0, beta=0.1, nu=1.3, tile=1024, lower_only=0, morton=False)
 MATERN_MEDIUM = dict(n=40000, seed=3, sigma2=1.0, beta=0.05, nus=(0.8, 2.3), tile=960, lower_only=1)
 MATERN_LARGE = dict(side=316, seed=7, sigma2=1.0, beta=0.02, nu=3.7, tile=1024, lower_only=1)
+# likelihood and gradient on a dense n x n covariance (Cholesky on the GPU)
+LOGLIK = dict(n=8192, seed=11, obs_seed=12, sigma2=1.0, beta=0.05, nu=0.8)

@@ -77,6 +77,35 @@ def test_argument_validation_is_host_side(lib):
     assert m(ctypes.byref(locs0), ctypes.byref(q), 4, 1, None, None) == 0
 
 
+def test_derivative_entry_points_validate_on_host(lib):
+    from paper_2502_00356_amd import api
+    d = lib.bk_besselk_deriv
+    d.restype = ctypes.c_int
+    d.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_int64, ctypes.POINTER(api.Params), ctypes.c_void_p]
+    a = ctypes.c_void_p(16)
+    assert d(a, a, a, a, a, -1, None, None) == 1
+    assert d(a, a, None, None, None, 4, None, None) == 1              # no output requested
+    assert d(None, a, a, None, None, 4, None, None) == 1              # null input
+    assert d(None, None, None, None, None, 0, None, None) == 0        # n == 0
+    for kw in (dict(mode=1), dict(mode=2), dict(result=2), dict(L_window=-1.0)):
+        p = api.Params(**kw)
+        assert d(a, a, a, a, a, 4, ctypes.byref(p), None) == 1, kw
+    g = lib.bk_matern_grad_tiles
+    g.restype = ctypes.c_int
+    g.argtypes = [ctypes.POINTER(api.Locs), ctypes.POINTER(api.Params), ctypes.c_int32, ctypes.c_int32,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    locs = api.Locs(x=a, y=a, n=10)
+    ok = dict(sigma2=1.0, beta=0.1, nu=1.2)
+    for kw in (dict(ok, mode=1), dict(ok, beta=0.0), dict(ok, nu=0.0), dict(ok, out_dtype=7)):
+        p = api.Params(**kw)
+        assert g(ctypes.byref(locs), ctypes.byref(p), 4, 1, a, a, a, None) == 1, kw
+    p = api.Params(**ok)
+    assert g(ctypes.byref(locs), ctypes.byref(p), 4, 1, None, None, None, None) == 1
+    assert g(ctypes.byref(locs), ctypes.byref(p), 0, 1, a, None, None, None) == 1
+    locs0 = api.Locs(x=None, y=None, n=0)
+    assert g(ctypes.byref(locs0), ctypes.byref(p), 4, 1, None, None, None, None) == 0
+
+
 @pytest.mark.parametrize("n,ts,lower", [(40000, 960, 1), (99856, 1024, 1), (1024, 1024, 0), (350, 100, 1),
                                         (350, 100, 0), (1, 5, 1), (7, 7, 1)])
 def test_tile_layout(n, ts, lower):

@@ -324,3 +324,150 @@ def test_empirical_upper_bound_replay(orc):
     L, err = orc.empirical_upper_bound(xs, nus, tol=1e-9)
     print("replayed upper bound: %s (max abs error %.3g)" % (L, err))
     assert L is not None and 5.0 <= L <= 9.0
+
+
+# ---------------------------------------------------------------------------
+# Derivatives (differentiation under the integral sign; the paper's future work,
+# Sec. VI) and the Matern gradient.
+# ---------------------------------------------------------------------------
+def _log_close(a, b, rel=4e-16, abs_=2e-15):
+    """|a - b| within rounding of log values of magnitude |b|."""
+    return np.all(np.abs(a - b) <= abs_ + rel * np.abs(b))
+
+
+def test_dx_integral_matches_recurrence(orc):
+    """The direct integral of cosh t cosh(nu t) e^{-x cosh t} equals
+    (K_{nu-1} + K_{nu+1}) / 2 (DLMF 10.29.2), with both K from the K integral."""
+    rng = np.random.default_rng(31)
+    nu = np.concatenate([rng.uniform(0.0, 12.0, 1500), [0.0, 0.5, 1.0, 2.0]])
+    x = np.concatenate([10 ** rng.uniform(-4, 3, 1500), [1e-3, 0.7, 35.0, 900.0]])
+    d = orc.besselk_deriv(nu, x)
+    _, lkm, _ = orc.besselk(np.abs(nu - 1.0), x)
+    _, lkp, _ = orc.besselk(nu + 1.0, x)
+    ref = np.logaddexp(lkm, lkp) - math.log(2.0)
+    assert _log_close(d["log_mdx"], ref)
+    assert np.all(np.isfinite(d["log_mdx"])) and np.all(d["dx"][x < 700] < 0.0)
+
+
+def test_dnu_half_order_closed_form(orc):
+    """dK_nu/dnu at nu = 1/2 is sqrt(pi/(2x)) E1(2x) e^x (DLMF 10.38.7)."""
+    x = 10 ** np.linspace(-3, 1.7, 60)
+    d = orc.besselk_deriv(np.full(x.size, 0.5), x)
+    ref = 0.5 * np.log(np.pi / (2 * x)) + np.log(sp.exp1(2 * x)) + x
+    assert _log_close(d["log_dnu"], ref, rel=1e-15, abs_=3e-15)
+    d = orc.besselk_deriv(np.full(x.size, -0.5), x)
+    assert np.all(d["dnu"] < 0.0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_dnu_integer_order_closed_form(orc, n):
+    """dK_nu/dnu at nu = n is (n!/2) (x/2)^-n sum_{k<n} (x/2)^k K_k(x) / ((n-k) k!)
+    (DLMF 10.38.6), with K_k from the K integral."""
+    x = np.array([0.01, 0.05, 0.3, 2.0, 7.5, 40.0, 300.0])
+    d = orc.besselk_deriv(np.full(x.size, float(n)), x)
+    lks = [orc.besselk(np.full(x.size, float(k)), x)[1] for k in range(n)]
+    terms = np.stack([k * np.log(x / 2) + lks[k] - math.log((n - k) * math.factorial(k)) for k in range(n)])
+    ref = math.log(math.factorial(n) / 2.0) - n * np.log(x / 2) + np.logaddexp.reduce(terms, axis=0)
+    assert _log_close(d["log_dnu"], ref, rel=1e-15, abs_=4e-15)
+
+
+def test_dnu_order_zero_and_sign(orc):
+    x = np.array([1e-3, 0.5, 20.0])
+    d = orc.besselk_deriv(np.zeros(3), x)
+    assert np.all(d["dnu"] == 0.0)
+    a = orc.besselk_deriv(np.full(3, 2.7), x)["dnu"]
+    b = orc.besselk_deriv(np.full(3, -2.7), x)["dnu"]
+    assert np.all(a > 0) and np.array_equal(a, -b)
+
+
+def test_derivatives_against_mpmath(orc):
+    """Both derivatives against mpmath's own Bessel K, differentiated numerically at
+    30 digits (an independent implementation)."""
+    mp.mp.dps = 30
+    pts = [(0.3, 0.01), (1.7, 0.9), (4.2, 3.3), (9.5, 0.05), (0.05, 12.0), (6.0, 150.0), (13.0, 2.0)]
+    nu = np.array([p[0] for p in pts]); x = np.array([p[1] for p in pts])
+    d = orc.besselk_deriv(nu, x)
+    for i, (v, z) in enumerate(pts):
+        rx = float(mp.diff(lambda s: mp.besselk(v, s), z))
+        rn = float(mp.diff(lambda s: mp.besselk(s, z), v))
+        assert abs(d["dx"][i] / rx - 1) < 1e-14, (v, z)
+        assert abs(d["dnu"][i] / rn - 1) < 1e-14, (v, z)
+
+
+def test_digamma(orc):
+    v = np.array([1e-3, 0.1, 0.5, 1.0, 2.3, 7.7, 19.5, 20.5, 140.0])
+    got = orc.digamma(v)
+    assert np.allclose(got, sp.digamma(v), rtol=2e-15, atol=0)
+    assert abs(orc.digamma(np.array([1.0]))[0] + 0.57721566490153286061) < 1e-16
+
+
+def test_matern_grad_closed_forms(orc):
+    """nu = 1/2: M = s2 e^{-z}, dM/dbeta = s2 z e^{-z} / beta,
+    dM/dnu = s2 (e^{-z} (ln 2z + gamma) + e^{z} E1(2z)) (from DLMF 10.38.7 and
+    psi(1/2) = -gamma - 2 ln 2); nu = 3/2: dM/dbeta = s2 z^2 e^{-z} / beta."""
+    rng = np.random.default_rng(37)
+    xy = rng.uniform(0, 1, (40, 2))
+    ii, jj = np.meshgrid(np.arange(40), np.arange(40), indexing="ij")
+    ii, jj = ii.ravel(), jj.ravel()
+    s2, beta = 1.7, 0.13
+    r = np.sqrt(((xy[ii] - xy[jj]) ** 2).sum(1))
+    z = r / beta
+    m, db, dn = orc.matern_grad_entries(xy, xy, ii, jj, s2, beta, 0.5)
+    off = r > 0
+    assert np.allclose(m[off], s2 * np.exp(-z[off]), rtol=1e-14, atol=0)
+    assert np.allclose(db[off], s2 * z[off] * np.exp(-z[off]) / beta, rtol=1e-14, atol=0)
+    zo = z[off]
+    ref = s2 * (np.exp(-zo) * (np.log(2 * zo) + np.euler_gamma) + np.exp(zo) * sp.exp1(2 * zo))
+    scale = s2 * (np.exp(-zo) * (np.abs(np.log(2 * zo)) + 1) + np.exp(zo) * sp.exp1(2 * zo))
+    assert np.all(np.abs(dn[off] - ref) <= 1e-14 * scale)
+    assert np.all(m[~off] == s2) and np.all(db[~off] == 0) and np.all(dn[~off] == 0)
+    _, db, _ = orc.matern_grad_entries(xy, xy, ii, jj, s2, beta, 1.5)
+    assert np.allclose(db[off], s2 * z[off] ** 2 * np.exp(-z[off]) / beta, rtol=1e-14, atol=0)
+
+
+def test_matern_grad_finite_differences(orc):
+    """dM/dbeta and dM/dnu against fourth-order central differences of the oracle's
+    own Matern entries (a different code path: no derivative integral)."""
+    rng = np.random.default_rng(41)
+    xy = rng.uniform(0, 1, (12, 2))
+    ii, jj = np.triu_indices(12, 1)
+    s2, beta, nu = 1.3, 0.2, 2.3
+    _, db, dn = orc.matern_grad_entries(xy, xy, ii, jj, s2, beta, nu)
+    f = lambda b, v: orc.matern_entries(xy, xy, ii, jj, s2, b, v)
+    hb, hv = 1e-3 * beta, 1e-3
+    fdb = (8 * (f(beta + hb, nu) - f(beta - hb, nu)) - (f(beta + 2 * hb, nu) - f(beta - 2 * hb, nu))) / (12 * hb)
+    fdn = (8 * (f(beta, nu + hv) - f(beta, nu - hv)) - (f(beta, nu + 2 * hv) - f(beta, nu - 2 * hv))) / (12 * hv)
+    assert np.allclose(db, fdb, rtol=1e-9, atol=1e-12)
+    assert np.allclose(dn, fdn, rtol=1e-8, atol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# Gaussian log-likelihood (the downstream use of the Matern matrix, Sec. III-A)
+# ---------------------------------------------------------------------------
+def test_loglik_exponential_kernel_against_scipy(orc):
+    """nu = 1/2 (exponential kernel, closed form sigma2 e^{-r/beta}): the oracle's
+    likelihood equals scipy's multivariate normal log-density of that matrix."""
+    from scipy.stats import multivariate_normal
+    rng = np.random.default_rng(43)
+    n = 60
+    xy = rng.uniform(0, 1, (n, 2))
+    z = rng.standard_normal(n)
+    s2, beta = 1.3, 0.2
+    r = np.sqrt(((xy[:, None, :] - xy[None, :, :]) ** 2).sum(-1))
+    ref = multivariate_normal(mean=np.zeros(n), cov=s2 * np.exp(-r / beta)).logpdf(z)
+    assert abs(orc.matern_loglik(xy, z, s2, beta, 0.5) - ref) <= 1e-10 * abs(ref)
+
+
+def test_loglik_gradient_finite_differences(orc):
+    rng = np.random.default_rng(47)
+    n = 40
+    xy = rng.uniform(0, 1, (n, 2))
+    z = rng.standard_normal(n)
+    th = np.array([1.1, 0.15, 1.7])
+    ll, g = orc.matern_loglik(xy, z, *th, grad=True)
+    f = lambda t: orc.matern_loglik(xy, z, *t)
+    for k in range(3):
+        h = 1e-4 * th[k]
+        e = np.zeros(3); e[k] = h
+        fd = (8 * (f(th + e) - f(th - e)) - (f(th + 2 * e) - f(th - 2 * e))) / (12 * h)
+        assert abs(g[k] - fd) <= 1e-6 * (abs(fd) + 1.0), (k, g[k], fd)
