@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="grid", choices=["grid", "matern-medium", "matern-large", "deriv-grid",
-                                                           "matern-grad-medium"],
+                                                           "matern-grad-medium", "loglik"],
                     help="grid: the headline standalone workload; matern-*: tiled covariance generation")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device-to-device copy instead (HBM reference for counters)")
@@ -129,6 +129,9 @@ def main():
     from paper_2502_00356_amd import api, workloads
     if a.workload in ("deriv-grid", "matern-grad-medium"):
         deriv_bench(a, torch, api, workloads)
+        return
+    if a.workload == "loglik":
+        loglik_bench(a, torch, api, workloads)
         return
     if a.workload != "grid":
         matern_bench(a, torch, api, workloads)
@@ -329,6 +332,38 @@ def deriv_bench(a, torch, api, workloads):
                                  "plain_tiles_ms": round(ms_c, 3), "cost_ratio_vs_tiles": ms / ms_c}
         line = {"metric": "Matern entries/s with dC/dbeta and dC/dnu", "workload": a.workload, "n": n, "tile": ts,
                 "entries": elems, "beta": beta, "dtype": "f64", "results": res}
+    print(json.dumps(line), flush=True)
+
+
+def loglik_bench(a, torch, api, workloads):
+    """Gaussian log-likelihood of one GP draw under the Matern covariance, with and
+    without its gradient: n = 8,192 uniform points (seed 11), beta = 0.05,
+    nu = 0.8, sigma2 = 1, observations from the exponential-correlation generator
+    (seed 12). Each call builds the dense covariance (and its derivative matrices),
+    factorises it and reduces; the call synchronises, so it is timed by the clock."""
+    dev = torch.device("cuda:0")
+    c = workloads.LOGLIK
+    xy = workloads.uniform_locations(c["n"], c["seed"])
+    z = workloads.gp_observations(xy, c["obs_seed"], length=c["beta"])
+    n = xy.shape[0]
+    lx = torch.from_numpy(np.ascontiguousarray(xy[:, 0])).to(dev)
+    ly = torch.from_numpy(np.ascontiguousarray(xy[:, 1])).to(dev)
+    zd = torch.from_numpy(z).to(dev)
+    ws = torch.empty(api.matern_loglik_workspace_bytes(n, True), dtype=torch.uint8, device=dev)
+    res = {}
+    for grad in (False, True):
+        f = lambda: api.matern_loglik(lx, ly, zd, c["sigma2"], c["beta"], c["nu"], grad=grad, workspace=ws)
+        for _ in range(max(1, a.warmup)):
+            f()
+        steps = max(1, min(a.steps, 3))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            v = f()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        res["with_grad" if grad else "value"] = {"ms": round(ms, 3), "result": v}
+    line = {"metric": "Matern Gaussian log-likelihood evaluations/s", "workload": a.workload, "n": n,
+            "beta": c["beta"], "nu": c["nu"], "dtype": "f64",
+            "evals_per_s": 1e3 / res["value"]["ms"], "results": res}
     print(json.dumps(line), flush=True)
 
 

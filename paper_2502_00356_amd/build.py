@@ -67,12 +67,15 @@ def node_slots(asm_path):
             seg = [x.strip() for x in body[a:b + 1]]
             ops = [x.split()[0] for x in seg if x.startswith("v_")]
             if form == "plain":
-                ok = ops.count("v_ldexp_f64") == 1 and "v_div_scale_f64" not in ops and "v_frexp_mant_f64_e32" not in ops
+                ok = ops.count("v_ldexp_f64") >= 1 and "v_div_scale_f64" not in ops and "v_frexp_mant_f64_e32" not in ops
             else:
                 ok = any(o.startswith("v_exp_f32") for o in ops) and "v_div_scale_f64" not in ops
             if ok:
                 slots = sum(4 if o.split("_e32")[0].split("_e64")[0] in TRANS_QUARTER else 1
                             for o in ops if not o.startswith("v_mfma"))
+                # an unrolled loop evaluates several nodes per trip: one node exponential each
+                per_trip = ops.count("v_ldexp_f64") if form == "plain" else sum(o.startswith("v_exp_f32") for o in ops)
+                slots = slots / max(1, per_trip)
                 if best is None or (b - a) < best[0]:
                     best = (b - a, slots)
         if best is not None:

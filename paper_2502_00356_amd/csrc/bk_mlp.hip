@@ -31,6 +31,7 @@
 #include "bk_internal.hpp"
 
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 namespace bk {
@@ -53,9 +54,9 @@ constexpr int kTableSize = 1024;       // Matern: MLP tabulated over log10 x at 
 
 // Device-side constants of a model for inference.
 struct MlpDev {
-    const half4_t* a1;   // [4 mt][64 lanes]      layer-1 A operand (W1 | b1 | 0)
-    const half4_t* a2;   // [4 mt][4 ks][64]      layer-2 A operand (W2)
-    const half4_t* a3;   // [4 ks][64]            layer-3 A operand (W3, rows >= 3 zero)
+    const half4_t* a1;   // [4 mt][64 lanes]      layer-1 A operand (W1 | b1 | 0), K = 16
+    const half8_t* a2;   // [4 mt][2 c][64]       layer-2 A operand (W2), K = 32 chunks
+    const half8_t* a3;   // [2 c][64]             layer-3 A operand (W3, rows >= 3 zero)
     const float* b2;     // [64]
     const float* b3;     // [3]
     float cx, sx, cnu, snu, st, sn;     // normalisation
@@ -86,8 +87,8 @@ static MlpDev make_dev(const bk_model* m)
 {
     MlpDev d;
     d.a1 = m->pack;
-    d.a2 = m->pack + 4 * 64;
-    d.a3 = m->pack + 20 * 64;
+    d.a2 = reinterpret_cast<const half8_t*>(m->pack + 4 * 64);
+    d.a3 = reinterpret_cast<const half8_t*>(m->pack + 20 * 64);
     d.b2 = m->bias;
     d.b3 = m->bias + 64;
     d.cx = (float)m->norm[0]; d.sx = (float)m->norm[1];
@@ -102,22 +103,43 @@ static MlpDev make_dev(const bk_model* m)
 
 // ---------------------------------------------------------------------------
 // Inference on matrix cores. Layers are computed transposed, H^T = W H_in^T, so
-// that with v_mfma_f32_16x16x16f16 the accumulator layout of one layer (lane
-// holds rows 4q..4q+3 of column r, q = lane/16, r = lane%16) is exactly the B
-// operand layout of the next (lane holds k = 4q..4q+3 of column r). A wave
-// evaluates its 64 entries as four column tiles of 16; all 64 lanes must be
-// active.
+// that the accumulator layout of one layer (v_mfma_f32_16x16x*: lane holds rows
+// 4q..4q+3 of column r, q = lane/16, r = lane%16) is the B operand of the next.
+// Layer 1 (K = 3 inputs + bias, padded to 16) uses v_mfma_f32_16x16x16f16, where a
+// lane's B operand is k = 4q..4q+3. Layers 2 and 3 (K = 64) use the gfx950
+// v_mfma_f32_16x16x32f16 in two K = 32 chunks, where a lane's B operand is
+// k = 8q..8q+7; chunk c takes the lane's accumulator rows of the two 16-unit
+// tiles 2c and 2c+1 as they stand, i.e. its k order is
+//   k = 8q + j  <->  hidden unit 16 (2c + (j >= 4)) + 4q + (j & 3),
+// and the A operands (W2, W3) are packed on the host in that same order. A wave
+// evaluates its 64 entries as four column tiles of 16; all 64 lanes must be active.
 // ---------------------------------------------------------------------------
-// ReLU as a clamp to [0, FLT_MAX] (one v_med3_f32, no NaN canonicalisation),
-// then packed conversion to FP16.
+// ReLU after rounding to FP16: packed conversion (two v_cvt_pk_f16_f32) and a
+// packed maximum with zero (two v_pk_max on half pairs). Rounding commutes with
+// max(., 0), so this equals rounding the FP32 ReLU.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ half4_t relu_h4(float4_t v)
 {
+    half2_t lo, hi;
+    lo[0] = (_Float16)v[0];
+    lo[1] = (_Float16)v[1];
+    hi[0] = (_Float16)v[2];
+    hi[1] = (_Float16)v[3];
+    const half2_t z = {(_Float16)0.0f, (_Float16)0.0f};
+    lo = __builtin_elementwise_max(lo, z);
+    hi = __builtin_elementwise_max(hi, z);
     half4_t h;
-    h[0] = (_Float16)__builtin_amdgcn_fmed3f(v[0], 0.0f, 3.0e38f);
-    h[1] = (_Float16)__builtin_amdgcn_fmed3f(v[1], 0.0f, 3.0e38f);
-    h[2] = (_Float16)__builtin_amdgcn_fmed3f(v[2], 0.0f, 3.0e38f);
-    h[3] = (_Float16)__builtin_amdgcn_fmed3f(v[3], 0.0f, 3.0e38f);
+    h[0] = lo[0];
+    h[1] = lo[1];
+    h[2] = hi[0];
+    h[3] = hi[1];
     return h;
+}
+
+__device__ __forceinline__ half8_t cat8(half4_t lo, half4_t hi)
+{
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
 __device__ inline void mlp_wave(const MlpDev& M, float u0, float u1, float& y0, float& y1, float& y2)
@@ -142,28 +164,35 @@ __device__ inline void mlp_wave(const MlpDev& M, float u0, float u1, float& y0, 
             h1[nt][mt] = relu_h4(__builtin_amdgcn_mfma_f32_16x16x16f16(M.a1[mt * 64 + lane], b0, zero, 0, 0, 0));
     }
     // Layers 2 and 3, one 16-unit row block of layer 2 at a time: each weight
-    // fragment is read once per wave and applied to the four column tiles, which
-    // are four independent accumulation chains.
+    // fragment is read once per wave and applied to the four column tiles (four
+    // independent accumulation chains); layer 3 consumes a K chunk as soon as both
+    // of its layer-2 tiles are done.
     float4_t o[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
         for (int it = 0; it < 4; ++it) o[nt][it] = (q == 0 && it < 3) ? M.b3[it] : 0.0f;
+    half4_t h2[4][2];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         const float4_t bias = *reinterpret_cast<const float4_t*>(M.b2 + 16 * mt + 4 * q);
         float4_t acc[4] = {bias, bias, bias, bias};
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const half4_t a = M.a2[(mt * 4 + ks) * 64 + lane];
+        for (int c = 0; c < 2; ++c) {
+            const half8_t a = M.a2[(mt * 2 + c) * 64 + lane];
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, h1[nt][ks], acc[nt], 0, 0, 0);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, cat8(h1[nt][2 * c], h1[nt][2 * c + 1]), acc[nt],
+                                                                 0, 0, 0);
         }
-        const half4_t a3 = M.a3[mt * 64 + lane];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-            o[nt] = __builtin_amdgcn_mfma_f32_16x16x16f16(a3, relu_h4(acc[nt]), o[nt], 0, 0, 0);
+        for (int nt = 0; nt < 4; ++nt) h2[nt][mt & 1] = relu_h4(acc[nt]);
+        if (mt & 1) {
+            const half8_t a3 = M.a3[(mt >> 1) * 64 + lane];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                o[nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a3, cat8(h2[nt][0], h2[nt][1]), o[nt], 0, 0, 0);
+        }
     }
     // outputs of entry 16 nt + r sit in lane r (q == 0) of tile nt, items 0..2
     y0 = y1 = y2 = 0.0f;
@@ -193,23 +222,58 @@ struct LearnedOut {
     int reason;     // 0 accepted, else a BK_STAT_FB_* index
 };
 
+// 1/a for a normal positive double: hardware reciprocal refined by two Newton
+// steps (correct to about an ulp; no IEEE division sequence).
+__device__ __forceinline__ double recip(double a)
+{
+    double r = __builtin_amdgcn_rcp(a);
+    r = fma(r, fma(-a, r, 1.0), r);
+    return fma(r, fma(-a, r, 1.0), r);
+}
+
+// expm1(w) for 0 <= w <= 0.3 by its Taylor polynomial through w^14 (truncation
+// below 2e-18 relative); larger w, which the learned step floor does not produce
+// (h <= 0.54), go to the library routine.
+__device__ __forceinline__ double expm1_small(double w)
+{
+    if (!(w <= 0.3)) return expm1(w);
+    double p = 1.0 / 87178291200.0;                    // 1/14!
+    p = fma(p, w, 1.0 / 6227020800.0);
+    p = fma(p, w, 1.0 / 479001600.0);
+    p = fma(p, w, 1.0 / 39916800.0);
+    p = fma(p, w, 1.0 / 3628800.0);
+    p = fma(p, w, 1.0 / 362880.0);
+    p = fma(p, w, 1.0 / 40320.0);
+    p = fma(p, w, 1.0 / 5040.0);
+    p = fma(p, w, 1.0 / 720.0);
+    p = fma(p, w, 1.0 / 120.0);
+    p = fma(p, w, 1.0 / 24.0);
+    p = fma(p, w, 1.0 / 6.0);
+    p = fma(p, w, 0.5);
+    p = fma(p, w, 1.0);
+    return p * w;
+}
+
 __device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double thi, int N)
 {
     LearnedOut o;
     o.reason = 0;
-    const double h = (thi - tlo) / (double)N;
+    // any step works as long as the walk uses it consistently: an FP32 reciprocal of N
+    // puts the last node within ~1e-7 of t_hi
+    const double h = (thi - tlo) * (double)__builtin_amdgcn_rcpf((float)N);
     // coefficients at t_ref = t_lo; sinh^2(t/2) = (cosh t - 1) / 2 loses ~1e-16 absolute,
     // i.e. at most ~2e-13 relative in the scale for x <= 1e3, far inside this form's budget
-    const double e = exp(tlo), ei = 1.0 / e;
+    const double e = exp(tlo), ei = recip(e);
     const double ch = 0.5 * (e + ei), sh = 0.5 * (e - ei);
     o.delta = nu * tlo - kLn2 - x * (ch - 1.0);
     const double A = 0.5 * x * ch, B = 0.5 * x * sh;
     // outward walk from w = 0: V = expm1(w), Bw = e^w, Bb = e^-w <= 1, P = e^(-2 nu t)
-    const double qm1 = expm1(0.5 * h), q = qm1 + 1.0, qi = 1.0 / q;
+    const double qm1 = expm1_small(0.5 * h), q = qm1 + 1.0, qi = recip(q);
     const double rho = exp(-2.0 * nu * h), nh = nu * h;
     double V = 0.0, Bw = 1.0, Bb = 1.0;
     double P = (double)__expf((float)(-2.0 * nu * tlo));   // enters only through 1 + P
     float s = 0.0f, c = 0.0f, e0 = 0.0f, e1 = 0.0f, eprev = 0.0f, elast = 0.0f;
+#pragma unroll 2
     for (int m = 0; m <= N; ++m) {
         const double sg = V * (1.0 + Bb);                     // 2 sinh(u/2), u = m h >= 0
         const double xterm = sg * (A * sg + B * (Bw + Bb));   // x (cosh t - cosh t_lo)
@@ -249,21 +313,37 @@ __device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double
     return o;
 }
 
+// Step floor for the learned forms: the strip bound of node_step at a single
+// half-width, a = min(sqrt(2 (Lq + ln 2) / (x + nu + 1)), 1.3) (the maximiser of
+// the bound's small-a expansion, capped), in FP32 with 1 - cos a = 2 sin^2(a/2),
+// shrunk by 0.1% so that rounding can only add nodes. Any a in (0, pi/2) gives an
+// admissible step; over the grid law this one is within 6% of the best of the 15
+// candidates the plain solver tries (median 0.5%), for a fraction of the work.
+__device__ __forceinline__ float node_step_learned(float nu, float x, float Lq)
+{
+    const float c = Lq + 0.693147181f, nu1 = nu + 1.0f;
+    const float a = fminf(__fsqrt_rn(2.0f * c / (x + nu1)), 1.3f);
+    const float s = __sinf(0.5f * a);
+    const float den = c + 2.0f * x * s * s - nu1 * __logf(__cosf(a));
+    return 6.28318531f * 0.999f * a / den;
+}
+
 // Window from a prediction (normalised outputs y), with the model's margins; the
-// node count is the prediction or the strip-bound rule's count for this window,
+// node count is the prediction or the step floor's count for this window,
 // whichever is larger (raised says which).
 __device__ __forceinline__ void decode_window(const MlpDev& M, float y0, float y1, float y2, double nu, double x,
-                                              double Lq, const RuleTable& R, double& tlo, double& thi, int& N,
-                                              bool& raised)
+                                              double Lq, double& tlo, double& thi, int& N, bool& raised)
 {
     tlo = fmax(0.0, (double)(y0 * M.st - M.d_lo));
     thi = (double)(y1 * M.st + M.d_hi);
     float nf = ceilf(y2 * M.sn * (1.0f + M.eta) + M.n_add);
     if (!(nf >= (float)kNodeMin)) nf = (float)kNodeMin;
     if (nf > (float)kNodeMax) nf = (float)kNodeMax;
-    const int Nr = node_count(thi - tlo, node_step(nu, x, Lq, R));
-    raised = Nr > (int)nf;
-    N = raised ? Nr : (int)nf;
+    float nr = ceilf((float)(thi - tlo) / node_step_learned((float)nu, (float)x, (float)Lq));
+    if (!(nr >= (float)kNodeMin)) nr = (float)kNodeMin;
+    if (nr > (float)kNodeMax) nr = (float)kNodeMax;
+    raised = nr > nf;
+    N = (int)(raised ? nr : nf);
 }
 
 __device__ __forceinline__ bool in_box(const MlpDev& M, float lx, float v)
@@ -335,7 +415,7 @@ __device__ void block_stats_w(unsigned long long* stats, const unsigned long lon
 constexpr int kLearnedBlock = 512;
 constexpr int kSortBins = 64;
 
-__global__ __launch_bounds__(kLearnedBlock, 6) void k_besselk_learned(MlpDev M, const double* __restrict__ nu,
+__global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, const double* __restrict__ nu,
                                                                    const double* __restrict__ x,
                                                                    double* __restrict__ out, int64_t n, int result,
                                                                    double Lq, const RuleTable* __restrict__ Rp,
@@ -373,7 +453,7 @@ __global__ __launch_bounds__(kLearnedBlock, 6) void k_besselk_learned(MlpDev M, 
             } else {
                 bool raised;
                 int Nd;
-                decode_window(M, y0, y1, y2, v, z, Lq, *Rp, tlo, thi, Nd, raised);
+                decode_window(M, y0, y1, y2, v, z, Lq, tlo, thi, Nd, raised);
                 c_raised = raised ? 1u : 0u;
                 if (!(thi > tlo) || !isfinite(thi)) { reject = true; c_nonfin = 1; }
                 else N = Nd;
@@ -507,7 +587,7 @@ __device__ inline void tile_of_l(int64_t p, const TileGeomL& g, int64_t& I, int6
 }
 
 template <typename OutT>
-__global__ __launch_bounds__(256) void k_matern_learned(MlpDev M, const float* __restrict__ table,
+__global__ __launch_bounds__(256, 3) void k_matern_learned(MlpDev M, const float* __restrict__ table,
                                                         const double* __restrict__ lx_, const double* __restrict__ ly_,
                                                         TileGeomL g, int64_t tile_base, double sigma2,
                                                         double inv_beta, double nu, double pref, double L, double Lq,
@@ -552,8 +632,8 @@ __global__ __launch_bounds__(256) void k_matern_learned(MlpDev M, const float* _
                 double tlo, thi;
                 int N;
                 bool raised;
-                decode_window(M, fminf(t0[0], t1[0]), fmaxf(t0[1], t1[1]), fmaxf(t0[2], t1[2]), nu, z, Lq, *Rp, tlo,
-                              thi, N, raised);
+                decode_window(M, fminf(t0[0], t1[0]), fmaxf(t0[1], t1[1]), fmaxf(t0[2], t1[2]), nu, z, Lq, tlo, thi,
+                              N, raised);
                 if (thi > tlo && isfinite(thi)) {
                     LearnedOut lo = learned_sum(nu, z, tlo, thi, N);
                     ok = lo.reason == 0;
@@ -738,29 +818,36 @@ __global__ __launch_bounds__(256) void k_residuals(MlpDev M, const float* __rest
 // Host helpers
 // ---------------------------------------------------------------------------
 // FP16 operand pack from the FP32 master parameters (host arrays).
+// Hidden unit at position k = 8q + j of K chunk c of the 16x16x32 operands (see the
+// inference comment above).
+static int chunk_unit(int c, int q, int j) { return 16 * (2 * c + (j >= 4 ? 1 : 0)) + 4 * q + (j & 3); }
+
 static void pack_weights(const float* P, std::vector<_Float16>& pack, std::vector<float>& bias)
 {
     pack.assign((size_t)24 * 64 * 4, (_Float16)0.0f);
+    _Float16* A1 = pack.data();                 // [4 mt][64][4]
+    _Float16* A2 = pack.data() + 4 * 64 * 4;    // [4 mt][2 c][64][8]
+    _Float16* A3 = pack.data() + 20 * 64 * 4;   // [2 c][64][8]
     for (int mt = 0; mt < 4; ++mt)
         for (int lane = 0; lane < 64; ++lane) {
             const int r = lane & 15, q = lane >> 4, j = 16 * mt + r;
-            _Float16* a1 = &pack[((size_t)mt * 64 + lane) * 4];
+            _Float16* a1 = A1 + ((size_t)mt * 64 + lane) * 4;
             if (q == 0) {
                 a1[0] = (_Float16)P[kOffW1 + 2 * j];
                 a1[1] = (_Float16)P[kOffW1 + 2 * j + 1];
                 a1[2] = (_Float16)P[kOffB1 + j];
             }
-            for (int ks = 0; ks < 4; ++ks) {
-                _Float16* a2 = &pack[((size_t)(4 + mt * 4 + ks) * 64 + lane) * 4];
-                for (int it = 0; it < 4; ++it) a2[it] = (_Float16)P[kOffW2 + j * kH + 16 * ks + 4 * q + it];
+            for (int c = 0; c < 2; ++c) {
+                _Float16* a2 = A2 + ((size_t)(mt * 2 + c) * 64 + lane) * 8;
+                for (int jj = 0; jj < 8; ++jj) a2[jj] = (_Float16)P[kOffW2 + j * kH + chunk_unit(c, q, jj)];
             }
         }
-    for (int ks = 0; ks < 4; ++ks)
+    for (int c = 0; c < 2; ++c)
         for (int lane = 0; lane < 64; ++lane) {
             const int r = lane & 15, q = lane >> 4;
-            _Float16* a3 = &pack[((size_t)(20 + ks) * 64 + lane) * 4];
+            _Float16* a3 = A3 + ((size_t)c * 64 + lane) * 8;
             if (r < 3)
-                for (int it = 0; it < 4; ++it) a3[it] = (_Float16)P[kOffW3 + r * kH + 16 * ks + 4 * q + it];
+                for (int jj = 0; jj < 8; ++jj) a3[jj] = (_Float16)P[kOffW3 + r * kH + chunk_unit(c, q, jj)];
         }
     bias.assign(68, 0.0f);
     for (int j = 0; j < kH; ++j) bias[j] = P[kOffB2 + j];
