@@ -42,7 +42,7 @@ NODE_SLOTS = load_node_slots()
 # HBM bytes per launch of the learned kernel on the 2^24 grid, from the FETCH_SIZE and
 # WRITE_SIZE counter runs scaled by a plain 1 GiB copy (profiles/besselk_grid_2e24_hbm_traffic.txt),
 # valid only for the kernel sources they were taken on (hash below); else reported as null.
-TRAFFIC = {"src_sha": "aeeae0324c79e2a8", "n": 1 << 24, "bytes": 404.2e6}
+TRAFFIC = {"src_sha": "2b6d78ce3d629c1d", "n": 1 << 24, "bytes": 431.8e6}
 KERNEL_SOURCES = ("bk_mlp.hip", "bk_math.hpp", "bk_internal.hpp")
 
 
@@ -108,6 +108,32 @@ def time_form(api, torch, nu, x, out, form, steps, warmup, model, ws):
     return ev0.elapsed_time(ev1) / steps, wall / steps * 1e3
 
 
+def per_region(nu, x, e, half_idx, idx):
+    """Max relative error (of e^x K) on the sample by region: decades of x, the
+    peak regime (nu^2 <= x: peak at t = 0), order bands, the half-integer subset,
+    the paper's region x in [0.1, 140], x < 0.1 and the underflow zone x > 708."""
+    out = {}
+    dec = np.floor(np.log10(x)).astype(int)
+    for d in range(-4, 3):
+        m = dec == d
+        if m.any():
+            out["x 1e%d..1e%d" % (d, d + 1)] = float(e[m].max())
+    flat = nu * nu <= x
+    out["peak at 0 (nu^2<=x)"] = float(e[flat].max()) if flat.any() else None
+    out["interior peak"] = float(e[~flat].max()) if (~flat).any() else None
+    for lo, hi in ((0.01, 1.0), (1.0, 4.0), (4.0, 10.0 + 1e-9)):
+        m = (nu >= lo) & (nu < hi)
+        if m.any():
+            out["nu %g..%g" % (lo, round(hi))] = float(e[m].max())
+    h = np.isin(idx, half_idx)
+    if h.any():
+        out["half-integer nu"] = float(e[h].max())
+    for name, m in (("paper region x 0.1..140", (x >= 0.1) & (x <= 140)), ("x < 0.1", x < 0.1), ("x > 708", x > 708)):
+        if m.any():
+            out[name] = float(e[m].max())
+    return out
+
+
 def node_total(api, torch, nu, x, out, form, model, ws):
     stats = torch.zeros(api.STATS_LEN, dtype=torch.int64, device=x.device)
     api.besselk(nu, x, out=out, mode=form, model=model, workspace=ws, stats=stats)
@@ -170,6 +196,7 @@ def main():
     # oracle's own throughput on that sample (CPU baseline)
     cpu = None
     acc = {}
+    region = {}
     if not a.no_cpu:
         import oracle
         m = min(a.cpu_sample, a.n)
@@ -190,6 +217,7 @@ def main():
             torch.cuda.synchronize()
             e = np.abs(o.cpu().numpy() - ks_ref) / ks_ref
             acc[f] = float(e.max())
+            region[f] = per_region(nu_h[idx], x_h[idx], e, half_idx, idx)
 
     achieved = NODE_SLOTS[form] * head["node_total"] / (head["ms_per_step"] * 1e-3) / 1e12
     line = {
@@ -211,6 +239,7 @@ def main():
         "forms": {f: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()} for f, d in forms.items()},
         "speedup_vs_plain_f64": forms["plain"]["ms_per_step"] / head["ms_per_step"] if "plain" in forms else 1.0,
         "max_rel_err_sample": acc,
+        "max_rel_err_by_region": region,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (VALU lane-ops)",
                      "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": (TRAFFIC["bytes"] if (form == "learned" and a.n == TRAFFIC["n"]

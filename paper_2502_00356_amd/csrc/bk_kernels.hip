@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_besselk(const double* __restric
         p.N = s_i[1][tid];
         p.mc = s_i[2][tid];
         const double A = s_d[6][tid], B = s_d[7][tid];
-        const double S = (MODE == BK_PLAIN_F64) ? sum_f64(v3, p, A, B) : sum_mixed(v3, p, A, B);
+        const double S = (MODE == BK_PLAIN_F64) ? sum_f64(v3, p, A, B) : sum_mixed(v3, z3, p, A);
         out[(int64_t)blockIdx.x * kSolveBlock + l3] = assemble(z3, s_d[5][tid], p.h * S, result);
         nodes = (unsigned long long)(p.N + 1);
         ents = 1;
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(256) void k_matern(const double* __restrict__ lx,
                 }
             } else {
                 Solved s = plain_solve(nu, z, L, Lq, *Rp);
-                double S = (MODE == BK_PLAIN_F64) ? sum_f64(nu, s.p, s.A, s.B) : sum_mixed(nu, s.p, s.A, s.B);
+                double S = (MODE == BK_PLAIN_F64) ? sum_f64(nu, s.p, s.A, s.B) : sum_mixed(nu, z, s.p, s.A);
                 val = sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * (s.p.h * S);
             }
         }

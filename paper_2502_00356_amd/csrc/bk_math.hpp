@@ -285,23 +285,100 @@ __device__ inline double sum_f64(double nu, const Plan& p, double A, double B)
     return S - 0.5 * ends;
 }
 
-// Mixed form: exponent in FP64, exponential in FP32, Kahan-compensated FP32 sum.
-// Exponents are <= 0 up to a small positive excess (t_ref is within h/2 of t*),
-// so the FP32 argument error |d| 2^-24 only matters for negligible terms.
-__device__ inline double sum_mixed(double nu, const Plan& p, double A, double B)
+// 1/a for a normal positive double: hardware reciprocal refined by two Newton
+// steps (correct to about an ulp; no IEEE division sequence).
+__device__ __forceinline__ double recip(double a)
 {
-    Walk w = walk_begin(nu, p);
+    double r = __builtin_amdgcn_rcp(a);
+    r = fma(r, fma(-a, r, 1.0), r);
+    return fma(r, fma(-a, r, 1.0), r);
+}
+
+// expm1(w) for 0 <= w <= 0.3 by its Taylor polynomial through w^14 (truncation
+// below 2e-18 relative); larger w go to the library routine.
+__device__ __forceinline__ double expm1_small(double w)
+{
+    if (!(w <= 0.3)) return expm1(w);
+    double p = 1.0 / 87178291200.0;                    // 1/14!
+    p = fma(p, w, 1.0 / 6227020800.0);
+    p = fma(p, w, 1.0 / 479001600.0);
+    p = fma(p, w, 1.0 / 39916800.0);
+    p = fma(p, w, 1.0 / 3628800.0);
+    p = fma(p, w, 1.0 / 362880.0);
+    p = fma(p, w, 1.0 / 40320.0);
+    p = fma(p, w, 1.0 / 5040.0);
+    p = fma(p, w, 1.0 / 720.0);
+    p = fma(p, w, 1.0 / 120.0);
+    p = fma(p, w, 1.0 / 24.0);
+    p = fma(p, w, 1.0 / 6.0);
+    p = fma(p, w, 0.5);
+    p = fma(p, w, 1.0);
+    return p * w;
+}
+
+// Node walk of the FP32-term forms (mixed and learned). Their terms need the
+// exponent only to ~1e-9 absolute, so it is formed directly in FP64, in base 2,
+//   d_m = log2(e) (nu (t_m - t_ref) - x (cosh t_m - cosh t_ref)),
+// with cosh t_m from the three-term recurrence c_{m+1} = 2 cosh(h) c_m - c_{m-1}
+// run forward from t_0 (the growing solution: its relative error stays within a
+// few m^2 ulps), so the absolute error of d_m is about x cosh(t_m) m^2 2^-53,
+// below 1e-10 on the whole (nu, x) range. The factor Q = 1 + e^(-2 nu t) follows
+// Q' = rho Q + (1 - rho), rho = e^(-2 nu h) (contracting, so no error growth).
+struct WalkF {
+    double c, cn, kappa;      // cosh t_m, cosh t_{m+1}, 2 cosh h
+    double a2, b2, c2, mm;    // d_m = a2 c_m + mm b2 + c2, mm = m - m_ref
+    double Q, rho, omr;       // Q = 1 + e^(-2 nu t_m)
+};
+
+// e = e^{t_0}, ei = e^{-t_0} and q = e^{h/2}, qi = e^{-h/2} given by the caller.
+__device__ __forceinline__ WalkF walkf_begin(double nu, double x, double t0, double h, int mref, double xch_ref,
+                                             double e, double ei, double q, double qi)
+{
+    WalkF w;
+    const double q2 = q * q, qi2 = qi * qi;
+    w.kappa = q2 + qi2;
+    w.c = 0.5 * (e + ei);
+    w.cn = 0.5 * (e * q2 + ei * qi2);
+    w.a2 = -x * kLog2e;
+    w.b2 = nu * h * kLog2e;
+    w.c2 = xch_ref * kLog2e;
+    w.mm = -(double)mref;
+    w.rho = exp(-2.0 * nu * h);
+    w.omr = 1.0 - w.rho;              // absolute error 2^-53: Q's error stays ~m 2^-53
+    // Q only needs FP32 accuracy: e^(-2 nu t_0) in FP32 moves Q by < 6e-8 relative
+    w.Q = 1.0 + (double)__expf((float)(-2.0 * nu * t0));
+    return w;
+}
+
+__device__ __forceinline__ double walkf_exponent2(const WalkF& w) { return fma(w.a2, w.c, fma(w.mm, w.b2, w.c2)); }
+
+__device__ __forceinline__ void walkf_step(WalkF& w)
+{
+    const double c2n = fma(w.kappa, w.cn, -w.c);
+    w.c = w.cn;
+    w.cn = c2n;
+    w.mm += 1.0;
+    w.Q = fma(w.Q, w.rho, w.omr);
+}
+
+// Mixed form: the walk above with the reference at the node nearest the peak
+// (exponents <= about 0), exponential in FP32, Kahan-compensated FP32 sum.
+// A = x cosh(t_ref) / 2 from the solve. Returns sum_m c_m e^{d_m} (1 + P_m).
+__device__ inline double sum_mixed(double nu, double x, const Plan& p, double A)
+{
+    const double e = exp(p.t0), ei = recip(e);
+    const double q = 1.0 + expm1_small(0.5 * p.h), qi = recip(q);
+    WalkF w = walkf_begin(nu, x, p.t0, p.h, p.mc, 2.0 * A, e, ei, q, qi);
     float s = 0.0f, c = 0.0f, ends = 0.0f;
+#pragma unroll 2
     for (int m = 0; m <= p.N; ++m) {
-        float d = (float)walk_exponent(w, m, nu, A, B);
-        float e = __builtin_amdgcn_exp2f(d * 1.44269504f);
-        float term = e * (float)(1.0 + w.P);
-        float y = term - c;
-        float t = s + y;
+        const float term = __builtin_amdgcn_exp2f((float)walkf_exponent2(w)) * (float)w.Q;
+        const float y = term - c;
+        const float t = s + y;
         c = (t - s) - y;
         s = t;
-        if (m == 0 || m == p.N) ends += term;
-        walk_step(w, m);
+        ends += (m == 0 || m == p.N) ? term : 0.0f;
+        walkf_step(w);
     }
     return (double)s - (double)c - 0.5 * (double)ends;
 }

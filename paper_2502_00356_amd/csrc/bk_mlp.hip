@@ -222,38 +222,6 @@ struct LearnedOut {
     int reason;     // 0 accepted, else a BK_STAT_FB_* index
 };
 
-// 1/a for a normal positive double: hardware reciprocal refined by two Newton
-// steps (correct to about an ulp; no IEEE division sequence).
-__device__ __forceinline__ double recip(double a)
-{
-    double r = __builtin_amdgcn_rcp(a);
-    r = fma(r, fma(-a, r, 1.0), r);
-    return fma(r, fma(-a, r, 1.0), r);
-}
-
-// expm1(w) for 0 <= w <= 0.3 by its Taylor polynomial through w^14 (truncation
-// below 2e-18 relative); larger w, which the learned step floor does not produce
-// (h <= 0.54), go to the library routine.
-__device__ __forceinline__ double expm1_small(double w)
-{
-    if (!(w <= 0.3)) return expm1(w);
-    double p = 1.0 / 87178291200.0;                    // 1/14!
-    p = fma(p, w, 1.0 / 6227020800.0);
-    p = fma(p, w, 1.0 / 479001600.0);
-    p = fma(p, w, 1.0 / 39916800.0);
-    p = fma(p, w, 1.0 / 3628800.0);
-    p = fma(p, w, 1.0 / 362880.0);
-    p = fma(p, w, 1.0 / 40320.0);
-    p = fma(p, w, 1.0 / 5040.0);
-    p = fma(p, w, 1.0 / 720.0);
-    p = fma(p, w, 1.0 / 120.0);
-    p = fma(p, w, 1.0 / 24.0);
-    p = fma(p, w, 1.0 / 6.0);
-    p = fma(p, w, 0.5);
-    p = fma(p, w, 1.0);
-    return p * w;
-}
-
 __device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double thi, int N)
 {
     LearnedOut o;
@@ -261,25 +229,21 @@ __device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double
     // any step works as long as the walk uses it consistently: an FP32 reciprocal of N
     // puts the last node within ~1e-7 of t_hi
     const double h = (thi - tlo) * (double)__builtin_amdgcn_rcpf((float)N);
-    // coefficients at t_ref = t_lo; sinh^2(t/2) = (cosh t - 1) / 2 loses ~1e-16 absolute,
+    // reference t_ref = t_lo; sinh^2(t/2) = (cosh t - 1) / 2 loses ~1e-16 absolute,
     // i.e. at most ~2e-13 relative in the scale for x <= 1e3, far inside this form's budget
     const double e = exp(tlo), ei = recip(e);
-    const double ch = 0.5 * (e + ei), sh = 0.5 * (e - ei);
+    const double ch = 0.5 * (e + ei);
     o.delta = nu * tlo - kLn2 - x * (ch - 1.0);
-    const double A = 0.5 * x * ch, B = 0.5 * x * sh;
-    // outward walk from w = 0: V = expm1(w), Bw = e^w, Bb = e^-w <= 1, P = e^(-2 nu t)
-    const double qm1 = expm1_small(0.5 * h), q = qm1 + 1.0, qi = recip(q);
-    const double rho = exp(-2.0 * nu * h), nh = nu * h;
-    double V = 0.0, Bw = 1.0, Bb = 1.0;
-    double P = (double)__expf((float)(-2.0 * nu * tlo));   // enters only through 1 + P
+    const double q = 1.0 + expm1_small(0.5 * h), qi = recip(q);
+    WalkF w = walkf_begin(nu, x, tlo, h, 0, x * ch, e, ei, q, qi);
+    // the exponent is not bounded above here (t_lo is not the peak), so the FP32
+    // exponential is split as 2^k 2^f with k, f formed in FP64
     float s = 0.0f, c = 0.0f, e0 = 0.0f, e1 = 0.0f, eprev = 0.0f, elast = 0.0f;
 #pragma unroll 2
     for (int m = 0; m <= N; ++m) {
-        const double sg = V * (1.0 + Bb);                     // 2 sinh(u/2), u = m h >= 0
-        const double xterm = sg * (A * sg + B * (Bw + Bb));   // x (cosh t - cosh t_lo)
-        const double d = fma((double)m, nh, -xterm) * kLog2e;
+        const double d = walkf_exponent2(w);
         const double kf = rint(d);
-        float term = __builtin_amdgcn_exp2f((float)(d - kf)) * (float)(1.0 + P);
+        float term = __builtin_amdgcn_exp2f((float)(d - kf)) * (float)w.Q;
         term = ldexpf(term, (int)kf);
         const float yk = term - c;
         const float tk = s + yk;
@@ -289,10 +253,7 @@ __device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double
         e1 = (m == 1) ? term : e1;
         eprev = elast;
         elast = term;
-        V = fma(V, q, qm1);
-        Bw *= q;
-        Bb *= qi;
-        P *= rho;
+        walkf_step(w);
     }
     const float ends = e0 + elast;
     const float S = (s - c) - 0.5f * ends;
@@ -412,7 +373,7 @@ __device__ void block_stats_w(unsigned long long* stats, const unsigned long lon
 // through LDS, so each wave walks entries of similar N (the wave runs as many
 // node steps as its largest N). Phase 3 (sorted order): node sums, tail checks,
 // stores to the entry's own index or the fallback queue.
-constexpr int kLearnedBlock = 512;
+constexpr int kLearnedBlock = 256;
 constexpr int kSortBins = 64;
 
 __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, const double* __restrict__ nu,
@@ -528,7 +489,7 @@ __global__ __launch_bounds__(256) void k_besselk_fallback(const double* __restri
         const unsigned int i = queue[j];
         const double v = fabs(nu[i]), z = x[i];
         Solved s = plain_solve(v, z, L, Lq, *Rp);
-        const double S = sum_mixed(v, s.p, s.A, s.B);
+        const double S = sum_mixed(v, z, s.p, s.A);
         out[i] = assemble_k(z, s.delta, s.p.h * S, result);
         nodes += (unsigned long long)(s.p.N + 1);
         ents += 1;
@@ -645,7 +606,7 @@ __global__ __launch_bounds__(256, 3) void k_matern_learned(MlpDev M, const float
             }
             if (!ok) {
                 Solved s = plain_solve(nu, z, L, Lq, *Rp);
-                hs = s.p.h * sum_mixed(nu, s.p, s.A, s.B);
+                hs = s.p.h * sum_mixed(nu, z, s.p, s.A);
                 delta = s.delta;
             }
             val = sigma2 * exp(pref + nu * log(z) + (delta - z)) * hs;
