@@ -63,58 +63,73 @@ __device__ __forceinline__ double logcosh_pos(double y)
     return y + log1p(exp(-2.0 * y)) - kLn2;
 }
 
-// g(t) and g'(t) for t >= 0.
-__device__ __forceinline__ void g_and_gp(double nu, double x, double t, double& g, double& gp)
+// g and its first three derivatives at t >= 0 (g''' for Halley's method on g').
+struct GDer {
+    double g, g1, g2, g3;
+};
+
+__device__ __forceinline__ GDer g_derivs(double nu, double x, double t)
 {
-    double p = exp(-2.0 * nu * t);
+    GDer d;
+    const double p = exp(-2.0 * nu * t);
+    const double ip = 1.0 / (1.0 + p);
+    const double th = (1.0 - p) * ip;                 // tanh(nu t)
+    const double s2 = 4.0 * p * ip * ip;              // sech^2(nu t)
     double ch, sh;
     cosh_sinh(t, ch, sh);
-    g = nu * t + log1p(p) - kLn2 - x * ch;
-    gp = nu * (1.0 - p) / (1.0 + p) - x * sh;
+    d.g = nu * t + log1p(p) - kLn2 - x * ch;
+    d.g1 = nu * th - x * sh;
+    d.g2 = nu * nu * s2 - x * ch;
+    d.g3 = -2.0 * nu * nu * nu * th * s2 - x * sh;
+    return d;
 }
 
-// Maximiser t* of g over t >= 0 when nu^2 > x (Sec. IV-B: otherwise t* = 0).
-// g' = nu tanh(nu t) - x sinh t has one zero; since nu tanh < nu, the zero lies
-// left of asinh(nu/x). g' is concave (g''' < 0) and g'' < 0 right of t*, so
-// Newton started at asinh(nu/x) decreases monotonically onto t* (the bracket
-// search of FINDRANGE is replaced by this analytic upper bound).
+// Halley step for a root of f with derivatives f1, f2: 2 f f1 / (2 f1^2 - f f2),
+// or the Newton step f / f1 where the Halley denominator is not positive.
+__device__ __forceinline__ double halley_step(double f, double f1, double f2)
+{
+    const double den = 2.0 * f1 * f1 - f * f2;
+    return den > 0.0 ? 2.0 * f * f1 / den : f / f1;
+}
+
+// The three roots below are found by Halley's method (cubic convergence) and
+// stop once a step is below 1e-7 (peak) or 1e-5 (window ends) of t: the error
+// left after such a step is of order its cube, below 1e-15 relative.
+
+// Maximiser t* of g over t >= 0 when nu^2 > x (Sec. IV-B: otherwise t* = 0), the
+// zero of g' = nu tanh(nu t) - x sinh t. Since nu tanh < nu, it lies left of
+// asinh(nu/x), where the iteration starts (the bracket search of FINDRANGE is
+// replaced by this analytic upper bound); g' is decreasing right of t* and steps
+// that would leave t > 0 are halved.
 __device__ inline double peak_solve(double nu, double x)
 {
     double t = asinh(fmin(nu / x, 1e300));
     for (int it = 0; it < 64; ++it) {
-        double p = exp(-2.0 * nu * t);
-        double ip = 1.0 / (1.0 + p);
-        double th = (1.0 - p) * ip;
-        double s2 = 4.0 * p * ip * ip;
-        double ch, sh;
-        cosh_sinh(t, ch, sh);
-        double gp = nu * th - x * sh;
-        double gpp = nu * nu * s2 - x * ch;
-        double dt = gp / gpp;
-        if (!(dt > 0.0)) break;           // at (or numerically past) the root
-        t -= dt;
-        if (dt <= 1e-14 * t || t < 1e-150) break;
+        const GDer d = g_derivs(nu, x, t);
+        const double dt = halley_step(d.g1, d.g2, d.g3);
+        double tn = t - dt;
+        if (!(tn > 0.0)) tn = 0.5 * t;
+        t = tn;
+        if (!(fabs(dt) > 1e-7 * t) || t < 1e-150) break;
     }
     return t;
 }
 
 // Root t1 > t* of G(t) = g(t) - gstar + L (g concave and decreasing beyond t*).
-// Start at lo = acosh(cosh t* + L/x): there the x-term alone has dropped by L
-// and the log cosh term has grown, so G(lo) >= 0 (FINDRANGE's lower end). The
-// first Newton step from lo lands on or right of the root because G is concave;
-// from there Newton decreases monotonically onto it.
+// Start at acosh(cosh t* + L/x): there the x-term alone has dropped by L and the
+// log cosh term has grown, so G >= 0 (FINDRANGE's lower end). Iterates are kept
+// in (t*, t* + 4 (start - t*) + 1].
 __device__ inline double window_right(double nu, double x, double tstar, double chstar,
                                       double gstar, double L)
 {
     double t = acosh(chstar + L / x);
-    double tcap = tstar + 4.0 * (t - tstar) + 1.0;     // guard against a flat first step
+    const double tcap = tstar + 4.0 * (t - tstar) + 1.0;
     for (int it = 0; it < 64; ++it) {
-        double g, gp;
-        g_and_gp(nu, x, t, g, gp);
-        double dt = (g - gstar + L) / gp;
+        const GDer d = g_derivs(nu, x, t);
+        const double dt = halley_step(d.g - gstar + L, d.g1, d.g2);
         double tn = fmin(t - dt, tcap);
         if (!(tn > tstar)) tn = 0.5 * (t + tstar);
-        bool done = fabs(tn - t) <= 1e-14 * t;
+        const bool done = !(fabs(tn - t) > 1e-5 * t);
         t = tn;
         if (done) break;
     }
@@ -122,20 +137,19 @@ __device__ inline double window_right(double nu, double x, double tstar, double 
 }
 
 // Root t0 in (0, t*) of G when G(0) < 0 (only possible if nu t* > L, since g' <= nu).
-// Bracket: G(0) < 0 and G(t* - L/nu) >= 0. Newton, with a bisection step whenever
-// a Newton step would leave the bracket; converged when the Newton step is below
-// the tolerance.
+// Bracket: G(0) < 0 and G(t* - L/nu) >= 0, shrunk at every iterate; a step that
+// would leave it is replaced by bisection.
 __device__ inline double window_left(double nu, double x, double tstar, double gstar, double L)
 {
     double lo = 0.0, hi = fmax(tstar - L / nu, 0.0);
     double t = hi;
     for (int it = 0; it < 100; ++it) {
-        double g, gp;
-        g_and_gp(nu, x, t, g, gp);
-        double G = g - gstar + L;
+        const GDer d = g_derivs(nu, x, t);
+        const double G = d.g - gstar + L;
         if (G >= 0.0) hi = t; else lo = t;
-        double tn = t - G / gp;
-        if (fabs(tn - t) <= 1e-14 * t) { t = fmin(fmax(tn, lo), hi); break; }
+        const double dt = halley_step(G, d.g1, d.g2);
+        double tn = t - dt;
+        if (!(fabs(dt) > 1e-5 * t)) { t = fmin(fmax(tn, lo), hi); break; }
         if (!(tn >= lo && tn <= hi)) tn = 0.5 * (lo + hi);
         t = tn;
         if (hi - lo <= 1e-15 * hi) break;
