@@ -165,7 +165,8 @@ __device__ __forceinline__ double assemble(double z, double delta, double hs, in
     if (result == BK_RESULT_SCALED) return exp(delta) * hs;
     if (result == BK_RESULT_LOG) return (delta - z) + log(hs);
     if (z < 708.0) return exp(-z) * exp(delta) * hs;   // exp(-z) still a normal number
-    return exp((delta - z) + log(hs));                   // subnormal range: one rounding
+    // subnormal range: e^(-z) formed 2^64 larger, product scaled back (one rounding)
+    return ldexp(exp(64.0 * kLn2 - z) * exp(delta) * hs, -64);
 }
 
 // Counting sort of a block's lanes by a small key (0..63): returns the lane's slot
@@ -334,7 +335,7 @@ __device__ __forceinline__ double unscale(double z, double s, int result)
 {
     if (result == BK_RESULT_SCALED) return s;
     if (z < 708.0) return exp(-z) * s;
-    return exp(log(s) - z);
+    return ldexp(exp(64.0 * kLn2 - z) * s, -64);
 }
 
 // K_nu(x), dK/dx and dK/dnu, one lane per entry, FP64: the K integral at orders

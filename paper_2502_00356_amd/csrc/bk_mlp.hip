@@ -137,6 +137,12 @@ __device__ __forceinline__ half4_t relu_h4(float4_t v)
     return h;
 }
 
+// Cross-lane read of v from the lane whose byte address (4 x lane) is addr.
+__device__ __forceinline__ float bperm(int addr, float v)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+
 __device__ __forceinline__ half8_t cat8(half4_t lo, half4_t hi)
 {
     return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
@@ -152,8 +158,9 @@ __device__ inline void mlp_wave(const MlpDev& M, float u0, float u1, float& y0, 
     half4_t h1[4][4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        const float e0 = __shfl(u0, 16 * nt + r, 64);
-        const float e1 = __shfl(u1, 16 * nt + r, 64);
+        const int src = (16 * nt + r) << 2;
+        const float e0 = bperm(src, u0);
+        const float e1 = bperm(src, u1);
         half4_t b0;
         b0[0] = (_Float16)(q == 0 ? e0 : 0.0f);
         b0[1] = (_Float16)(q == 0 ? e1 : 0.0f);
@@ -198,7 +205,7 @@ __device__ inline void mlp_wave(const MlpDev& M, float u0, float u1, float& y0, 
     y0 = y1 = y2 = 0.0f;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        const float s0 = __shfl(o[nt][0], r, 64), s1 = __shfl(o[nt][1], r, 64), s2 = __shfl(o[nt][2], r, 64);
+        const float s0 = bperm(r << 2, o[nt][0]), s1 = bperm(r << 2, o[nt][1]), s2 = bperm(r << 2, o[nt][2]);
         if (q == nt) { y0 = s0; y1 = s1; y2 = s2; }
     }
 }
@@ -319,8 +326,11 @@ __device__ __forceinline__ double assemble_k(double z, double delta, double hs, 
 {
     if (result == BK_RESULT_SCALED) return exp(delta) * hs;
     if (result == BK_RESULT_LOG) return (delta - z) + log(hs);
-    if (z < 708.0) return exp(delta - z) * hs;
-    return exp((delta - z) + log(hs));
+    // where e^(Delta - z) would be subnormal, form it 2^64 larger and scale the
+    // product back, so that only the final result rounds into the subnormal range
+    const double r = delta - z;
+    const double sc = r < -700.0 ? 64.0 : 0.0;
+    return ldexp(exp(fma(sc, kLn2, r)) * hs, -(int)sc);
 }
 
 __device__ __forceinline__ bool special_k(double v, double z, int result, double& r)
