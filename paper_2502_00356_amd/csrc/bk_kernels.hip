@@ -341,7 +341,7 @@ __device__ __forceinline__ double unscale(double z, double s, int result)
 // K_nu(x), dK/dx and dK/dnu, one lane per entry, FP64: the K integral at orders
 // nu and |nu - 1| and the dK/dnu integral, each with its own plain solve. NULL
 // outputs are skipped (dK/dx still evaluates K_nu). dK/dnu carries the sign of nu.
-__global__ __launch_bounds__(256) void k_besselk_deriv(const double* __restrict__ nu, const double* __restrict__ x,
+__global__ __launch_bounds__(256, 3) void k_besselk_deriv(const double* __restrict__ nu, const double* __restrict__ x,
                                                        double* __restrict__ k, double* __restrict__ dkdx,
                                                        double* __restrict__ dkdnu, int64_t n, int result, double L,
                                                        double Lq, const RuleTable* __restrict__ Rp,

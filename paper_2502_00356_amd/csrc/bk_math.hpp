@@ -422,30 +422,44 @@ __device__ inline double sum_mixed(double nu, double x, const Plan& p, double A)
 // and Q = 1 - P follows Q' = Q rho + (1 - rho) (rho = e^(-2 nu h)), a recurrence
 // that never amplifies Q's relative error.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void dnu_log_and_slope(double nu, double x, double t, double& d, double& dp)
+// d and its first three derivatives at t > 0:
+//   d'   = 1/t + nu coth(nu t) - x sinh t
+//   d''  = -1/t^2 - nu^2 csch^2(nu t) - x cosh t
+//   d''' = 2/t^3 + 2 nu^3 coth(nu t) csch^2(nu t) - x sinh t
+struct DDer {
+    double d, d1, d2, d3;
+};
+
+__device__ __forceinline__ DDer dnu_derivs(double nu, double x, double t)
 {
+    DDer r;
     const double omp = -expm1(-2.0 * nu * t);        // 1 - e^(-2 nu t)
+    const double p = 1.0 - omp;
+    const double it = 1.0 / t, io = 1.0 / omp;
+    const double cth = (2.0 - omp) * io;               // coth(nu t)
+    const double cs2 = 4.0 * p * io * io;              // csch^2(nu t)
     double ch, sh;
     cosh_sinh(t, ch, sh);
-    d = log(t) + nu * t + log(omp) - kLn2 - x * ch;
-    dp = 1.0 / t + nu * (2.0 - omp) / omp - x * sh;
+    r.d = log(t) + nu * t + log(omp) - kLn2 - x * ch;
+    r.d1 = it + nu * cth - x * sh;
+    r.d2 = -it * it - nu * nu * cs2 - x * ch;
+    r.d3 = 2.0 * it * it * it + 2.0 * nu * nu * nu * cth * cs2 - x * sh;
+    return r;
 }
 
+// Maximiser t_d of d: Halley on d' inside the bracket above (bisection when a step
+// leaves it), stopped once a step is below 1e-7 of t.
 __device__ inline double dnu_peak(double nu, double x)
 {
     double lo = fmax(asinh(nu / x), fmin(1.0, sqrt(1.70 / x)));
     double hi = asinh((2.0 / lo + nu) / x);
     double t = 0.5 * (lo + hi);
     for (int it = 0; it < 100; ++it) {
-        const double omp = -expm1(-2.0 * nu * t);
-        const double p = 1.0 - omp;
-        double ch, sh;
-        cosh_sinh(t, ch, sh);
-        const double f = 1.0 / t + nu * (1.0 + p) / omp - x * sh;
-        const double fp = -1.0 / (t * t) - 4.0 * nu * nu * p / (omp * omp) - x * ch;
-        if (f > 0.0) lo = t; else hi = t;
-        double tn = t - f / fp;
-        if (fabs(tn - t) <= 1e-14 * t) { t = fmin(fmax(tn, lo), hi); break; }
+        const DDer r = dnu_derivs(nu, x, t);
+        if (r.d1 > 0.0) lo = t; else hi = t;
+        const double dt = halley_step(r.d1, r.d2, r.d3);
+        double tn = t - dt;
+        if (!(fabs(dt) > 1e-7 * t)) { t = fmin(fmax(tn, lo), hi); break; }
         if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
         t = tn;
         if (hi - lo <= 1e-15 * hi) break;
@@ -453,20 +467,19 @@ __device__ inline double dnu_peak(double nu, double x)
     return t;
 }
 
-// Root t1 > t_d of d(t) = dstar - L. Start at acosh(cosh t_d + L/x), where the
-// x term alone has dropped by L while log t + log sinh(nu t) grew, so the start is
-// left of the root; d is concave, so the first Newton step lands right of the root
-// and Newton then decreases monotonically onto it.
+// Root t1 > t_d of d(t) = dstar - L by Halley, from acosh(cosh t_d + L/x): there
+// the x term alone has dropped by L while log t + log sinh(nu t) grew, so the start
+// is left of the root. Iterates are kept in (t_d, t_d + 4 (start - t_d) + 1].
 __device__ inline double dnu_window_right(double nu, double x, double td, double chd, double dstar, double L)
 {
     double t = acosh(chd + L / x);
     const double tcap = td + 4.0 * (t - td) + 1.0;
     for (int it = 0; it < 64; ++it) {
-        double d, dp;
-        dnu_log_and_slope(nu, x, t, d, dp);
-        double tn = fmin(t - (d - dstar + L) / dp, tcap);
+        const DDer r = dnu_derivs(nu, x, t);
+        const double dt = halley_step(r.d - dstar + L, r.d1, r.d2);
+        double tn = fmin(t - dt, tcap);
         if (!(tn > td)) tn = 0.5 * (t + td);
-        const bool done = fabs(tn - t) <= 1e-14 * t;
+        const bool done = !(fabs(tn - t) > 1e-5 * t);
         t = tn;
         if (done) break;
     }
@@ -480,11 +493,10 @@ __device__ inline double dnu_window_right(double nu, double x, double td, double
 __device__ inline Solved dnu_solve(double nu, double x, double t0, double L, double Lq, const RuleTable& R)
 {
     const double td = dnu_peak(nu, x);
-    double d, dp;
-    dnu_log_and_slope(nu, x, td, d, dp);
+    const DDer r = dnu_derivs(nu, x, td);
     double chd, shd;
     cosh_sinh(td, chd, shd);
-    const double t1 = dnu_window_right(nu, x, td, chd, d, L);
+    const double t1 = dnu_window_right(nu, x, td, chd, r.d, L);
     const double extra = log1p(1.5707963267948966 / td) - log(tanh(nu * td));
     return plan_window(nu, x, t0, t1, td, node_step(nu, x, Lq + extra, R));
 }
