@@ -6,7 +6,9 @@
 // which g(t) >= g(t*) - L, and the trapezoid sum is taken relative to a reference
 // point t_ref (Eq. "refined": log K = g(t_ref) + log sum h c_m exp(g(t_m) - g(t_ref))).
 //
-// Node terms are built without cancellation. With u = t - t_ref, w = u/2:
+// The plain FP64 form builds its node terms without cancellation (below); the
+// FP32-term forms form the exponent directly (WalkF, further down), which their
+// precision allows. With u = t - t_ref, w = u/2:
 //   g(t) - g(t_ref) = nu u + log(1+P(t)) - log(1+P(t_ref)) - xterm,
 //   P(t) = exp(-2 nu t),   xterm = x (cosh t - cosh t_ref)
 //                                = 2 sinh w (x cosh t_ref sinh w + x sinh t_ref cosh w),
