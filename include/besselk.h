@@ -153,7 +153,9 @@ typedef struct {
  * whole n x n column-major matrix.
  * out : device buffer of bk_matern_out_elems(n, tile_size, lower_only) elements
  *       of params->out_dtype. params->mode selects the form (BK_LEARNED needs a
- *       model; the Matern path uses no workspace). */
+ *       model; the Matern path uses no caller workspace: the learned form rebuilds
+ *       the model's window table for params->nu and uses the model's fallback list,
+ *       so learned Matern calls that share a model must not overlap). */
 int bk_matern_tiles(const bk_locs* locs, const bk_params* params, int32_t tile_size,
                     int32_t lower_only, void* out, hipStream_t stream);
 

@@ -51,6 +51,10 @@ static_assert(kNParam == BK_MLP_NPARAM, "parameter count");
 // and FP32 node rounding (~2e-7) this keeps the total well inside 2e-6.
 constexpr float kTailTol = 3e-7f;
 constexpr int kTableSize = 1024;       // Matern: MLP tabulated over log10 x at fixed nu
+// Matern learned launches: at most 2^21 workgroups (2^23 waves) each, so the
+// model's fallback list (one entry per wave with a rejected entry) never overflows.
+constexpr int64_t kMaternWgPerLaunch = 1LL << 21;
+constexpr int64_t kMaternWavesPerLaunch = kMaternWgPerLaunch * 4;
 
 // Device-side constants of a model for inference.
 struct MlpDev {
@@ -71,6 +75,7 @@ struct bk_model {
     half4_t* pack = nullptr;      // device FP16 operand pack (a1, a2, a3)
     float* bias = nullptr;        // device b2 (64) and b3 (3)
     float* table = nullptr;       // device Matern window table [kTableSize][4]
+    unsigned int* mlist = nullptr; // device Matern fallback list: count at [0], wave ids from [64]
     double norm[8] = {-0.5, 3.5, 5.005, 4.995, 8.0, 32.0, 0.0, 0.0};
     double box[4] = {-4.0, 3.0, 0.01, 10.0};
     double margins[4] = {0.05, 0.05, 0.05, 1.0};
@@ -557,12 +562,16 @@ __device__ inline void tile_of_l(int64_t p, const TileGeomL& g, int64_t& I, int6
     I = J + (p - (J * T - J * (J - 1) / 2));
 }
 
+// Learned Matern. An entry the learned form rejects is written as NaN and its
+// wave is appended to the model's fallback list; k_matern_fallback then recomputes
+// the NaN entries of the listed waves with the mixed form. Keeping the fallback out
+// of this kernel keeps its registers (and so its occupancy) those of the learned pass.
 template <typename OutT>
-__global__ __launch_bounds__(256, 3) void k_matern_learned(MlpDev M, const float* __restrict__ table,
+__global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float* __restrict__ table,
                                                         const double* __restrict__ lx_, const double* __restrict__ ly_,
                                                         TileGeomL g, int64_t tile_base, double sigma2,
-                                                        double inv_beta, double nu, double pref, double L, double Lq,
-                                                        const RuleTable* __restrict__ Rp, OutT* __restrict__ out)
+                                                        double inv_beta, double nu, double pref, double Lq,
+                                                        unsigned int* __restrict__ mlist, OutT* __restrict__ out)
 {
     constexpr int kColsPerWave = 8, kColsPerGroup = 32;
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
@@ -583,14 +592,13 @@ __global__ __launch_bounds__(256, 3) void k_matern_learned(MlpDev M, const float
     const int cend = (int)min((int64_t)kColsPerWave, nJ - jl0);
     const float tscale = (float)(kTableSize - 1) / (M.lx_hi - M.lx_lo);
     const bool nu_ok = (float)nu >= M.nu_lo && (float)nu <= M.nu_hi;
+    bool rejected = false;
     for (int c = 0; c < cend; ++c) {
         const int64_t jl = jl0 + c;
         const double dx = lx_[J * g.ts + jl] - xi, dy = ly_[J * g.ts + jl] - yi;
         const double rr = sqrt(dx * dx + dy * dy);
-        double val;
-        if (rr == 0.0) {
-            val = sigma2;
-        } else {
+        double val = sigma2;
+        if (rr != 0.0) {
             const double z = rr * inv_beta;
             const float lz = __log2f((float)z) * 0.30102999566f;
             bool ok = nu_ok && lz >= M.lx_lo && lz <= M.lx_hi;
@@ -614,14 +622,63 @@ __global__ __launch_bounds__(256, 3) void k_matern_learned(MlpDev M, const float
                     ok = false;
                 }
             }
-            if (!ok) {
-                Solved s = plain_solve(nu, z, L, Lq, *Rp);
-                hs = s.p.h * sum_mixed(nu, z, s.p, s.A);
-                delta = s.delta;
+            if (ok) {
+                val = sigma2 * exp(pref + nu * log(z) + (delta - z)) * hs;
+            } else {
+                val = __builtin_nan("");
+                rejected = true;
             }
-            val = sigma2 * exp(pref + nu * log(z) + (delta - z)) * hs;
         }
         out[base + il + jl * mI] = (OutT)val;
+    }
+    // lane 0 is active whenever any lane of the wave is (rows grow with the lane)
+    if (__ballot(rejected) != 0ull && lane == 0) {
+        const unsigned int slot = atomicAdd(mlist, 1u);
+        mlist[64 + slot] = (unsigned int)(blockIdx.x * 4 + wave);
+    }
+}
+
+// Fallback of the learned Matern kernel: each wave takes listed waves (grid-stride),
+// re-derives their rows and columns, and recomputes the NaN entries with the mixed
+// form (FP64 solve, FP32 node terms).
+template <typename OutT>
+__global__ __launch_bounds__(256) void k_matern_fallback(const double* __restrict__ lx_, const double* __restrict__ ly_,
+                                                         TileGeomL g, int64_t tile_base, double sigma2,
+                                                         double inv_beta, double nu, double pref, double L, double Lq,
+                                                         const RuleTable* __restrict__ Rp,
+                                                         const unsigned int* __restrict__ mlist, OutT* __restrict__ out)
+{
+    constexpr int kColsPerWave = 8, kColsPerGroup = 32;
+    const unsigned int cnt = mlist[0];
+    const int lane = threadIdx.x & 63;
+    const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
+    for (unsigned int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < cnt; w += gridDim.x * 4) {
+        const unsigned int id = mlist[64 + w];
+        const int64_t blk = id >> 2;
+        const int wave = (int)(id & 3u);
+        const int64_t p = tile_base + blk / wg_per_tile;
+        const int64_t local = blk % wg_per_tile;
+        const int rb = (int)(local % g.rb_per_tile), cb = (int)(local / g.rb_per_tile);
+        int64_t I, J;
+        tile_of_l(p, g, I, J);
+        const int64_t mI = min((int64_t)g.ts, g.n - I * g.ts);
+        const int64_t nJ = min((int64_t)g.ts, g.n - J * g.ts);
+        const int64_t il = (int64_t)rb * 64 + lane;
+        const int64_t jl0 = (int64_t)cb * kColsPerGroup + (int64_t)wave * kColsPerWave;
+        if (il >= mI || jl0 >= nJ) continue;
+        const int64_t base = tile_offset_l(g.n, g.ts, g.T, g.lower, I, J);
+        const double xi = lx_[I * g.ts + il], yi = ly_[I * g.ts + il];
+        const int cend = (int)min((int64_t)kColsPerWave, nJ - jl0);
+        for (int c = 0; c < cend; ++c) {
+            const int64_t o = base + il + (jl0 + c) * mI;
+            if (!isnan((double)out[o])) continue;
+            const int64_t jl = jl0 + c;
+            const double dx = lx_[J * g.ts + jl] - xi, dy = ly_[J * g.ts + jl] - yi;
+            const double z = sqrt(dx * dx + dy * dy) * inv_beta;
+            const Solved s = plain_solve(nu, z, L, Lq, *Rp);
+            const double hs = s.p.h * sum_mixed(nu, z, s.p, s.A);
+            out[o] = (OutT)(sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * hs);
+        }
     }
 }
 
@@ -833,6 +890,8 @@ static int model_alloc(bk_model* m)
     if (hipMalloc((void**)&m->pack, sizeof(_Float16) * 24 * 64 * 4) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->bias, sizeof(float) * 68) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->table, sizeof(float) * 4 * kTableSize) != hipSuccess) return BK_ENOMEM;
+    if (hipMalloc((void**)&m->mlist, sizeof(unsigned int) * (64 + (size_t)kMaternWavesPerLaunch)) != hipSuccess)
+        return BK_ENOMEM;
     return BK_OK;
 }
 
@@ -914,18 +973,24 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
     const double nu = prm->nu;
     const double pref = (1.0 - nu) * kLn2 - lgamma(nu);
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
-    const int64_t max_wg = 1LL << 23;
-    const int64_t tiles_per_launch = max_wg / wg_per_tile > 0 ? max_wg / wg_per_tile : 1;
+    const int64_t tiles_per_launch = kMaternWgPerLaunch / wg_per_tile > 0 ? kMaternWgPerLaunch / wg_per_tile : 1;
+    if (wg_per_tile > kMaternWgPerLaunch) return BK_EINVAL;   // a tile side beyond 2^14 rows / 2^12 column blocks
+    const double ib = 1.0 / prm->beta;
     for (int64_t t0 = 0; t0 < ntiles; t0 += tiles_per_launch) {
         const int64_t nt = ntiles - t0 < tiles_per_launch ? ntiles - t0 : tiles_per_launch;
-        if (prm->out_dtype == BK_OUT_F32)
-            hipLaunchKernelGGL(k_matern_learned<float>, dim3((unsigned)(nt * wg_per_tile)), dim3(256), 0, stream, M,
-                               m->table, locs->x, locs->y, g, t0, prm->sigma2, 1.0 / prm->beta, nu, pref, L, Lq,
-                               R, (float*)out);
-        else
-            hipLaunchKernelGGL(k_matern_learned<double>, dim3((unsigned)(nt * wg_per_tile)), dim3(256), 0, stream, M,
-                               m->table, locs->x, locs->y, g, t0, prm->sigma2, 1.0 / prm->beta, nu, pref, L, Lq,
-                               R, (double*)out);
+        const dim3 grid((unsigned)(nt * wg_per_tile));
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, m->mlist);
+        if (prm->out_dtype == BK_OUT_F32) {
+            hipLaunchKernelGGL(k_matern_learned<float>, grid, dim3(256), 0, stream, M, m->table, locs->x, locs->y, g,
+                               t0, prm->sigma2, ib, nu, pref, Lq, m->mlist, (float*)out);
+            hipLaunchKernelGGL(k_matern_fallback<float>, dim3(1024), dim3(256), 0, stream, locs->x, locs->y, g, t0,
+                               prm->sigma2, ib, nu, pref, L, Lq, R, m->mlist, (float*)out);
+        } else {
+            hipLaunchKernelGGL(k_matern_learned<double>, grid, dim3(256), 0, stream, M, m->table, locs->x, locs->y, g,
+                               t0, prm->sigma2, ib, nu, pref, Lq, m->mlist, (double*)out);
+            hipLaunchKernelGGL(k_matern_fallback<double>, dim3(1024), dim3(256), 0, stream, locs->x, locs->y, g, t0,
+                               prm->sigma2, ib, nu, pref, L, Lq, R, m->mlist, (double*)out);
+        }
         if (hipGetLastError() != hipSuccess) return BK_EHIP;
     }
     return BK_OK;
@@ -955,6 +1020,7 @@ extern "C" void bk_model_destroy(bk_model* m)
     if (m->pack) (void)hipFree(m->pack);
     if (m->bias) (void)hipFree(m->bias);
     if (m->table) (void)hipFree(m->table);
+    if (m->mlist) (void)hipFree(m->mlist);
     delete m;
 }
 

@@ -176,6 +176,26 @@ def test_zero_weights_force_fallback(api, orc):
     assert s[api.STAT_FB_TAIL] + s[api.STAT_FB_NONFINITE] == nu.size
 
 
+def test_zero_weights_force_matern_fallback(api, orc):
+    """Learned Matern tiles with an all-zero model: every off-diagonal entry is
+    rejected, marked and recomputed by the fallback kernel from the model's list of
+    waves (three tile rows with a ragged last one, FP64 and FP32 output)."""
+    import torch
+    from paper_2502_00356_amd import workloads as w
+    m = api.Model()
+    m.set_params(torch.zeros(api.MLP_NPARAM))
+    xy = w.uniform_locations(170, seed=53)
+    lx, ly = to_dev(xy[:, 0]), to_dev(xy[:, 1])
+    R = orc.matern_full(xy, 1.3, 0.05, 1.7)
+    for dt in (api.OUT_F64, api.OUT_F32):
+        out = api.matern_tiles(lx, ly, 1.3, 0.05, 1.7, 64, 1, mode="learned", model=m, out_dtype=dt)
+        torch.cuda.synchronize()
+        A = api.unpack_tiles(out, 170, 64, 1).double().numpy()
+        assert np.all(np.isfinite(A))
+        mm = R > 1e-300
+        assert rel_err(A[mm], R[mm]).max() <= TOL_MIXED + (2 ** -24 if dt == api.OUT_F32 else 0.0)
+
+
 def test_halved_node_prediction_is_raised(api, orc, trained, tmp_path):
     """Halving the predicted node count (through the output scale) leaves the step
     too coarse; the strip-bound rule raises N for those entries and the bar holds."""
