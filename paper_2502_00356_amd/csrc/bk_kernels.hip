@@ -1,9 +1,11 @@
 // bk_kernels.hip - HIP kernels and C ABI for standalone K_nu(x), the window
-// export and tiled Matern covariance generation (arXiv 2502.00356, Sec. IV-B,
-// Sec. III-A, Alg. 3), for gfx950.
+// export, tiled Matern covariance generation (arXiv 2502.00356, Sec. IV-B,
+// Sec. III-A, Alg. 3), the paper's refined algorithm (Sec. IV-A, IV-C, Alg. 2),
+// and the derivatives of K_nu and of the Matern covariance, for gfx950.
 //
-// Mapping: one lane per output entry, 256-lane workgroups (four wave64s).
-// Standalone: entry i = global lane id, coalesced FP64 loads/stores.
+// Mapping: one lane per output entry. Standalone K_nu: 512-entry workgroups whose
+// entries are re-sorted through LDS between phases (coalesced FP64 loads, stores
+// to each entry's own index); the other kernels: 256-lane workgroups.
 // Matern: each wave covers 64 consecutive rows of a tile column (one 512-byte
 // FP64 or 256-byte FP32 store per column); the row location lives in VGPRs and
 // the column location is wave-uniform, so it is read through scalar loads

@@ -5,17 +5,16 @@
 //
 // The learned form replaces the per-entry peak/window solve of Sec. IV-B with a
 // prediction of [t_lo, t_hi] and the node count N from (log10 x, nu). The node
-// sum is taken relative to t_lo (the first node), so every node lies at or
-// right of the reference and the outward recurrences of bk_math.hpp apply. Node
-// exponents can then be large and positive; the FP32 exponential is split as
-// 2^k 2^f with k integer and f in [-1/2, 1/2] formed in FP64, so FP32 rounding
-// only touches f. The node count is the predicted one, raised if needed to what
-// the strip-bound rule asks for the predicted window (a few dozen FP64 operations,
-// the same rule the plain solver uses), so the step is always admissible. An entry
-// is accepted only if (a) it lies inside the model's training box and (b) the
-// integral beyond each end of the window, bounded through the concavity of g
-// from the two end nodes, is below a tolerance; otherwise it is recomputed with
-// the plain FP64 solver and FP32-compensated node terms.
+// sum is taken relative to t_lo (the first node) with the direct-exponent walk of
+// bk_math.hpp (WalkF). Node exponents can then be large and positive; the FP32
+// exponential is split as 2^k 2^f with k integer and f in [-1/2, 1/2] formed in
+// FP64, so FP32 rounding only touches f. The node count is the predicted one,
+// raised if needed to what the strip bound asks for the predicted window (one
+// half-width, in FP32), so the step is always admissible. An entry is accepted
+// only if (a) it lies inside the model's training box and (b) the integral beyond
+// each end of the window, bounded through the concavity of g from the two end
+// nodes, is below a tolerance; otherwise it is recomputed with the plain FP64
+// solver and FP32-compensated node terms.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
