@@ -72,7 +72,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="grid", choices=["grid", "matern-medium", "matern-large", "deriv-grid",
-                                                           "matern-grad-medium", "loglik"],
+                                                           "matern-grad-medium", "loglik", "paper-grid"],
                     help="grid: the headline standalone workload; matern-*: tiled covariance generation")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device-to-device copy instead (HBM reference for counters)")
@@ -164,6 +164,9 @@ def main():
         return
     if a.workload == "loglik":
         loglik_bench(a, torch, api, workloads)
+        return
+    if a.workload == "paper-grid":
+        paper_bench(a, torch, api, workloads)
         return
     if a.workload != "grid":
         matern_bench(a, torch, api, workloads)
@@ -367,6 +370,40 @@ def deriv_bench(a, torch, api, workloads):
                                  "plain_tiles_ms": round(ms_c, 3), "cost_ratio_vs_tiles": ms / ms_c}
         line = {"metric": "Matern entries/s with dC/dbeta and dC/dnu", "workload": a.workload, "n": n, "tile": ts,
                 "entries": elems, "beta": beta, "dtype": "f64", "results": res}
+    print(json.dumps(line), flush=True)
+
+
+def paper_bench(a, torch, api, workloads):
+    """The paper's refined algorithm (Temme's series below x = 0.1, the fixed window
+    [0, 9] with b = 40 bins above) on the 2^24-pair grid, beside plain FP64, plus its
+    accuracy against the oracle on a 2^16 sample (the b-versus-x trade-off shows as
+    large errors at large x; the RE metric of Sec. IV-C is reported per x range)."""
+    dev = torch.device("cuda:0")
+    nu_h, x_h, _ = workloads.grid_pairs(a.n, seed=2)
+    nu = torch.from_numpy(nu_h).to(dev)
+    x = torch.from_numpy(x_h).to(dev)
+    out = torch.empty_like(x)
+    steps = max(1, a.steps)
+    ms_p = _event_ms(torch, lambda: api.besselk(nu, x, out=out, mode="paper"), steps, a.warmup)
+    ms_k = _event_ms(torch, lambda: api.besselk(nu, x, out=out, mode="plain"), steps, a.warmup)
+    res = {"paper_refined_b40": {"ms": round(ms_p, 4), "evals_per_s": a.n / (ms_p * 1e-3)},
+           "plain_f64": {"ms": round(ms_k, 4), "evals_per_s": a.n / (ms_k * 1e-3)},
+           "temme_fraction": float(np.mean(x_h < 0.1))}
+    if not a.no_cpu:
+        import oracle
+        idx = np.random.default_rng(98).permutation(a.n)[:1 << 16]
+        _, lk, _ = oracle.besselk(nu_h[idx], x_h[idx])
+        sel = torch.from_numpy(idx).to(dev)
+        lg = api.besselk(nu[sel].contiguous(), x[sel].contiguous(), mode="paper", result=api.RESULT_LOG)
+        torch.cuda.synchronize()
+        re = np.log10(1.0 + np.abs(lg.cpu().numpy() - lk) / 2.0 ** -52)
+        xs = x_h[idx]
+        res["max_RE"] = {"x < 0.1 (Temme)": float(re[xs < 0.1].max()),
+                         "0.1 <= x <= 10": float(re[(xs >= 0.1) & (xs <= 10)].max()),
+                         "10 < x <= 140": float(re[(xs > 10) & (xs <= 140)].max()),
+                         "x > 140": float(re[xs > 140].max())}
+    line = {"metric": "K_nu evals/s, the paper's refined algorithm", "workload": a.workload, "n": a.n,
+            "dtype": "f64", "results": res}
     print(json.dumps(line), flush=True)
 
 

@@ -51,10 +51,19 @@ struct Plan {
     int mc;        // index of the reference node (0 <= mc <= N)
 };
 
+// 1/a for a normal nonzero double: hardware reciprocal refined by two Newton
+// steps (within about an ulp; no IEEE division sequence).
+__device__ __forceinline__ double recip(double a)
+{
+    double r = __builtin_amdgcn_rcp(a);
+    r = fma(r, fma(-a, r, 1.0), r);
+    return fma(r, fma(-a, r, 1.0), r);
+}
+
 __device__ __forceinline__ void cosh_sinh(double t, double& ch, double& sh)
 {
     double e = exp(t);
-    double ei = 1.0 / e;
+    double ei = recip(e);
     ch = 0.5 * (e + ei);
     sh = 0.5 * (e - ei);
 }
@@ -74,7 +83,7 @@ __device__ __forceinline__ GDer g_derivs(double nu, double x, double t)
 {
     GDer d;
     const double p = exp(-2.0 * nu * t);
-    const double ip = 1.0 / (1.0 + p);
+    const double ip = recip(1.0 + p);
     const double th = (1.0 - p) * ip;                 // tanh(nu t)
     const double s2 = 4.0 * p * ip * ip;              // sech^2(nu t)
     double ch, sh;
@@ -87,11 +96,12 @@ __device__ __forceinline__ GDer g_derivs(double nu, double x, double t)
 }
 
 // Halley step for a root of f with derivatives f1, f2: 2 f f1 / (2 f1^2 - f f2),
-// or the Newton step f / f1 where the Halley denominator is not positive.
+// or the Newton step f / f1 where the Halley denominator is not a positive normal
+// number.
 __device__ __forceinline__ double halley_step(double f, double f1, double f2)
 {
     const double den = 2.0 * f1 * f1 - f * f2;
-    return den > 0.0 ? 2.0 * f * f1 / den : f / f1;
+    return den > 1e-300 ? 2.0 * f * f1 * recip(den) : f / f1;
 }
 
 // The three roots below are found by Halley's method (cubic convergence) and
@@ -255,12 +265,12 @@ __device__ __forceinline__ Walk walk_begin(double nu, const Plan& p)
     w.k = -(double)p.mc;
     w.V = expm1(0.5 * (double)p.mc * p.h);        // expm1(|w_0|), w_0 = -mc h / 2
     w.Bb = w.V + 1.0;
-    w.Bw = 1.0 / w.Bb;
+    w.Bw = recip(w.Bb);
     w.P = exp(-2.0 * nu * p.t0);
     w.h = p.h;
     w.qm1 = expm1(0.5 * p.h);
     w.q = w.qm1 + 1.0;
-    w.qi = 1.0 / w.q;
+    w.qi = recip(w.q);
     w.rho = exp(-2.0 * nu * p.h);
     return w;
 }
@@ -299,15 +309,6 @@ __device__ inline double sum_f64(double nu, const Plan& p, double A, double B)
         walk_step(w, m);
     }
     return S - 0.5 * ends;
-}
-
-// 1/a for a normal positive double: hardware reciprocal refined by two Newton
-// steps (correct to about an ulp; no IEEE division sequence).
-__device__ __forceinline__ double recip(double a)
-{
-    double r = __builtin_amdgcn_rcp(a);
-    r = fma(r, fma(-a, r, 1.0), r);
-    return fma(r, fma(-a, r, 1.0), r);
 }
 
 // expm1(w) for 0 <= w <= 0.3 by its Taylor polynomial through w^14 (truncation
@@ -437,7 +438,7 @@ __device__ __forceinline__ DDer dnu_derivs(double nu, double x, double t)
     DDer r;
     const double omp = -expm1(-2.0 * nu * t);        // 1 - e^(-2 nu t)
     const double p = 1.0 - omp;
-    const double it = 1.0 / t, io = 1.0 / omp;
+    const double it = recip(t), io = recip(omp);
     const double cth = (2.0 - omp) * io;               // coth(nu t)
     const double cs2 = 4.0 * p * io * io;              // csch^2(nu t)
     double ch, sh;
