@@ -298,9 +298,9 @@ __global__ __launch_bounds__(256) void k_besselk_paper(const double* __restrict_
                 r = assemble(z, 0.0, temme_k(v, z, *Cp) * exp(z), result);
             } else {
                 const FixedOut f = paper_fixed(v, z, bins, T);
-                // K = exp(g(t_lmax)) h S, written through Delta = g(t_lmax) + z so that
-                // the shared assembly (exp(-z) exp(Delta) h S) applies
-                r = assemble(z, f.gmax + z, f.hs, result);
+                // K = exp(lscale) h S, written through Delta = lscale + z so that the
+                // shared assembly (exp(-z) exp(Delta) h S) applies
+                r = assemble(z, f.lscale + z, f.hs, result);
                 nodes = (unsigned long long)(bins + 1);
                 ents = 1;
             }
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(256) void k_matern(const double* __restrict__ lx,
                     val = sigma2 * exp(pref + nu * log(z)) * temme_k(nu, z, *Cp);
                 } else {
                     const FixedOut f = paper_fixed(nu, z, bins, T);
-                    val = sigma2 * exp(pref + nu * log(z) + f.gmax) * f.hs;
+                    val = sigma2 * exp(pref + nu * log(z) + f.lscale) * f.hs;
                 }
             } else {
                 Solved s = plain_solve(nu, z, L, Lq, *Rp);

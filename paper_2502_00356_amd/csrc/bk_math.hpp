@@ -525,41 +525,61 @@ __device__ inline double sum_dnu_f64(double nu, const Plan& p, double A, double 
 // ---------------------------------------------------------------------------
 // The paper's refined algorithm, integral branch (Sec. IV-C, Alg. 2): fixed
 // window [0, T], b bins, nodes t_m = m h (h = T / b), weights 1/2 at both ends,
-// scaled by the largest node value g(t_lmax). Since g is unimodal on t >= 0,
-// the largest node is found by bisection on the sign of g(t_{m+1}) - g(t_m)
-// (about log2(b) + 1 pairs of evaluations) instead of a pass over all nodes.
-// Each node evaluates g directly in FP64.
+// scaled by the largest node value. g is unimodal on t >= 0, so the sum is taken
+// relative to the node nearest t* (within one node of the largest) with the
+// cancellation-free walk of the plain form: one FP64 exponential and a few
+// multiplies per node instead of evaluating g at every node. b may run to the
+// thousands, so the walk's multiplicative state is re-seeded from closed forms
+// every kReseed nodes (its rounding drift grows with the steps taken) and the sum
+// is compensated. The scale factors out of the sum: K = exp(lscale) hs.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double g_direct(double nu, double x, double t)
-{
-    double ch, sh;
-    cosh_sinh(t, ch, sh);
-    return nu * t + log1p(exp(-2.0 * nu * t)) - kLn2 - x * ch;
-}
-
 struct FixedOut {
-    double gmax;   // g(t_lmax)
-    double hs;     // h * sum_m c_m exp(g(t_m) - g(t_lmax))
+    double lscale;   // log of the factor taken out of the sum
+    double hs;       // h * sum_m c_m exp(nu u_m - xterm_m) (1 + P_m), the walk's terms
 };
+
+constexpr int kReseed = 32;
+
+// Walk state at node m from closed forms (u = (m - mc) h, V = expm1(|u| / 2)).
+__device__ inline void walk_reseed(Walk& w, const Plan& p, double nu, int m)
+{
+    const int k = m - p.mc;
+    w.k = (double)k;
+    w.V = expm1(0.5 * p.h * (double)(k < 0 ? -k : k));
+    const double big = w.V + 1.0, small = recip(big);
+    w.Bw = (k <= 0) ? small : big;                // e^(u/2)
+    w.Bb = (k <= 0) ? big : small;                // e^(-u/2)
+    w.P = exp(-2.0 * nu * (p.t0 + (double)m * p.h));
+}
 
 __device__ inline FixedOut paper_fixed(double nu, double x, int bins, double T)
 {
-    const double h = T / (double)bins;
-    int lo = 0, hi = bins;            // the largest node lies in [lo, hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (g_direct(nu, x, (double)(mid + 1) * h) > g_direct(nu, x, (double)mid * h)) lo = mid + 1;
-        else hi = mid;
+    const double tstar = (nu * nu > x) ? peak_solve(nu, x) : 0.0;
+    Plan p;
+    p.t0 = 0.0;
+    p.h = T / (double)bins;
+    p.N = bins;
+    p.mc = (int)fmin(fmax(rint(tstar / p.h), 0.0), (double)bins);
+    p.tref = (double)p.mc * p.h;
+    double ch, sh;
+    cosh_sinh(p.tref, ch, sh);
+    const double em = expm1(0.5 * p.tref);               // sinh(t/2) = em (em + 2) / (2 (em + 1))
+    const double sh2 = em * (em + 2.0) / (2.0 * (em + 1.0));
+    const double A = 0.5 * x * ch, B = 0.5 * x * sh;
+    Walk w = walk_begin(nu, p);
+    double S = 0.0, c = 0.0, ends = 0.0;
+    for (int m = 0; m <= p.N; ++m) {
+        if (m > 0 && m % kReseed == 0) walk_reseed(w, p, nu, m);
+        const double term = exp(walk_exponent(w, m, nu, A, B)) * (1.0 + w.P);
+        const double y = term - c, t = S + y;    // Kahan
+        c = (t - S) - y;
+        S = t;
+        if (m == 0 || m == p.N) ends += term;
+        walk_step(w, m);
     }
-    const double glo = g_direct(nu, x, (double)lo * h), ghi = g_direct(nu, x, (double)hi * h);
     FixedOut o;
-    o.gmax = fmax(glo, ghi);
-    double S = 0.0;
-    for (int m = 0; m <= bins; ++m) {
-        const double c = (m == 0 || m == bins) ? 0.5 : 1.0;
-        S += c * exp(g_direct(nu, x, (double)m * h) - o.gmax);
-    }
-    o.hs = h * S;
+    o.lscale = nu * p.tref - kLn2 - 2.0 * x * sh2 * sh2 - x;
+    o.hs = p.h * ((S - c) - 0.5 * ends);
     return o;
 }
 

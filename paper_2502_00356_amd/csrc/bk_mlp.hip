@@ -63,6 +63,7 @@ struct MlpDev {
     const float* b2;     // [64]
     const float* b3;     // [3]
     float cx, sx, cnu, snu, st, sn;     // normalisation
+    float isx, isnu;                    // 1 / sx, 1 / snu
     float lx_lo, lx_hi, nu_lo, nu_hi;   // training box
     float d_lo, d_hi, eta, n_add;       // margins
 };
@@ -97,6 +98,7 @@ static MlpDev make_dev(const bk_model* m)
     d.b3 = m->bias + 64;
     d.cx = (float)m->norm[0]; d.sx = (float)m->norm[1];
     d.cnu = (float)m->norm[2]; d.snu = (float)m->norm[3];
+    d.isx = (float)(1.0 / m->norm[1]); d.isnu = (float)(1.0 / m->norm[3]);
     d.st = (float)m->norm[4]; d.sn = (float)m->norm[5];
     d.lx_lo = (float)m->box[0]; d.lx_hi = (float)m->box[1];
     d.nu_lo = (float)m->box[2]; d.nu_hi = (float)m->box[3];
@@ -276,10 +278,10 @@ __device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double
     // nodes is no steeper than g'(t_N), so using it keeps the bound. In units of
     // the sum S (integral / h): e_N / |log(e_N / e_{N-1})|. The same bound on the
     // left (g concave where nu t is not small) is e_0 / log(e_1 / e_0).
-    const float lr = __builtin_amdgcn_logf(elast / eprev) * 0.69314718f;
+    const float lr = __builtin_amdgcn_logf(elast * __builtin_amdgcn_rcpf(eprev)) * 0.69314718f;
     if (!(elast < eprev) || elast > -lr * kTailTol * S) { o.reason = BK_STAT_FB_TAIL; return o; }
     if (tlo > 0.0) {
-        const float ll = __builtin_amdgcn_logf(e1 / e0) * 0.69314718f;
+        const float ll = __builtin_amdgcn_logf(e1 * __builtin_amdgcn_rcpf(e0)) * 0.69314718f;
         if (!(e0 < e1) || e0 > ll * kTailTol * S) { o.reason = BK_STAT_FB_TAIL; return o; }
     }
     return o;
@@ -294,10 +296,10 @@ __device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double
 __device__ __forceinline__ float node_step_learned(float nu, float x, float Lq)
 {
     const float c = Lq + 0.693147181f, nu1 = nu + 1.0f;
-    const float a = fminf(__fsqrt_rn(2.0f * c / (x + nu1)), 1.3f);
+    const float a = fminf(__builtin_amdgcn_sqrtf(2.0f * c * __builtin_amdgcn_rcpf(x + nu1)), 1.3f);
     const float s = __sinf(0.5f * a);
     const float den = c + 2.0f * x * s * s - nu1 * __logf(__cosf(a));
-    return 6.28318531f * 0.999f * a / den;
+    return 6.28318531f * 0.999f * a * __builtin_amdgcn_rcpf(den);
 }
 
 // Window from a prediction (normalised outputs y), with the model's margins; the
@@ -311,7 +313,7 @@ __device__ __forceinline__ void decode_window(const MlpDev& M, float y0, float y
     float nf = ceilf(y2 * M.sn * (1.0f + M.eta) + M.n_add);
     if (!(nf >= (float)kNodeMin)) nf = (float)kNodeMin;
     if (nf > (float)kNodeMax) nf = (float)kNodeMax;
-    float nr = ceilf((float)(thi - tlo) / node_step_learned((float)nu, (float)x, (float)Lq));
+    float nr = ceilf((float)(thi - tlo) * __builtin_amdgcn_rcpf(node_step_learned((float)nu, (float)x, (float)Lq)));
     if (!(nr >= (float)kNodeMin)) nr = (float)kNodeMin;
     if (nr > (float)kNodeMax) nr = (float)kNodeMax;
     raised = nr > nf;
@@ -323,18 +325,25 @@ __device__ __forceinline__ bool in_box(const MlpDev& M, float lx, float v)
     return lx >= M.lx_lo && lx <= M.lx_hi && v >= M.nu_lo && v <= M.nu_hi;
 }
 
-// Final value for the FP32-term forms: one exponential of (Delta - z); its argument
-// rounding (|Delta - z| 2^-53 <= 1e-13 relative for x <= 1e3) is far inside the
+// c e^r for the FP32-term forms: r log2 e = k + f is split in FP64 (|f| <= 1/2),
+// 2^f is the FP32 exponential (about an ulp, 1.2e-7 relative) and 2^k is applied
+// last, so that only the final result rounds (into the subnormal range, if it
+// lies there). The split's rounding, |r| 2^-53 <= 1e-13 for the arguments here,
+// and the conversion of f to FP32 (< 2e-8) add less than 2e-7 in all, inside the
 // 2e-6 budget of these forms.
+__device__ __forceinline__ double scaled_exp(double r, double c)
+{
+    const double y = r * kLog2e;
+    const double k = rint(y);
+    return ldexp((double)__builtin_amdgcn_exp2f((float)(y - k)) * c, (int)k);
+}
+
+// Final value for the FP32-term forms: c = h S times e^(Delta - z) (or e^Delta).
 __device__ __forceinline__ double assemble_k(double z, double delta, double hs, int result)
 {
-    if (result == BK_RESULT_SCALED) return exp(delta) * hs;
+    if (result == BK_RESULT_SCALED) return scaled_exp(delta, hs);
     if (result == BK_RESULT_LOG) return (delta - z) + log(hs);
-    // where e^(Delta - z) would be subnormal, form it 2^64 larger and scale the
-    // product back, so that only the final result rounds into the subnormal range
-    const double r = delta - z;
-    const double sc = r < -700.0 ? 64.0 : 0.0;
-    return ldexp(exp(fma(sc, kLn2, r)) * hs, -(int)sc);
+    return scaled_exp(delta - z, hs);
 }
 
 __device__ __forceinline__ bool special_k(double v, double z, int result, double& r)
@@ -409,7 +418,7 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
     if (live) { v = fabs(nu[i]); z = x[i]; }
     if (tid < kSortBins) hist[tid] = 0u;
     const float lx = __log2f((float)(z > 0.0 ? z : 1.0)) * 0.30102999566f;   // log10 x in FP32
-    const float u0 = (lx - M.cx) / M.sx, u1 = ((float)v - M.cnu) / M.snu;
+    const float u0 = (lx - M.cx) * M.isx, u1 = ((float)v - M.cnu) * M.isnu;
     float y0, y1, y2;
     mlp_wave(M, u0, u1, y0, y1, y2);          // whole wave participates
     // per-lane statistics as scalars (a dynamically indexed array would live in scratch)
@@ -525,7 +534,7 @@ __global__ __launch_bounds__(256) void k_matern_table(MlpDev M, float nu, float*
     const int i = blockIdx.x * 256 + threadIdx.x;
     const float lx = M.lx_lo + (M.lx_hi - M.lx_lo) * (float)min(i, kTableSize - 1) / (float)(kTableSize - 1);
     float y0, y1, y2;
-    mlp_wave(M, (lx - M.cx) / M.sx, (nu - M.cnu) / M.snu, y0, y1, y2);
+    mlp_wave(M, (lx - M.cx) * M.isx, (nu - M.cnu) * M.isnu, y0, y1, y2);
     if (i < kTableSize) {
         table[4 * i] = y0;
         table[4 * i + 1] = y1;
@@ -622,7 +631,7 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
                 }
             }
             if (ok) {
-                val = sigma2 * exp(pref + nu * log(z) + (delta - z)) * hs;
+                val = scaled_exp(pref + nu * log(z) + (delta - z), sigma2 * hs);
             } else {
                 val = __builtin_nan("");
                 rejected = true;

@@ -28,7 +28,7 @@ def _paper_region(n, seed):
     return rng.uniform(1e-3, 20.0, n), 10 ** rng.uniform(-1.0, math.log10(140.0), n)
 
 
-@pytest.mark.parametrize("bins,T", [(40, 9.0), (16, 9.0), (128, 9.0), (200, 14.0)])
+@pytest.mark.parametrize("bins,T", [(40, 9.0), (16, 9.0), (128, 9.0), (200, 14.0), (5000, 14.0)])
 def test_fixed_window_sum_matches_oracle(api, orc, bins, T):
     """x >= 0.1: the b-bin trapezoid on [0, T] against the oracle's long-double sum."""
     import torch
