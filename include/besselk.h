@@ -46,7 +46,10 @@ typedef enum {
  *                  FP64 prefactor. Looser window (relative error ~1e-7 class).
  *  BK_LEARNED    : a 2-64-64-3 MLP on (log10 x, nu) predicts the window and node
  *                  count in place of the solve (the count is raised to the
- *                  strip-bound rule's if lower); terms as in BK_MIXED_F32C; entries
+ *                  strip-bound rule's if lower); the standalone form reads the
+ *                  prediction from the model's cells (bk_model_get_cells), the
+ *                  Matern form from a table along log10 x at its nu; terms as in
+ *                  BK_MIXED_F32C; entries
  *                  outside the model's training box, or whose window fails the
  *                  tail check, are recomputed with BK_MIXED_F32C.
  *  BK_PAPER_REFINED: the paper's refined algorithm (Sec. IV-C, Alg. 2), FP64:
@@ -266,7 +269,9 @@ int bk_model_train(bk_model* model, const double* nu, const double* x, int64_t n
  * N = ceil(N_pred * (1 + eta) + n_add) (host values). */
 int bk_model_set_margins(bk_model* model, double d_lo, double d_hi, double eta, double n_add);
 
-/* Copy the flat FP32 parameter vector to host (BK_MLP_NPARAM floats) or set it. */
+/* Copy the flat FP32 parameter vector to host (BK_MLP_NPARAM floats) or set it
+ * (setting it, the normalisation or the box rebuilds the prediction cells below
+ * and synchronises the device). */
 int bk_model_get_params(const bk_model* model, float* host_params);
 int bk_model_set_params(bk_model* model, const float* host_params);
 
@@ -277,6 +282,19 @@ int bk_model_set_norm(bk_model* model, const double* norm8);
 /* Training box: box[0..3] = log10 x min, log10 x max, nu min, nu max (host). */
 int bk_model_get_box(const bk_model* model, double* box4);
 int bk_model_set_box(bk_model* model, const double* box4);
+
+/* Prediction cells of the learned K_nu form (an implementation choice, not from
+ * the paper: the network's two inputs allow tabulating it). The training box is
+ * cut into dims[0] cells along log10 x by dims[1] along nu; cell (i, j) has its
+ * corners at (box[0] + (i + a) (box[1] - box[0]) / dims[0],
+ * box[2] + (j + b) (box[3] - box[2]) / dims[1]), a, b in {0, 1}, and holds the
+ * smallest normalised t_lo and the largest t_hi and N that the network predicts
+ * at those four corners, then 0: four floats at host[4 (i dims[1] + j)].
+ * The cells are rebuilt (synchronously) whenever the parameters, normalisation
+ * or box change. dims (host, 2 ints) is always filled; host (cap floats) may be
+ * NULL to query dims only; BK_EINVAL if cap < 4 dims[0] dims[1], BK_ENOMODEL
+ * before parameters exist. Synchronous copy. */
+int bk_model_get_cells(const bk_model* model, float* host, int64_t cap, int32_t* dims);
 
 /* MLP forward pass as used at inference (FP16 matrix-core products with FP32
  * accumulation) on n normalised inputs u (n x 2 floats, device), writing y

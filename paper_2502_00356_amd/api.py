@@ -86,6 +86,7 @@ _m_getn = _sig("bk_model_get_norm", ctypes.c_int, [_vp, _vp])
 _m_setn = _sig("bk_model_set_norm", ctypes.c_int, [_vp, _vp])
 _m_getb = _sig("bk_model_get_box", ctypes.c_int, [_vp, _vp])
 _m_setb = _sig("bk_model_set_box", ctypes.c_int, [_vp, _vp])
+_m_cells = _sig("bk_model_get_cells", ctypes.c_int, [_vp, _vp, _i64, _vp])
 _mlp_infer = _sig("bk_mlp_infer", ctypes.c_int, [_vp, _vp, _vp, _i64, _vp])
 _mlp_grad = _sig("bk_mlp_grad", ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, ctypes.c_size_t, _vp])
 _mlp_grad_scratch = _sig("bk_mlp_grad_scratch_bytes", ctypes.c_size_t, [_i64])
@@ -363,6 +364,16 @@ class Model:
     def set_box(self, box4):
         t = torch.as_tensor(box4, dtype=torch.float64).contiguous()
         _check(_m_setb(self.handle, t.data_ptr()))
+
+    def get_cells(self):
+        """Prediction cells of the learned K_nu form: float32 (cells along log10 x,
+        cells along nu, 4) = smallest t_lo, largest t_hi and N (normalised) that the
+        network predicts at the cell's four corners, then 0."""
+        dims = (ctypes.c_int32 * 2)()
+        _check(_m_cells(self.handle, None, 0, dims))
+        t = torch.empty((dims[0], dims[1], 4), dtype=torch.float32)
+        _check(_m_cells(self.handle, t.data_ptr(), t.numel(), dims))
+        return t
 
     def infer(self, u, stream=None):
         """Raw MLP forward (FP16 matrix cores) on normalised inputs u (n x 2 float32)."""

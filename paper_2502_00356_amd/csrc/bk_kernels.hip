@@ -50,13 +50,14 @@ const RuleTable& rule_table()
             t.omc[k] = 1.0 - cos(a);
             t.lsec[k] = -log(cos(a));
         }
+        for (int j = 0; j < 64; ++j) t.exp2_64[j] = (double)exp2l((long double)j / 64.0L);
         return t;
     }();
     return R;
 }
 
 // Device copy of the rule table, one per GPU, made on first use and kept for the
-// life of the process (360 bytes). Kernels read it through a pointer, so its
+// life of the process (872 bytes). Kernels read it through a pointer, so its
 // values are scalar loads rather than 90 kernel-argument SGPRs.
 const RuleTable* rule_table_dev()
 {

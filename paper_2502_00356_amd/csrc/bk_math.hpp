@@ -35,11 +35,13 @@ constexpr int kNodeMax = 512;
 constexpr int kRuleCand = 15;
 
 // Node-count rule constants, filled on the host: for each strip half-width a_k,
-// a_k, 1 - cos a_k and log sec a_k (see node_step).
+// a_k, 1 - cos a_k and log sec a_k (see node_step); and 2^(j/64), j = 0..63, for
+// exp_tab.
 struct RuleTable {
     double a[kRuleCand];
     double omc[kRuleCand];
     double lsec[kRuleCand];
+    double exp2_64[64];
 };
 
 // Per-entry quadrature plan.
@@ -341,6 +343,28 @@ __device__ __forceinline__ double expm1_small(double w)
 // few m^2 ulps), so the absolute error of d_m is about x cosh(t_m) m^2 2^-53,
 // below 1e-10 on the whole (nu, x) range. The factor Q = 1 + e^(-2 nu t) follows
 // Q' = rho Q + (1 - rho), rho = e^(-2 nu h) (contracting, so no error growth).
+// e^x for |x| < 700 from T[j] = 2^(j/64), j = 0..63 (Tang's table-driven method):
+// with k = floor(64 x log2 e) and f = x - k ln2/64, in [0, ln2/64) up to rounding,
+// e^x = 2^(k div 64) T[k mod 64] e^f, and e^f is its Taylor polynomial through f^6
+// (truncation below 2e-18). ln2/64 rounded to FP64 is off by < 1e-19, so the
+// reduction adds at most |k| 1e-19 (< 1e-15 for |x| < 700); the result is within
+// a few ulps for the arguments of the walk set-up (|x| < 20), where the FP32-term
+// forms need about 1e-12.
+__device__ __forceinline__ double exp_tab(double x, const double* T)
+{
+    const double k = floor(x * 92.332482616893656);          // 64 log2 e
+    const double f = fma(-k, 0.010830424696249145, x);        // ln2 / 64
+    double p = 1.0 / 720.0;
+    p = fma(p, f, 1.0 / 120.0);
+    p = fma(p, f, 1.0 / 24.0);
+    p = fma(p, f, 1.0 / 6.0);
+    p = fma(p, f, 0.5);
+    p = fma(p, f, 1.0);
+    p = fma(p, f, 1.0);
+    const int ki = (int)k;
+    return ldexp(T[ki & 63] * p, ki >> 6);
+}
+
 struct WalkF {
     double c, cn, kappa;      // cosh t_m, cosh t_{m+1}, 2 cosh h
     double a2, b2, c2, mm;    // d_m = a2 c_m + mm b2 + c2, mm = m - m_ref
@@ -363,6 +387,25 @@ __device__ __forceinline__ WalkF walkf_begin(double nu, double x, double t0, dou
     w.rho = exp(-2.0 * nu * h);
     w.omr = 1.0 - w.rho;              // absolute error 2^-53: Q's error stays ~m 2^-53
     // Q only needs FP32 accuracy: e^(-2 nu t_0) in FP32 moves Q by < 6e-8 relative
+    w.Q = 1.0 + (double)__expf((float)(-2.0 * nu * t0));
+    return w;
+}
+
+// The same state from the exponentials themselves: e = e^{t_0}, ei = e^{-t_0},
+// q2 = e^h, qi2 = e^{-h}, rho = e^{-2 nu h}.
+__device__ __forceinline__ WalkF walkf_begin_exp(double nu, double x, double t0, double h, int mref, double xch_ref,
+                                                 double e, double ei, double q2, double qi2, double rho)
+{
+    WalkF w;
+    w.kappa = q2 + qi2;
+    w.c = 0.5 * (e + ei);
+    w.cn = 0.5 * (e * q2 + ei * qi2);
+    w.a2 = -x * kLog2e;
+    w.b2 = nu * h * kLog2e;
+    w.c2 = xch_ref * kLog2e;
+    w.mm = -(double)mref;
+    w.rho = rho;
+    w.omr = 1.0 - rho;
     w.Q = 1.0 + (double)__expf((float)(-2.0 * nu * t0));
     return w;
 }
@@ -530,8 +573,8 @@ __device__ inline double sum_dnu_f64(double nu, const Plan& p, double A, double 
 // cancellation-free walk of the plain form: one FP64 exponential and a few
 // multiplies per node instead of evaluating g at every node. b may run to the
 // thousands, so the walk's multiplicative state is re-seeded from closed forms
-// every kReseed nodes (its rounding drift grows with the steps taken) and the sum
-// is compensated. The scale factors out of the sum: K = exp(lscale) hs.
+// every kReseed nodes (its rounding drift grows with the steps taken) and long
+// sums are compensated. The scale factors out of the sum: K = exp(lscale) hs.
 // ---------------------------------------------------------------------------
 struct FixedOut {
     double lscale;   // log of the factor taken out of the sum
@@ -552,6 +595,32 @@ __device__ inline void walk_reseed(Walk& w, const Plan& p, double nu, int m)
     w.P = exp(-2.0 * nu * (p.t0 + (double)m * p.h));
 }
 
+// Trapezoid sum of the fixed window on the re-seeded walk; Kahan-compensated when
+// Comp (b beyond kFixedPlainMax nodes, where plain FP64 accumulation error grows
+// past the walk's own).
+constexpr int kFixedPlainMax = 256;
+
+template <bool Comp>
+__device__ inline double fixed_sum(double nu, const Plan& p, double A, double B)
+{
+    Walk w = walk_begin(nu, p);
+    double S = 0.0, c = 0.0, ends = 0.0;
+    for (int m = 0; m <= p.N; ++m) {
+        if (m > 0 && m % kReseed == 0) walk_reseed(w, p, nu, m);
+        const double term = exp(walk_exponent(w, m, nu, A, B)) * (1.0 + w.P);
+        if (Comp) {
+            const double y = term - c, t = S + y;
+            c = (t - S) - y;
+            S = t;
+        } else {
+            S += term;
+        }
+        if (m == 0 || m == p.N) ends += term;
+        walk_step(w, m);
+    }
+    return (S - c) - 0.5 * ends;
+}
+
 __device__ inline FixedOut paper_fixed(double nu, double x, int bins, double T)
 {
     const double tstar = (nu * nu > x) ? peak_solve(nu, x) : 0.0;
@@ -566,20 +635,9 @@ __device__ inline FixedOut paper_fixed(double nu, double x, int bins, double T)
     const double em = expm1(0.5 * p.tref);               // sinh(t/2) = em (em + 2) / (2 (em + 1))
     const double sh2 = em * (em + 2.0) / (2.0 * (em + 1.0));
     const double A = 0.5 * x * ch, B = 0.5 * x * sh;
-    Walk w = walk_begin(nu, p);
-    double S = 0.0, c = 0.0, ends = 0.0;
-    for (int m = 0; m <= p.N; ++m) {
-        if (m > 0 && m % kReseed == 0) walk_reseed(w, p, nu, m);
-        const double term = exp(walk_exponent(w, m, nu, A, B)) * (1.0 + w.P);
-        const double y = term - c, t = S + y;    // Kahan
-        c = (t - S) - y;
-        S = t;
-        if (m == 0 || m == p.N) ends += term;
-        walk_step(w, m);
-    }
     FixedOut o;
     o.lscale = nu * p.tref - kLn2 - 2.0 * x * sh2 * sh2 - x;
-    o.hs = p.h * ((S - c) - 0.5 * ends);
+    o.hs = p.h * (bins > kFixedPlainMax ? fixed_sum<true>(nu, p, A, B) : fixed_sum<false>(nu, p, A, B));
     return o;
 }
 

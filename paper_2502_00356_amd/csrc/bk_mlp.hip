@@ -4,7 +4,12 @@
 // Matern tiles.
 //
 // The learned form replaces the per-entry peak/window solve of Sec. IV-B with a
-// prediction of [t_lo, t_hi] and the node count N from (log10 x, nu). The node
+// prediction of [t_lo, t_hi] and the node count N from (log10 x, nu). The network
+// has two inputs, so its predictions are tabulated once per model: the training
+// box is cut into cells, and each cell holds the window that contains the
+// network's predictions at its four corners (smallest t_lo, largest t_hi and N);
+// an entry reads its cell (one 16-byte load) instead of evaluating the network.
+// The Matern kernels tabulate it along log10 x at the launch's nu instead. The node
 // sum is taken relative to t_lo (the first node) with the direct-exponent walk of
 // bk_math.hpp (WalkF). Node exponents can then be large and positive; the FP32
 // exponential is split as 2^k 2^f with k integer and f in [-1/2, 1/2] formed in
@@ -50,6 +55,8 @@ static_assert(kNParam == BK_MLP_NPARAM, "parameter count");
 // and FP32 node rounding (~2e-7) this keeps the total well inside 2e-6.
 constexpr float kTailTol = 3e-7f;
 constexpr int kTableSize = 1024;       // Matern: MLP tabulated over log10 x at fixed nu
+// Standalone K_nu: prediction cells over the training box, log10 x by nu.
+constexpr int kCellsLx = 512, kCellsNu = 128, kCells = kCellsLx * kCellsNu;
 // Matern learned launches: at most 2^21 workgroups (2^23 waves) each, so the
 // model's fallback list (one entry per wave with a rejected entry) never overflows.
 constexpr int64_t kMaternWgPerLaunch = 1LL << 21;
@@ -66,6 +73,8 @@ struct MlpDev {
     float isx, isnu;                    // 1 / sx, 1 / snu
     float lx_lo, lx_hi, nu_lo, nu_hi;   // training box
     float d_lo, d_hi, eta, n_add;       // margins
+    const float4_t* cells;              // [kCellsLx][kCellsNu] cell windows (normalised y0, y1, y2, 0)
+    float cl_scale, cn_scale;           // cells per unit of log10 x and of nu
 };
 
 }  // namespace bk
@@ -75,6 +84,7 @@ struct bk_model {
     half4_t* pack = nullptr;      // device FP16 operand pack (a1, a2, a3)
     float* bias = nullptr;        // device b2 (64) and b3 (3)
     float* table = nullptr;       // device Matern window table [kTableSize][4]
+    float* cells = nullptr;       // device prediction cells [kCellsLx][kCellsNu][4]
     unsigned int* mlist = nullptr; // device Matern fallback list: count at [0], wave ids from [64]
     double norm[8] = {-0.5, 3.5, 5.005, 4.995, 8.0, 32.0, 0.0, 0.0};
     double box[4] = {-4.0, 3.0, 0.01, 10.0};
@@ -104,6 +114,9 @@ static MlpDev make_dev(const bk_model* m)
     d.nu_lo = (float)m->box[2]; d.nu_hi = (float)m->box[3];
     d.d_lo = (float)m->margins[0]; d.d_hi = (float)m->margins[1];
     d.eta = (float)m->margins[2]; d.n_add = (float)m->margins[3];
+    d.cells = reinterpret_cast<const float4_t*>(m->cells);
+    d.cl_scale = (float)((double)kCellsLx / (m->box[1] - m->box[0]));
+    d.cn_scale = (float)((double)kCellsNu / (m->box[3] - m->box[2]));
     return d;
 }
 
@@ -226,6 +239,41 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpDev M, const float* __rest
     if (i < n) { y[3 * i] = y0; y[3 * i + 1] = y1; y[3 * i + 2] = y2; }
 }
 
+// Prediction cells: one lane per cell (i along log10 x, j along nu) evaluates the
+// network at the cell's four corners and keeps the window that contains all four
+// predictions. Corner (i, j) lies at (lx_lo + i dl, nu_lo + j dn); the corner
+// inputs are rounded operation by operation (contraction into FMA is off here),
+// so that they can be reproduced exactly elsewhere.
+__global__ __launch_bounds__(256) void k_cell_table(MlpDev M, float4_t* __restrict__ cells)
+{
+#pragma clang fp contract(off)
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int cc = min(c, kCells - 1);
+    const int i = cc / kCellsNu, j = cc % kCellsNu;
+    const float dl = (M.lx_hi - M.lx_lo) / (float)kCellsLx;
+    const float dn = (M.nu_hi - M.nu_lo) / (float)kCellsNu;
+    float4_t w = {__builtin_inff(), -__builtin_inff(), -__builtin_inff(), 0.0f};
+    for (int k = 0; k < 4; ++k) {          // uniform trip count: the whole wave runs the network
+        const float lx = M.lx_lo + (float)(i + (k & 1)) * dl;
+        const float nu = M.nu_lo + (float)(j + (k >> 1)) * dn;
+        float y0, y1, y2;
+        mlp_wave(M, (lx - M.cx) * M.isx, (nu - M.cnu) * M.isnu, y0, y1, y2);
+        w[0] = fminf(w[0], y0);
+        w[1] = fmaxf(w[1], y1);
+        w[2] = fmaxf(w[2], y2);
+    }
+    if (c < kCells) cells[c] = w;
+}
+
+// The cell of an entry inside the training box (the last cell of each axis also
+// takes the box's upper edge).
+__device__ __forceinline__ float4_t cell_of(const MlpDev& M, float lx, float v)
+{
+    const int i = min(max((int)((lx - M.lx_lo) * M.cl_scale), 0), kCellsLx - 1);
+    const int j = min(max((int)((v - M.nu_lo) * M.cn_scale), 0), kCellsNu - 1);
+    return M.cells[i * kCellsNu + j];
+}
+
 // ---------------------------------------------------------------------------
 // Learned node sum. Reference t_ref = t_lo (node 0), outward walk only.
 // ---------------------------------------------------------------------------
@@ -235,7 +283,8 @@ struct LearnedOut {
     int reason;     // 0 accepted, else a BK_STAT_FB_* index
 };
 
-__device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double thi, int N)
+// T: the table 2^(j/64) of exp_tab (in LDS where the kernel stages it).
+__device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double thi, int N, const double* T)
 {
     LearnedOut o;
     o.reason = 0;
@@ -244,11 +293,11 @@ __device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double
     const double h = (thi - tlo) * (double)__builtin_amdgcn_rcpf((float)N);
     // reference t_ref = t_lo; sinh^2(t/2) = (cosh t - 1) / 2 loses ~1e-16 absolute,
     // i.e. at most ~2e-13 relative in the scale for x <= 1e3, far inside this form's budget
-    const double e = exp(tlo), ei = recip(e);
+    const double e = exp_tab(tlo, T), ei = recip(e);
     const double ch = 0.5 * (e + ei);
     o.delta = nu * tlo - kLn2 - x * (ch - 1.0);
-    const double q = 1.0 + expm1_small(0.5 * h), qi = recip(q);
-    WalkF w = walkf_begin(nu, x, tlo, h, 0, x * ch, e, ei, q, qi);
+    const double q2 = exp_tab(h, T), qi2 = recip(q2);
+    WalkF w = walkf_begin_exp(nu, x, tlo, h, 0, x * ch, e, ei, q2, qi2, exp_tab(-2.0 * nu * h, T));
     // the exponent is not bounded above here (t_lo is not the peak), so the FP32
     // exponential is split as 2^k 2^f with k, f formed in FP64
     float s = 0.0f, c = 0.0f, e0 = 0.0f, e1 = 0.0f, eprev = 0.0f, elast = 0.0f;
@@ -298,7 +347,8 @@ __device__ __forceinline__ float node_step_learned(float nu, float x, float Lq)
     const float c = Lq + 0.693147181f, nu1 = nu + 1.0f;
     const float a = fminf(__builtin_amdgcn_sqrtf(2.0f * c * __builtin_amdgcn_rcpf(x + nu1)), 1.3f);
     const float s = __sinf(0.5f * a);
-    const float den = c + 2.0f * x * s * s - nu1 * __logf(__cosf(a));
+    // cos a >= cos 1.3 > 0.26: the hardware logarithm needs no range handling
+    const float den = c + 2.0f * x * s * s - nu1 * 0.69314718f * __builtin_amdgcn_logf(__cosf(a));
     return 6.28318531f * 0.999f * a * __builtin_amdgcn_rcpf(den);
 }
 
@@ -391,8 +441,8 @@ __device__ void block_stats_w(unsigned long long* stats, const unsigned long lon
     }
 }
 
-// Learned K_nu. Phase 1 (entry order): MLP on the matrix cores, window decode,
-// range check. Phase 2: the block's entries are counting-sorted by node count
+// Learned K_nu. Phase 1 (entry order): range check, the entry's prediction cell,
+// window decode. Phase 2: the block's entries are counting-sorted by node count
 // through LDS, so each wave walks entries of similar N (the wave runs as many
 // node steps as its largest N). Phase 3 (sorted order): node sums, tail checks,
 // stores to the entry's own index or the fallback queue.
@@ -408,6 +458,7 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
                                                                    unsigned long long* __restrict__ stats)
 {
     __shared__ unsigned int hist[kSortBins];
+    __shared__ double s_exp2[64];
     __shared__ double s_v[kLearnedBlock], s_z[kLearnedBlock], s_tlo[kLearnedBlock], s_thi[kLearnedBlock];
     __shared__ int s_N[kLearnedBlock];
     __shared__ unsigned int s_idx[kLearnedBlock];
@@ -417,10 +468,8 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
     double v = 0.0, z = 1.0;
     if (live) { v = fabs(nu[i]); z = x[i]; }
     if (tid < kSortBins) hist[tid] = 0u;
+    if (tid < 64) s_exp2[tid] = Rp->exp2_64[tid];     // read after the sort's barriers
     const float lx = __log2f((float)(z > 0.0 ? z : 1.0)) * 0.30102999566f;   // log10 x in FP32
-    const float u0 = (lx - M.cx) * M.isx, u1 = ((float)v - M.cnu) * M.isnu;
-    float y0, y1, y2;
-    mlp_wave(M, u0, u1, y0, y1, y2);          // whole wave participates
     // per-lane statistics as scalars (a dynamically indexed array would live in scratch)
     unsigned int c_range = 0, c_tail = 0, c_raised = 0, c_nonfin = 0, c_nodes = 0, c_ent = 0;
     double tlo = 0.0, thi = 0.0;
@@ -437,7 +486,8 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
             } else {
                 bool raised;
                 int Nd;
-                decode_window(M, y0, y1, y2, v, z, Lq, tlo, thi, Nd, raised);
+                const float4_t y = cell_of(M, lx, (float)v);
+                decode_window(M, y[0], y[1], y[2], v, z, Lq, tlo, thi, Nd, raised);
                 c_raised = raised ? 1u : 0u;
                 if (!(thi > tlo) || !isfinite(thi)) { reject = true; c_nonfin = 1; }
                 else N = Nd;
@@ -475,7 +525,7 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
     if (Ns >= 0) {
         const double vs = s_v[tid], zs = s_z[tid];
         const unsigned int idx = s_idx[tid];
-        LearnedOut lo = learned_sum(vs, zs, s_tlo[tid], s_thi[tid], Ns);
+        LearnedOut lo = learned_sum(vs, zs, s_tlo[tid], s_thi[tid], Ns, s_exp2);
         c_nodes = (unsigned int)(Ns + 1);
         c_ent = 1;
         if (lo.reason == 0) {
@@ -579,6 +629,7 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
                                                         const double* __restrict__ lx_, const double* __restrict__ ly_,
                                                         TileGeomL g, int64_t tile_base, double sigma2,
                                                         double inv_beta, double nu, double pref, double Lq,
+                                                        const RuleTable* __restrict__ Rp,
                                                         unsigned int* __restrict__ mlist, OutT* __restrict__ out)
 {
     constexpr int kColsPerWave = 8, kColsPerGroup = 32;
@@ -622,7 +673,7 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
                 decode_window(M, fminf(t0[0], t1[0]), fmaxf(t0[1], t1[1]), fmaxf(t0[2], t1[2]), nu, z, Lq, tlo, thi,
                               N, raised);
                 if (thi > tlo && isfinite(thi)) {
-                    LearnedOut lo = learned_sum(nu, z, tlo, thi, N);
+                    LearnedOut lo = learned_sum(nu, z, tlo, thi, N, Rp->exp2_64);
                     ok = lo.reason == 0;
                     hs = lo.hs;
                     delta = lo.delta;
@@ -898,12 +949,25 @@ static int model_alloc(bk_model* m)
     if (hipMalloc((void**)&m->pack, sizeof(_Float16) * 24 * 64 * 4) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->bias, sizeof(float) * 68) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->table, sizeof(float) * 4 * kTableSize) != hipSuccess) return BK_ENOMEM;
+    if (hipMalloc((void**)&m->cells, sizeof(float) * 4 * kCells) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->mlist, sizeof(unsigned int) * (64 + (size_t)kMaternWavesPerLaunch)) != hipSuccess)
         return BK_ENOMEM;
     return BK_OK;
 }
 
-// Upload host parameters: master copy and inference pack (synchronous).
+// Prediction cells for the current parameters, normalisation and box (synchronous,
+// on the null stream; nothing to do before the parameters exist).
+static int model_cells(bk_model* m)
+{
+    if (!m->params) return BK_OK;
+    hipLaunchKernelGGL(k_cell_table, dim3((kCells + 255) / 256), dim3(256), 0, nullptr, make_dev(m),
+                       reinterpret_cast<float4_t*>(m->cells));
+    if (hipGetLastError() != hipSuccess) return BK_EHIP;
+    return hip_ok(hipStreamSynchronize(nullptr));
+}
+
+// Upload host parameters: master copy and inference pack, then the prediction
+// cells (synchronous).
 static int model_upload(bk_model* m, const float* hostP)
 {
     int st = model_alloc(m);
@@ -914,7 +978,7 @@ static int model_upload(bk_model* m, const float* hostP)
     if (hipMemcpy(m->params, hostP, sizeof(float) * kNParam, hipMemcpyHostToDevice) != hipSuccess) return BK_EHIP;
     if (hipMemcpy(m->pack, pack.data(), sizeof(_Float16) * pack.size(), hipMemcpyHostToDevice) != hipSuccess) return BK_EHIP;
     if (hipMemcpy(m->bias, bias.data(), sizeof(float) * bias.size(), hipMemcpyHostToDevice) != hipSuccess) return BK_EHIP;
-    return BK_OK;
+    return model_cells(m);
 }
 
 static size_t grad_scratch_floats(int64_t B) { return (size_t)B * (2 + 4 * 64 + 3); }
@@ -990,12 +1054,12 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, m->mlist);
         if (prm->out_dtype == BK_OUT_F32) {
             hipLaunchKernelGGL(k_matern_learned<float>, grid, dim3(256), 0, stream, M, m->table, locs->x, locs->y, g,
-                               t0, prm->sigma2, ib, nu, pref, Lq, m->mlist, (float*)out);
+                               t0, prm->sigma2, ib, nu, pref, Lq, R, m->mlist, (float*)out);
             hipLaunchKernelGGL(k_matern_fallback<float>, dim3(1024), dim3(256), 0, stream, locs->x, locs->y, g, t0,
                                prm->sigma2, ib, nu, pref, L, Lq, R, m->mlist, (float*)out);
         } else {
             hipLaunchKernelGGL(k_matern_learned<double>, grid, dim3(256), 0, stream, M, m->table, locs->x, locs->y, g,
-                               t0, prm->sigma2, ib, nu, pref, Lq, m->mlist, (double*)out);
+                               t0, prm->sigma2, ib, nu, pref, Lq, R, m->mlist, (double*)out);
             hipLaunchKernelGGL(k_matern_fallback<double>, dim3(1024), dim3(256), 0, stream, locs->x, locs->y, g, t0,
                                prm->sigma2, ib, nu, pref, L, Lq, R, m->mlist, (double*)out);
         }
@@ -1028,6 +1092,7 @@ extern "C" void bk_model_destroy(bk_model* m)
     if (m->pack) (void)hipFree(m->pack);
     if (m->bias) (void)hipFree(m->bias);
     if (m->table) (void)hipFree(m->table);
+    if (m->cells) (void)hipFree(m->cells);
     if (m->mlist) (void)hipFree(m->mlist);
     delete m;
 }
@@ -1117,7 +1182,7 @@ extern "C" int bk_model_set_norm(bk_model* m, const double* n8)
 {
     if (!m || !n8 || !(n8[1] > 0) || !(n8[3] > 0) || !(n8[4] > 0) || !(n8[5] > 0)) return BK_EINVAL;
     memcpy(m->norm, n8, sizeof(m->norm));
-    return BK_OK;
+    return model_cells(m);
 }
 
 extern "C" int bk_model_get_box(const bk_model* m, double* b4)
@@ -1131,7 +1196,18 @@ extern "C" int bk_model_set_box(bk_model* m, const double* b4)
 {
     if (!m || !b4 || !(b4[1] > b4[0]) || !(b4[3] > b4[2])) return BK_EINVAL;
     memcpy(m->box, b4, sizeof(m->box));
-    return BK_OK;
+    return model_cells(m);
+}
+
+extern "C" int bk_model_get_cells(const bk_model* m, float* host, int64_t cap, int32_t* dims)
+{
+    if (!m || !dims) return BK_EINVAL;
+    dims[0] = kCellsLx;
+    dims[1] = kCellsNu;
+    if (!host) return BK_OK;
+    if (cap < (int64_t)4 * kCells) return BK_EINVAL;
+    if (!m->params) return BK_ENOMODEL;
+    return hip_ok(hipMemcpy(host, m->cells, sizeof(float) * 4 * kCells, hipMemcpyDeviceToHost));
 }
 
 extern "C" int bk_mlp_infer(const bk_model* m, const float* u, float* y, int64_t n, hipStream_t s)

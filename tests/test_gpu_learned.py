@@ -117,6 +117,51 @@ def trained(api, tmp_path_factory):
     return m
 
 
+def test_prediction_cells_hold_corner_predictions(api, trained):
+    """The learned K_nu form reads its window from the model's cells: each cell must
+    hold the smallest t_lo and the largest t_hi and N that the network (the same
+    matrix-core forward as bk_mlp_infer) predicts at the cell's four corners; the
+    cells follow a change of the box."""
+    import torch
+    f32 = np.float32
+
+    def check(m, ncheck, seed):
+        cells = m.get_cells().numpy()
+        L, Nn, _ = cells.shape
+        box = m.get_box().numpy()
+        norm = m.get_norm().numpy()
+        rng = np.random.default_rng(seed)
+        i = rng.integers(0, L, ncheck)
+        j = rng.integers(0, Nn, ncheck)
+        i[:2] = (0, L - 1)
+        j[:2] = (0, Nn - 1)
+        b = box.astype(f32)
+        dl = (b[1] - b[0]) / f32(L)
+        dn = (b[3] - b[2]) / f32(Nn)
+        ys = []
+        for a, c in ((0, 0), (1, 0), (0, 1), (1, 1)):
+            lx = b[0] + (i + a).astype(f32) * dl
+            nu = b[2] + (j + c).astype(f32) * dn
+            u = np.stack([(lx - f32(norm[0])) * f32(1.0 / norm[1]), (nu - f32(norm[2])) * f32(1.0 / norm[3])], 1)
+            ys.append(m.infer(to_dev(u.astype(f32))).cpu().numpy())
+        ys = np.stack(ys)
+        want = np.stack([ys[:, :, 0].min(0), ys[:, :, 1].max(0), ys[:, :, 2].max(0)], 1)
+        got = cells[i, j, :3]
+        # both sides round the corner inputs the same way and run the same forward
+        assert np.array_equal(got, want), np.abs(got - want).max()
+        assert np.all(cells[:, :, 3] == 0.0)
+
+    check(trained, 4096, 21)
+    m = api.Model()
+    m.set_params(trained.get_params())
+    box = trained.get_box().numpy().copy()
+    box[1] -= 1.0
+    box[3] *= 0.5
+    m.set_box(box)
+    torch.cuda.synchronize()
+    check(m, 1024, 22)
+
+
 def test_training_reduces_loss(api):
     import torch
     from paper_2502_00356_amd import workloads
