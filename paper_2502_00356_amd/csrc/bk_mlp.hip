@@ -299,28 +299,29 @@ __device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double
     const double q2 = exp_tab(h, T), qi2 = recip(q2);
     WalkF w = walkf_begin_exp(nu, x, tlo, h, 0, x * ch, e, ei, q2, qi2, exp_tab(-2.0 * nu * h, T));
     // the exponent is not bounded above here (t_lo is not the peak), so the FP32
-    // exponential is split as 2^k 2^f with k, f formed in FP64
-    float s = 0.0f, c = 0.0f, e0 = 0.0f, e1 = 0.0f, eprev = 0.0f, elast = 0.0f;
-#pragma unroll 2
-    for (int m = 0; m <= N; ++m) {
+    // exponential is split as 2^k 2^f with k, f formed in FP64; the FP32 terms are
+    // summed in FP64, whose rounding is negligible next to theirs
+    auto node = [&]() {
         const double d = walkf_exponent2(w);
         const double kf = rint(d);
-        float term = __builtin_amdgcn_exp2f((float)(d - kf)) * (float)w.Q;
-        term = ldexpf(term, (int)kf);
-        const float yk = term - c;
-        const float tk = s + yk;
-        c = (tk - s) - yk;
-        s = tk;
-        e0 = (m == 0) ? term : e0;
-        e1 = (m == 1) ? term : e1;
-        eprev = elast;
-        elast = term;
+        const float t = ldexpf(__builtin_amdgcn_exp2f((float)(d - kf)) * (float)w.Q, (int)kf);
         walkf_step(w);
+        return t;
+    };
+    const float e0 = node(), e1 = node();      // N >= kNodeMin: at least five nodes
+    double Sd = (double)e0 + (double)e1;
+    float eprev = e0, elast = e1;
+#pragma unroll 2
+    for (int m = 2; m <= N; ++m) {
+        const float t = node();
+        Sd += (double)t;
+        eprev = elast;
+        elast = t;
     }
-    const float ends = e0 + elast;
-    const float S = (s - c) - 0.5f * ends;
-    o.hs = h * (double)S;
-    if (!(S > 0.0f) || !isfinite(S)) { o.reason = BK_STAT_FB_NONFINITE; return o; }
+    Sd -= 0.5 * ((double)e0 + (double)elast);
+    o.hs = h * Sd;
+    if (!(Sd > 0.0) || !isfinite(Sd)) { o.reason = BK_STAT_FB_NONFINITE; return o; }
+    const float S = (float)Sd;
     // Tails beyond the ends. Right of the peak g is concave, so past the last node
     // the integrand lies below the exponential with slope g'(t_N), and the tail
     // integral is at most f(t_N) / |g'(t_N)|; the secant slope of the last two
