@@ -367,9 +367,11 @@ __device__ __forceinline__ double exp_tab(double x, const double* T)
 
 struct WalkF {
     double c, cn, kappa;      // cosh t_m, cosh t_{m+1}, 2 cosh h
-    double a2, b2, c2, mm;    // d_m = a2 c_m + mm b2 + c2, mm = m - m_ref
+    double a2, e, b2;         // d_m = a2 c_m + e_m; e_m = x cosh(t_ref) log2 e + (m - m_ref) b2, advanced by b2
     double Q, rho, omr;       // Q = 1 + e^(-2 nu t_m)
 };
+// e_m accumulates one rounding per node: m ulps of |e| <= x cosh t_ref + 30, below
+// 1e-11 absolute in d_m for the windows here (the FP32 terms need ~1e-8).
 
 // e = e^{t_0}, ei = e^{-t_0} and q = e^{h/2}, qi = e^{-h/2} given by the caller.
 __device__ __forceinline__ WalkF walkf_begin(double nu, double x, double t0, double h, int mref, double xch_ref,
@@ -382,8 +384,7 @@ __device__ __forceinline__ WalkF walkf_begin(double nu, double x, double t0, dou
     w.cn = 0.5 * (e * q2 + ei * qi2);
     w.a2 = -x * kLog2e;
     w.b2 = nu * h * kLog2e;
-    w.c2 = xch_ref * kLog2e;
-    w.mm = -(double)mref;
+    w.e = fma(-(double)mref, w.b2, xch_ref * kLog2e);
     w.rho = exp(-2.0 * nu * h);
     w.omr = 1.0 - w.rho;              // absolute error 2^-53: Q's error stays ~m 2^-53
     // Q only needs FP32 accuracy: e^(-2 nu t_0) in FP32 moves Q by < 6e-8 relative
@@ -402,22 +403,21 @@ __device__ __forceinline__ WalkF walkf_begin_exp(double nu, double x, double t0,
     w.cn = 0.5 * (e * q2 + ei * qi2);
     w.a2 = -x * kLog2e;
     w.b2 = nu * h * kLog2e;
-    w.c2 = xch_ref * kLog2e;
-    w.mm = -(double)mref;
+    w.e = fma(-(double)mref, w.b2, xch_ref * kLog2e);
     w.rho = rho;
     w.omr = 1.0 - rho;
     w.Q = 1.0 + (double)__expf((float)(-2.0 * nu * t0));
     return w;
 }
 
-__device__ __forceinline__ double walkf_exponent2(const WalkF& w) { return fma(w.a2, w.c, fma(w.mm, w.b2, w.c2)); }
+__device__ __forceinline__ double walkf_exponent2(const WalkF& w) { return fma(w.a2, w.c, w.e); }
 
 __device__ __forceinline__ void walkf_step(WalkF& w)
 {
     const double c2n = fma(w.kappa, w.cn, -w.c);
     w.c = w.cn;
     w.cn = c2n;
-    w.mm += 1.0;
+    w.e += w.b2;
     w.Q = fma(w.Q, w.rho, w.omr);
 }
 

@@ -308,11 +308,19 @@ __device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double
         walkf_step(w);
         return t;
     };
+    // Nodes go in pairs: a pair is added in FP32 (one rounding, <= 6e-8 of the pair)
+    // and the pair sums in FP64.
     const float e0 = node(), e1 = node();      // N >= kNodeMin: at least five nodes
-    double Sd = (double)e0 + (double)e1;
+    double Sd = (double)(e0 + e1);
     float eprev = e0, elast = e1;
-#pragma unroll 2
-    for (int m = 2; m <= N; ++m) {
+    int m = 2;
+    for (; m + 1 <= N; m += 2) {
+        const float ta = node(), tb = node();
+        Sd += (double)(ta + tb);
+        eprev = ta;
+        elast = tb;
+    }
+    if (m == N) {                               // odd node count left one node
         const float t = node();
         Sd += (double)t;
         eprev = elast;
