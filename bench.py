@@ -19,18 +19,20 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs, 4 SIMD16 per CU -> 64 VALU lanes per CU per clock, 2.4 GHz.
-# A full-rate VALU instruction (FP64 or FP32 FMA/add/mul) retires one lane-op per
-# lane per clock; FP32 transcendentals (v_exp_f32, v_log_f32, v_rcp_f32) are
-# quarter rate and count as 4 issue slots.
+# MI355X: 256 CUs at 2.4 GHz; a CU issues one full-rate wave64 VALU instruction
+# per clock (64 lane-ops) across its four SIMDs. Measured on gfx950: FP64 add, mul
+# and fma, conversions and FP32 max/ldexp run at that rate; FP32 add, mul and fma,
+# integer adds and moves at twice it (half an issue clock each); FP32
+# transcendentals at half of it (two clocks); FP64 reciprocal at a quarter (four).
+# The peak is the full-rate lane-op rate.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
-# VALU issue slots of one trapezoid node: the loop body of each form's node walk in
-# the gfx950 code of libbesselk.so, counted by the build (paper_2502_00356_amd/build.py
-# writes node_slots.json; quarter-rate transcendentals count 4).
+# VALU issue clocks of one trapezoid node: the loop body of each form's node walk
+# in the gfx950 code of libbesselk.so, weighted by those rates, counted by the
+# build (paper_2502_00356_amd/build.py writes node_slots.json).
 def load_node_slots():
     path = os.path.join(ROOT, "paper_2502_00356_amd", "node_slots.json")
-    slots = {"plain": 50.0, "mixed": 39.0, "learned": 36.0}
+    slots = {"plain": 49.5, "mixed": 13.75, "learned": 14.5}
     if os.path.exists(path):
         with open(path) as f:
             slots.update({k: float(v) for k, v in json.load(f).items()})
@@ -249,12 +251,13 @@ def main():
         "speedup_vs_plain_f64": forms["plain"]["ms_per_step"] / head["ms_per_step"] if "plain" in forms else 1.0,
         "max_rel_err_sample": acc,
         "max_rel_err_by_region": region,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (VALU lane-ops)",
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (full-rate VALU lane-op slots)",
                      "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": (TRAFFIC["bytes"] if (form == "learned" and a.n == TRAFFIC["n"]
                                                       and kernel_src_sha() == TRAFFIC["src_sha"]) else None),
                      "kernel": "k_besselk<%s>" % form,
-                     "work": "%.0f issue slots per trapezoid node x %d nodes per step" % (NODE_SLOTS[form], head["node_total"]),
+                     "work": "%.2f VALU issue clocks (full-rate lane-op slots) per trapezoid node x %d nodes per step"
+                             % (NODE_SLOTS[form], head["node_total"]),
                      "hbm_gbps": 24.0 * a.n / (head["ms_per_step"] * 1e-3) / 1e9},
         "cpu_baseline": cpu,
     }

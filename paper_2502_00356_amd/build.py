@@ -17,8 +17,30 @@ LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
 ARCH = os.environ.get("BK_OFFLOAD_ARCH", "gfx950")
 
 
-TRANS_QUARTER = ("v_exp_f32", "v_log_f32", "v_rcp_f32", "v_rsq_f32", "v_sqrt_f32", "v_sin_f32", "v_cos_f32",
-                 "v_rcp_f64", "v_rsq_f64", "v_sqrt_f64", "v_exp_f16", "v_log_f16")
+# Issue cost of a wave64 VALU instruction on gfx950 in CU clocks (one CU issues
+# one full-rate wave64 VALU instruction per clock across its four SIMDs), measured
+# on MI355X with independent chains of one instruction at a time: FP32 add, mul,
+# fma, 32-bit integer add and moves run at about two per clock; FP32
+# transcendentals at one per two clocks; FP64 reciprocal, square root and
+# reciprocal square root at one per four; everything else checked (FP64 add, mul,
+# fma, ldexp, rounding, conversions, FP32 max, ldexp and rounding, selects) at one
+# per clock.
+HALF_COST = ("v_add_f32", "v_sub_f32", "v_subrev_f32", "v_mul_f32", "v_fma_f32", "v_fmac_f32", "v_fmamk_f32",
+             "v_fmaak_f32", "v_mac_f32", "v_add_u32", "v_sub_u32", "v_subrev_u32", "v_mov_b32")
+DOUBLE_COST = ("v_exp_f32", "v_log_f32", "v_rcp_f32", "v_rsq_f32", "v_sqrt_f32", "v_sin_f32", "v_cos_f32",
+               "v_rcp_iflag_f32", "v_exp_f16", "v_log_f16")
+QUAD_COST = ("v_rcp_f64", "v_rsq_f64", "v_sqrt_f64")
+
+
+def issue_cost(op):
+    base = op.split("_e32")[0].split("_e64")[0].split("_dpp")[0].split("_sdwa")[0]
+    if base in QUAD_COST:
+        return 4.0
+    if base in DOUBLE_COST:
+        return 2.0
+    if base in HALF_COST:
+        return 0.5
+    return 1.0
 
 
 def _loops(lines):
@@ -41,11 +63,11 @@ def _loops(lines):
 
 
 def node_slots(asm_path):
-    """VALU issue slots of one trapezoid node per K_nu kernel, read from the gfx950
-    assembly of this build: the node loop is the innermost loop that evaluates the
-    node exponential (v_exp_f32 for the FP32-term forms; the inlined FP64 exp, one
-    v_ldexp_f64 without divisions or logarithms, for the plain form). Quarter-rate
-    transcendental instructions count four slots."""
+    """VALU issue cost of one trapezoid node per K_nu kernel, in CU clocks per wave
+    (issue_cost above), read from the gfx950 assembly of this build: the node loop
+    is the innermost loop that evaluates the node exponential (v_exp_f32 for the
+    FP32-term forms; the inlined FP64 exp, one v_ldexp_f64 without divisions or
+    logarithms, for the plain form)."""
     text = open(asm_path).read().split("\n")
     funcs = {}
     cur = None
@@ -71,8 +93,7 @@ def node_slots(asm_path):
             else:
                 ok = any(o.startswith("v_exp_f32") for o in ops) and "v_div_scale_f64" not in ops
             if ok:
-                slots = sum(4 if o.split("_e32")[0].split("_e64")[0] in TRANS_QUARTER else 1
-                            for o in ops if not o.startswith("v_mfma"))
+                slots = sum(issue_cost(o) for o in ops if not o.startswith("v_mfma"))
                 # an unrolled loop evaluates several nodes per trip: one node exponential each
                 per_trip = ops.count("v_ldexp_f64") if form == "plain" else sum(o.startswith("v_exp_f32") for o in ops)
                 slots = slots / max(1, per_trip)
