@@ -162,6 +162,14 @@ __device__ __forceinline__ bool special_value(double v, double z, int result, do
     return false;
 }
 
+// exp_tab's table into LDS; every thread of the block must call it (it ends with
+// a barrier).
+__device__ __forceinline__ void stage_exp2(double* s, const RuleTable* R)
+{
+    if (threadIdx.x < 64) s[threadIdx.x] = R->exp2_64[threadIdx.x];
+    __syncthreads();
+}
+
 // Final assembly from exp(-x) exp(Delta) h S (see bk_math.hpp).
 __device__ __forceinline__ double assemble(double z, double delta, double hs, int result)
 {
@@ -217,9 +225,11 @@ __global__ __launch_bounds__(kSolveBlock) void k_besselk(const double* __restric
                                                          unsigned long long* __restrict__ stats)
 {
     __shared__ unsigned int hist[64];
+    __shared__ double s_exp2[64];
     __shared__ double s_d[8][kSolveBlock];
     __shared__ int s_i[3][kSolveBlock];
     const int tid = threadIdx.x;
+    if (tid < 64) s_exp2[tid] = Rp->exp2_64[tid];   // read after the sorts' barriers
     const int64_t i = (int64_t)blockIdx.x * kSolveBlock + tid;
     double v = 0.0, z = 1.0;
     bool work = false;
@@ -270,7 +280,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_besselk(const double* __restric
         p.N = s_i[1][tid];
         p.mc = s_i[2][tid];
         const double A = s_d[6][tid], B = s_d[7][tid];
-        const double S = (MODE == BK_PLAIN_F64) ? sum_f64(v3, p, A, B) : sum_mixed(v3, z3, p, A);
+        const double S = (MODE == BK_PLAIN_F64) ? sum_f64(v3, p, A, B, s_exp2) : sum_mixed(v3, z3, p, A, s_exp2);
         out[(int64_t)blockIdx.x * kSolveBlock + l3] = assemble(z3, s_d[5][tid], p.h * S, result);
         nodes = (unsigned long long)(p.N + 1);
         ents = 1;
@@ -286,8 +296,11 @@ __global__ __launch_bounds__(kSolveBlock) void k_besselk(const double* __restric
 __global__ __launch_bounds__(256) void k_besselk_paper(const double* __restrict__ nu, const double* __restrict__ x,
                                                        double* __restrict__ out, int64_t n, int result, int bins,
                                                        double T, const TemmeCoef* __restrict__ Cp,
+                                                       const RuleTable* __restrict__ Rp,
                                                        unsigned long long* __restrict__ stats)
 {
+    __shared__ double s_exp2[64];
+    stage_exp2(s_exp2, Rp);
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long nodes = 0, ents = 0;
     if (i < n) {
@@ -298,7 +311,7 @@ __global__ __launch_bounds__(256) void k_besselk_paper(const double* __restrict_
                 // K directly; written as exp(-z) exp(0) (e^z K) for the shared assembly
                 r = assemble(z, 0.0, temme_k(v, z, *Cp) * exp(z), result);
             } else {
-                const FixedOut f = paper_fixed(v, z, bins, T);
+                const FixedOut f = paper_fixed(v, z, bins, T, s_exp2);
                 // K = exp(lscale) h S, written through Delta = lscale + z so that the
                 // shared assembly (exp(-z) exp(Delta) h S) applies
                 r = assemble(z, f.lscale + z, f.hs, result);
@@ -350,6 +363,8 @@ __global__ __launch_bounds__(256, 3) void k_besselk_deriv(const double* __restri
                                                        double Lq, const RuleTable* __restrict__ Rp,
                                                        unsigned long long* __restrict__ stats)
 {
+    __shared__ double s_exp2[64];
+    stage_exp2(s_exp2, Rp);
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long nodes = 0, ents = 0;
     if (i < n) {
@@ -368,21 +383,21 @@ __global__ __launch_bounds__(256, 3) void k_besselk_deriv(const double* __restri
         } else {
             const RuleTable& R = *Rp;
             const Solved s0 = plain_solve(v, z, L, Lq, R);
-            const double hs0 = s0.p.h * sum_f64(v, s0.p, s0.A, s0.B);
+            const double hs0 = s0.p.h * sum_f64(v, s0.p, s0.A, s0.B, s_exp2);
             rk = assemble(z, s0.delta, hs0, result);
             nodes += (unsigned long long)(s0.p.N + 1);
             rx = 0.0;
             if (dkdx) {
                 const double v1 = fabs(v - 1.0);
                 const Solved s1 = plain_solve(v1, z, L, Lq, R);
-                const double hs1 = s1.p.h * sum_f64(v1, s1.p, s1.A, s1.B);
+                const double hs1 = s1.p.h * sum_f64(v1, s1.p, s1.A, s1.B, s_exp2);
                 nodes += (unsigned long long)(s1.p.N + 1);
                 rx = -unscale(z, exp(s1.delta) * hs1 + (v / z) * (exp(s0.delta) * hs0), result);
             }
             rn = 0.0;
             if (dkdnu && v > 0.0) {
                 const Solved sd = dnu_solve(v, z, s0.p.t0, L, Lq, R);
-                const double hsd = sd.p.h * sum_dnu_f64(v, sd.p, sd.A, sd.B);
+                const double hsd = sd.p.h * sum_dnu_f64(v, sd.p, sd.A, sd.B, s_exp2);
                 nodes += (unsigned long long)(sd.p.N + 1);
                 rn = copysign(assemble(z, sd.delta, hsd, result), nr);
             } else if (dkdnu) {
@@ -443,6 +458,8 @@ __global__ __launch_bounds__(256) void k_matern(const double* __restrict__ lx,
                                                 const RuleTable* __restrict__ Rp, int bins, double T,
                                                 const TemmeCoef* __restrict__ Cp, OutT* __restrict__ out)
 {
+    __shared__ double s_exp2[64];
+    stage_exp2(s_exp2, Rp);                   // before any wave leaves
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
     const int64_t p = tile_base + (int64_t)blockIdx.x / wg_per_tile;
     const int64_t local = (int64_t)blockIdx.x % wg_per_tile;
@@ -473,12 +490,12 @@ __global__ __launch_bounds__(256) void k_matern(const double* __restrict__ lx,
                 if (z < kPaperTemmeX) {
                     val = sigma2 * exp(pref + nu * log(z)) * temme_k(nu, z, *Cp);
                 } else {
-                    const FixedOut f = paper_fixed(nu, z, bins, T);
+                    const FixedOut f = paper_fixed(nu, z, bins, T, s_exp2);
                     val = sigma2 * exp(pref + nu * log(z) + f.lscale) * f.hs;
                 }
             } else {
                 Solved s = plain_solve(nu, z, L, Lq, *Rp);
-                double S = (MODE == BK_PLAIN_F64) ? sum_f64(nu, s.p, s.A, s.B) : sum_mixed(nu, z, s.p, s.A);
+                double S = (MODE == BK_PLAIN_F64) ? sum_f64(nu, s.p, s.A, s.B, s_exp2) : sum_mixed(nu, z, s.p, s.A, s_exp2);
                 val = sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * (s.p.h * S);
             }
         }
@@ -500,6 +517,8 @@ __global__ __launch_bounds__(256) void k_matern_grad(const double* __restrict__ 
                                                      const RuleTable* __restrict__ Rp, OutT* __restrict__ oc,
                                                      OutT* __restrict__ ob, OutT* __restrict__ on)
 {
+    __shared__ double s_exp2[64];
+    stage_exp2(s_exp2, Rp);                   // before any wave leaves
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
     const int64_t p = tile_base + (int64_t)blockIdx.x / wg_per_tile;
     const int64_t local = (int64_t)blockIdx.x % wg_per_tile;
@@ -527,16 +546,16 @@ __global__ __launch_bounds__(256) void k_matern_grad(const double* __restrict__ 
             const RuleTable& R = *Rp;
             const double z = r * inv_beta, lz = log(z);
             const Solved s0 = plain_solve(nu, z, L, Lq, R);
-            vc = sigma2 * exp(pref + nu * lz + (s0.delta - z)) * (s0.p.h * sum_f64(nu, s0.p, s0.A, s0.B));
+            vc = sigma2 * exp(pref + nu * lz + (s0.delta - z)) * (s0.p.h * sum_f64(nu, s0.p, s0.A, s0.B, s_exp2));
             if (ob) {
                 const Solved s1 = plain_solve(nu1, z, L, Lq, R);
                 vb = sigma2 * inv_beta * exp(pref + (nu + 1.0) * lz + (s1.delta - z)) *
-                     (s1.p.h * sum_f64(nu1, s1.p, s1.A, s1.B));
+                     (s1.p.h * sum_f64(nu1, s1.p, s1.A, s1.B, s_exp2));
             }
             if (on) {
                 const Solved sd = dnu_solve(nu, z, s0.p.t0, L, Lq, R);
                 vn = vc * (lz - kLn2 - psi) +
-                     sigma2 * exp(pref + nu * lz + (sd.delta - z)) * (sd.p.h * sum_dnu_f64(nu, sd.p, sd.A, sd.B));
+                     sigma2 * exp(pref + nu * lz + (sd.delta - z)) * (sd.p.h * sum_dnu_f64(nu, sd.p, sd.A, sd.B, s_exp2));
             }
         }
         const int64_t o = base + il + jl * mI;
@@ -611,7 +630,7 @@ extern "C" int bk_besselk_ex(const double* nu, const double* x, double* out, int
         const int64_t b256 = (n + 255) / 256;
         hipLaunchKernelGGL(k_besselk_paper, dim3((unsigned)b256), dim3(256), 0, stream, nu, x, out, n, prm->result,
                            prm->bins > 0 ? prm->bins : kPaperBins, prm->t_upper > 0.0 ? prm->t_upper : kPaperT, Cp,
-                           prm->stats);
+                           R, prm->stats);
         return launch_status();
     }
     default:

@@ -62,6 +62,30 @@ __device__ __forceinline__ double recip(double a)
     return fma(r, fma(-a, r, 1.0), r);
 }
 
+// e^x from T[j] = 2^(j/64), j = 0..63 (Tang's table-driven method): with
+// k = floor(64 x log2 e) and f = x - k ln2/64, in [0, ln2/64) up to rounding,
+// e^x = 2^(k div 64) T[k mod 64] e^f, and e^f is its Taylor polynomial through f^6
+// (truncation below 2e-18). ln2/64 rounded to FP64 is off by < 1e-19, so the
+// reduction adds at most |k| 1e-19 relative (< 1e-15 for |x| < 700); within a
+// few ulps overall. x is clamped at -746, where e^x is already below half the
+// smallest subnormal and the final ldexp gives 0 (also for x = -inf); ldexp takes
+// large x to infinity. The kernels stage T in LDS.
+__device__ __forceinline__ double exp_tab(double x, const double* T)
+{
+    x = fmax(x, -746.0);
+    const double k = floor(x * 92.332482616893656);          // 64 log2 e
+    const double f = fma(-k, 0.010830424696249145, x);        // ln2 / 64
+    double p = 1.0 / 720.0;
+    p = fma(p, f, 1.0 / 120.0);
+    p = fma(p, f, 1.0 / 24.0);
+    p = fma(p, f, 1.0 / 6.0);
+    p = fma(p, f, 0.5);
+    p = fma(p, f, 1.0);
+    p = fma(p, f, 1.0);
+    const int ki = (int)k;
+    return ldexp(T[ki & 63] * p, ki >> 6);
+}
+
 __device__ __forceinline__ void cosh_sinh(double t, double& ch, double& sh)
 {
     double e = exp(t);
@@ -299,40 +323,19 @@ __device__ __forceinline__ void walk_step(Walk& w, int m)
     w.V = (m + 1 <= w.mc) ? vin : vout;
 }
 
-// FP64 trapezoid sum S = sum_m c_m exp(d_m) (1 + P_m), c_0 = c_N = 1/2.
-__device__ inline double sum_f64(double nu, const Plan& p, double A, double B)
+// FP64 trapezoid sum S = sum_m c_m exp(d_m) (1 + P_m), c_0 = c_N = 1/2; T is
+// exp_tab's table.
+__device__ inline double sum_f64(double nu, const Plan& p, double A, double B, const double* T)
 {
     Walk w = walk_begin(nu, p);
     double S = 0.0, ends = 0.0;
     for (int m = 0; m <= p.N; ++m) {
-        double term = exp(walk_exponent(w, m, nu, A, B)) * (1.0 + w.P);
+        double term = exp_tab(walk_exponent(w, m, nu, A, B), T) * (1.0 + w.P);
         S += term;
         if (m == 0 || m == p.N) ends += term;
         walk_step(w, m);
     }
     return S - 0.5 * ends;
-}
-
-// expm1(w) for 0 <= w <= 0.3 by its Taylor polynomial through w^14 (truncation
-// below 2e-18 relative); larger w go to the library routine.
-__device__ __forceinline__ double expm1_small(double w)
-{
-    if (!(w <= 0.3)) return expm1(w);
-    double p = 1.0 / 87178291200.0;                    // 1/14!
-    p = fma(p, w, 1.0 / 6227020800.0);
-    p = fma(p, w, 1.0 / 479001600.0);
-    p = fma(p, w, 1.0 / 39916800.0);
-    p = fma(p, w, 1.0 / 3628800.0);
-    p = fma(p, w, 1.0 / 362880.0);
-    p = fma(p, w, 1.0 / 40320.0);
-    p = fma(p, w, 1.0 / 5040.0);
-    p = fma(p, w, 1.0 / 720.0);
-    p = fma(p, w, 1.0 / 120.0);
-    p = fma(p, w, 1.0 / 24.0);
-    p = fma(p, w, 1.0 / 6.0);
-    p = fma(p, w, 0.5);
-    p = fma(p, w, 1.0);
-    return p * w;
 }
 
 // Node walk of the FP32-term forms (mixed and learned). Their terms need the
@@ -343,28 +346,6 @@ __device__ __forceinline__ double expm1_small(double w)
 // few m^2 ulps), so the absolute error of d_m is about x cosh(t_m) m^2 2^-53,
 // below 1e-10 on the whole (nu, x) range. The factor Q = 1 + e^(-2 nu t) follows
 // Q' = rho Q + (1 - rho), rho = e^(-2 nu h) (contracting, so no error growth).
-// e^x for |x| < 700 from T[j] = 2^(j/64), j = 0..63 (Tang's table-driven method):
-// with k = floor(64 x log2 e) and f = x - k ln2/64, in [0, ln2/64) up to rounding,
-// e^x = 2^(k div 64) T[k mod 64] e^f, and e^f is its Taylor polynomial through f^6
-// (truncation below 2e-18). ln2/64 rounded to FP64 is off by < 1e-19, so the
-// reduction adds at most |k| 1e-19 (< 1e-15 for |x| < 700); the result is within
-// a few ulps for the arguments of the walk set-up (|x| < 20), where the FP32-term
-// forms need about 1e-12.
-__device__ __forceinline__ double exp_tab(double x, const double* T)
-{
-    const double k = floor(x * 92.332482616893656);          // 64 log2 e
-    const double f = fma(-k, 0.010830424696249145, x);        // ln2 / 64
-    double p = 1.0 / 720.0;
-    p = fma(p, f, 1.0 / 120.0);
-    p = fma(p, f, 1.0 / 24.0);
-    p = fma(p, f, 1.0 / 6.0);
-    p = fma(p, f, 0.5);
-    p = fma(p, f, 1.0);
-    p = fma(p, f, 1.0);
-    const int ki = (int)k;
-    return ldexp(T[ki & 63] * p, ki >> 6);
-}
-
 struct WalkF {
     double c, cn, kappa;      // cosh t_m, cosh t_{m+1}, 2 cosh h
     double a2, e, b2;         // d_m = a2 c_m + e_m; e_m = x cosh(t_ref) log2 e + (m - m_ref) b2, advanced by b2
@@ -373,27 +354,8 @@ struct WalkF {
 // e_m accumulates one rounding per node: m ulps of |e| <= x cosh t_ref + 30, below
 // 1e-11 absolute in d_m for the windows here (the FP32 terms need ~1e-8).
 
-// e = e^{t_0}, ei = e^{-t_0} and q = e^{h/2}, qi = e^{-h/2} given by the caller.
-__device__ __forceinline__ WalkF walkf_begin(double nu, double x, double t0, double h, int mref, double xch_ref,
-                                             double e, double ei, double q, double qi)
-{
-    WalkF w;
-    const double q2 = q * q, qi2 = qi * qi;
-    w.kappa = q2 + qi2;
-    w.c = 0.5 * (e + ei);
-    w.cn = 0.5 * (e * q2 + ei * qi2);
-    w.a2 = -x * kLog2e;
-    w.b2 = nu * h * kLog2e;
-    w.e = fma(-(double)mref, w.b2, xch_ref * kLog2e);
-    w.rho = exp(-2.0 * nu * h);
-    w.omr = 1.0 - w.rho;              // absolute error 2^-53: Q's error stays ~m 2^-53
-    // Q only needs FP32 accuracy: e^(-2 nu t_0) in FP32 moves Q by < 6e-8 relative
-    w.Q = 1.0 + (double)__expf((float)(-2.0 * nu * t0));
-    return w;
-}
-
-// The same state from the exponentials themselves: e = e^{t_0}, ei = e^{-t_0},
-// q2 = e^h, qi2 = e^{-h}, rho = e^{-2 nu h}.
+// Walk state from the exponentials e = e^{t_0}, ei = e^{-t_0}, q2 = e^h,
+// qi2 = e^{-h}, rho = e^{-2 nu h} (given by the caller).
 __device__ __forceinline__ WalkF walkf_begin_exp(double nu, double x, double t0, double h, int mref, double xch_ref,
                                                  double e, double ei, double q2, double qi2, double rho)
 {
@@ -405,7 +367,8 @@ __device__ __forceinline__ WalkF walkf_begin_exp(double nu, double x, double t0,
     w.b2 = nu * h * kLog2e;
     w.e = fma(-(double)mref, w.b2, xch_ref * kLog2e);
     w.rho = rho;
-    w.omr = 1.0 - rho;
+    w.omr = 1.0 - rho;                // absolute error 2^-53: Q's error stays ~m 2^-53
+    // Q only needs FP32 accuracy: e^(-2 nu t_0) in FP32 moves Q by < 6e-8 relative
     w.Q = 1.0 + (double)__expf((float)(-2.0 * nu * t0));
     return w;
 }
@@ -423,12 +386,13 @@ __device__ __forceinline__ void walkf_step(WalkF& w)
 
 // Mixed form: the walk above with the reference at the node nearest the peak
 // (exponents <= about 0), exponential in FP32, Kahan-compensated FP32 sum.
-// A = x cosh(t_ref) / 2 from the solve. Returns sum_m c_m e^{d_m} (1 + P_m).
-__device__ inline double sum_mixed(double nu, double x, const Plan& p, double A)
+// A = x cosh(t_ref) / 2 from the solve; T is exp_tab's table. Returns
+// sum_m c_m e^{d_m} (1 + P_m).
+__device__ inline double sum_mixed(double nu, double x, const Plan& p, double A, const double* T)
 {
-    const double e = exp(p.t0), ei = recip(e);
-    const double q = 1.0 + expm1_small(0.5 * p.h), qi = recip(q);
-    WalkF w = walkf_begin(nu, x, p.t0, p.h, p.mc, 2.0 * A, e, ei, q, qi);
+    const double e = exp_tab(p.t0, T), ei = recip(e);
+    const double q2 = exp_tab(p.h, T), qi2 = recip(q2);
+    WalkF w = walkf_begin_exp(nu, x, p.t0, p.h, p.mc, 2.0 * A, e, ei, q2, qi2, exp_tab(-2.0 * nu * p.h, T));
     float s = 0.0f, c = 0.0f, ends = 0.0f;
 #pragma unroll 2
     for (int m = 0; m <= p.N; ++m) {
@@ -548,7 +512,7 @@ __device__ inline Solved dnu_solve(double nu, double x, double t0, double L, dou
 }
 
 // FP64 trapezoid sum of D's node terms e^(nu u - xterm) t (1 - P).
-__device__ inline double sum_dnu_f64(double nu, const Plan& p, double A, double B)
+__device__ inline double sum_dnu_f64(double nu, const Plan& p, double A, double B, const double* T)
 {
     Walk w = walk_begin(nu, p);
     double Q = -expm1(-2.0 * nu * p.t0);
@@ -556,7 +520,7 @@ __device__ inline double sum_dnu_f64(double nu, const Plan& p, double A, double 
     double S = 0.0, ends = 0.0;
     for (int m = 0; m <= p.N; ++m) {
         const double t = fma((double)m, p.h, p.t0);
-        const double term = exp(walk_exponent(w, m, nu, A, B)) * t * Q;
+        const double term = exp_tab(walk_exponent(w, m, nu, A, B), T) * t * Q;
         S += term;
         if (m == 0 || m == p.N) ends += term;
         walk_step(w, m);
@@ -601,13 +565,13 @@ __device__ inline void walk_reseed(Walk& w, const Plan& p, double nu, int m)
 constexpr int kFixedPlainMax = 256;
 
 template <bool Comp>
-__device__ inline double fixed_sum(double nu, const Plan& p, double A, double B)
+__device__ inline double fixed_sum(double nu, const Plan& p, double A, double B, const double* T)
 {
     Walk w = walk_begin(nu, p);
     double S = 0.0, c = 0.0, ends = 0.0;
     for (int m = 0; m <= p.N; ++m) {
         if (m > 0 && m % kReseed == 0) walk_reseed(w, p, nu, m);
-        const double term = exp(walk_exponent(w, m, nu, A, B)) * (1.0 + w.P);
+        const double term = exp_tab(walk_exponent(w, m, nu, A, B), T) * (1.0 + w.P);
         if (Comp) {
             const double y = term - c, t = S + y;
             c = (t - S) - y;
@@ -621,7 +585,7 @@ __device__ inline double fixed_sum(double nu, const Plan& p, double A, double B)
     return (S - c) - 0.5 * ends;
 }
 
-__device__ inline FixedOut paper_fixed(double nu, double x, int bins, double T)
+__device__ inline FixedOut paper_fixed(double nu, double x, int bins, double T, const double* E)
 {
     const double tstar = (nu * nu > x) ? peak_solve(nu, x) : 0.0;
     Plan p;
@@ -637,7 +601,7 @@ __device__ inline FixedOut paper_fixed(double nu, double x, int bins, double T)
     const double A = 0.5 * x * ch, B = 0.5 * x * sh;
     FixedOut o;
     o.lscale = nu * p.tref - kLn2 - 2.0 * x * sh2 * sh2 - x;
-    o.hs = p.h * (bins > kFixedPlainMax ? fixed_sum<true>(nu, p, A, B) : fixed_sum<false>(nu, p, A, B));
+    o.hs = p.h * (bins > kFixedPlainMax ? fixed_sum<true>(nu, p, A, B, E) : fixed_sum<false>(nu, p, A, B, E));
     return o;
 }
 

@@ -565,13 +565,16 @@ __global__ __launch_bounds__(256) void k_besselk_fallback(const double* __restri
                                                           const RuleTable* __restrict__ Rp,
                                                           unsigned long long* __restrict__ stats)
 {
+    __shared__ double s_exp2[64];
+    if (threadIdx.x < 64) s_exp2[threadIdx.x] = Rp->exp2_64[threadIdx.x];
+    __syncthreads();
     const unsigned int cnt = *qcount;
     unsigned long long nodes = 0, ents = 0;
     for (unsigned int j = blockIdx.x * 256 + threadIdx.x; j < cnt; j += gridDim.x * 256) {
         const unsigned int i = queue[j];
         const double v = fabs(nu[i]), z = x[i];
         Solved s = plain_solve(v, z, L, Lq, *Rp);
-        const double S = sum_mixed(v, z, s.p, s.A);
+        const double S = sum_mixed(v, z, s.p, s.A, s_exp2);
         out[i] = assemble_k(z, s.delta, s.p.h * S, result);
         nodes += (unsigned long long)(s.p.N + 1);
         ents += 1;
@@ -717,6 +720,9 @@ __global__ __launch_bounds__(256) void k_matern_fallback(const double* __restric
                                                          const unsigned int* __restrict__ mlist, OutT* __restrict__ out)
 {
     constexpr int kColsPerWave = 8, kColsPerGroup = 32;
+    __shared__ double s_exp2[64];
+    if (threadIdx.x < 64) s_exp2[threadIdx.x] = Rp->exp2_64[threadIdx.x];
+    __syncthreads();
     const unsigned int cnt = mlist[0];
     const int lane = threadIdx.x & 63;
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
@@ -744,7 +750,7 @@ __global__ __launch_bounds__(256) void k_matern_fallback(const double* __restric
             const double dx = lx_[J * g.ts + jl] - xi, dy = ly_[J * g.ts + jl] - yi;
             const double z = sqrt(dx * dx + dy * dy) * inv_beta;
             const Solved s = plain_solve(nu, z, L, Lq, *Rp);
-            const double hs = s.p.h * sum_mixed(nu, z, s.p, s.A);
+            const double hs = s.p.h * sum_mixed(nu, z, s.p, s.A, s_exp2);
             out[o] = (OutT)(sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * hs);
         }
     }
