@@ -77,7 +77,7 @@ def node_slots(asm_path):
             funcs[cur] = []
         elif cur is not None:
             funcs[cur].append(l)
-    want = {"plain": "k_besselkILi0", "mixed": "k_besselkILi1", "learned": "k_besselk_learned"}
+    want = {"plain": "k_besselkILi0", "mixed": "k_besselkILi1", "learned": "k_besselk_learnedILb1"}
     out = {}
     for form, key in want.items():
         name = next((f for f in funcs if key in f), None)

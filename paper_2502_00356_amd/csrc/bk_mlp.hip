@@ -37,6 +37,7 @@
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef double double4_t __attribute__((ext_vector_type(4)));
 
 namespace bk {
 
@@ -74,6 +75,8 @@ struct MlpDev {
     float lx_lo, lx_hi, nu_lo, nu_hi;   // training box
     float d_lo, d_hi, eta, n_add;       // margins
     const float4_t* cells;              // [kCellsLx][kCellsNu] cell windows (normalised y0, y1, y2, 0)
+    const float4_t* plan_a;             // [cell] quadrature plan: t_lo, t_hi, N (int bits), flags (int bits)
+    const double4_t* plan_b;            // [cell] quadrature plan: h, cosh t_lo, cosh(t_lo + h), 2 cosh h
     float cl_scale, cn_scale;           // cells per unit of log10 x and of nu
 };
 
@@ -85,6 +88,9 @@ struct bk_model {
     float* bias = nullptr;        // device b2 (64) and b3 (3)
     float* table = nullptr;       // device Matern window table [kTableSize][4]
     float* cells = nullptr;       // device prediction cells [kCellsLx][kCellsNu][4]
+    float* plan_a = nullptr;      // device per-cell quadrature plans (float4 part)
+    double* plan_b = nullptr;     // device per-cell quadrature plans (double4 part)
+    double plan_Lq = -1.0;        // node target the plans were built for (< 0: none)
     unsigned int* mlist = nullptr; // device Matern fallback list: count at [0], wave ids from [64]
     double norm[8] = {-0.5, 3.5, 5.005, 4.995, 8.0, 32.0, 0.0, 0.0};
     double box[4] = {-4.0, 3.0, 0.01, 10.0};
@@ -115,6 +121,8 @@ static MlpDev make_dev(const bk_model* m)
     d.d_lo = (float)m->margins[0]; d.d_hi = (float)m->margins[1];
     d.eta = (float)m->margins[2]; d.n_add = (float)m->margins[3];
     d.cells = reinterpret_cast<const float4_t*>(m->cells);
+    d.plan_a = reinterpret_cast<const float4_t*>(m->plan_a);
+    d.plan_b = reinterpret_cast<const double4_t*>(m->plan_b);
     d.cl_scale = (float)((double)kCellsLx / (m->box[1] - m->box[0]));
     d.cn_scale = (float)((double)kCellsNu / (m->box[3] - m->box[2]));
     return d;
@@ -267,11 +275,11 @@ __global__ __launch_bounds__(256) void k_cell_table(MlpDev M, float4_t* __restri
 
 // The cell of an entry inside the training box (the last cell of each axis also
 // takes the box's upper edge).
-__device__ __forceinline__ float4_t cell_of(const MlpDev& M, float lx, float v)
+__device__ __forceinline__ int cell_index(const MlpDev& M, float lx, float v)
 {
     const int i = min(max((int)((lx - M.lx_lo) * M.cl_scale), 0), kCellsLx - 1);
     const int j = min(max((int)((v - M.nu_lo) * M.cn_scale), 0), kCellsNu - 1);
-    return M.cells[i * kCellsNu + j];
+    return i * kCellsNu + j;
 }
 
 // ---------------------------------------------------------------------------
@@ -283,21 +291,50 @@ struct LearnedOut {
     int reason;     // 0 accepted, else a BK_STAT_FB_* index
 };
 
-// T: the table 2^(j/64) of exp_tab (in LDS where the kernel stages it).
-__device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double thi, int N, const double* T)
+// Quadrature plan of a learned window: nodes t_lo + m h, m = 0..N, and the start of
+// the cosh recurrence, c0 = cosh t_lo, c1 = cosh(t_lo + h), kappa = 2 cosh h.
+struct LearnedPlan {
+    double tlo, h, c0, c1, kappa;
+    int N;
+};
+
+// The plan of the window [t_lo, t_hi] with N intervals. Any step works as long as
+// the walk uses it consistently: an FP32 reciprocal of N puts the last node within
+// ~1e-7 of t_hi. T: the table 2^(j/64) of exp_tab.
+__device__ inline LearnedPlan learned_plan(double tlo, double thi, int N, const double* T)
+{
+    LearnedPlan P;
+    P.tlo = tlo;
+    P.N = N;
+    P.h = (thi - tlo) * (double)__builtin_amdgcn_rcpf((float)N);
+    const double e = exp_tab(tlo, T), ei = recip(e);
+    const double q2 = exp_tab(P.h, T), qi2 = recip(q2);
+    P.c0 = 0.5 * (e + ei);
+    P.c1 = 0.5 * (e * q2 + ei * qi2);
+    P.kappa = q2 + qi2;
+    return P;
+}
+
+// The node sum of a plan for one (nu, x), its prefactor and the acceptance tests.
+__device__ inline LearnedOut learned_walk(double nu, double x, const LearnedPlan& P, const double* T)
 {
     LearnedOut o;
     o.reason = 0;
-    // any step works as long as the walk uses it consistently: an FP32 reciprocal of N
-    // puts the last node within ~1e-7 of t_hi
-    const double h = (thi - tlo) * (double)__builtin_amdgcn_rcpf((float)N);
+    const double tlo = P.tlo, h = P.h;
+    const int N = P.N;
     // reference t_ref = t_lo; sinh^2(t/2) = (cosh t - 1) / 2 loses ~1e-16 absolute,
     // i.e. at most ~2e-13 relative in the scale for x <= 1e3, far inside this form's budget
-    const double e = exp_tab(tlo, T), ei = recip(e);
-    const double ch = 0.5 * (e + ei);
-    o.delta = nu * tlo - kLn2 - x * (ch - 1.0);
-    const double q2 = exp_tab(h, T), qi2 = recip(q2);
-    WalkF w = walkf_begin_exp(nu, x, tlo, h, 0, x * ch, e, ei, q2, qi2, exp_tab(-2.0 * nu * h, T));
+    o.delta = nu * tlo - kLn2 - x * (P.c0 - 1.0);
+    WalkF w;
+    w.kappa = P.kappa;
+    w.c = P.c0;
+    w.cn = P.c1;
+    w.a2 = -x * kLog2e;
+    w.b2 = nu * h * kLog2e;
+    w.e = x * P.c0 * kLog2e;
+    w.rho = exp_tab(-2.0 * nu * h, T);
+    w.omr = 1.0 - w.rho;
+    w.Q = 1.0 + (double)__expf((float)(-2.0 * nu * tlo));
     // the exponent is not bounded above here (t_lo is not the peak), so the FP32
     // exponential is split as 2^k 2^f with k, f formed in FP64; the FP32 terms are
     // summed in FP64, whose rounding is negligible next to theirs
@@ -345,6 +382,11 @@ __device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double
     return o;
 }
 
+__device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double thi, int N, const double* T)
+{
+    return learned_walk(nu, x, learned_plan(tlo, thi, N, T), T);
+}
+
 // Step floor for the learned forms: the strip bound of node_step at a single
 // half-width, a = min(sqrt(2 (Lq + ln 2) / (x + nu + 1)), 1.3) (the maximiser of
 // the bound's small-a expansion, capped), in FP32 with 1 - cos a = 2 sin^2(a/2),
@@ -382,6 +424,45 @@ __device__ __forceinline__ void decode_window(const MlpDev& M, float y0, float y
 __device__ __forceinline__ bool in_box(const MlpDev& M, float lx, float v)
 {
     return lx >= M.lx_lo && lx <= M.lx_hi && v >= M.nu_lo && v <= M.nu_hi;
+}
+
+// Quadrature plans of the prediction cells for the node target Lq, one lane per
+// cell: the window decoded from the cell's union with the model's margins; the node
+// count from the prediction, raised to the strip-bound floor taken at the cell's
+// corner of largest x and nu (at any point of the cell the half-width of that
+// corner gives a larger admissible step, so this floor holds over the whole cell);
+// and the start of the walk in FP64. plan_a: t_lo, t_hi, N (-1 if the window is
+// empty or not finite) and flags (bit 0: N raised), the last two as int bits.
+__global__ __launch_bounds__(256) void k_cell_plans(MlpDev M, double Lq, float4_t* __restrict__ pa,
+                                                    double4_t* __restrict__ pb)
+{
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= kCells) return;
+    const int i = c / kCellsNu, j = c % kCellsNu;
+    const float4_t y = M.cells[c];
+    const double lxm = (double)M.lx_lo + (double)(i + 1) * (((double)M.lx_hi - (double)M.lx_lo) / kCellsLx);
+    const double xm = exp10(lxm);
+    const double num = (double)M.nu_lo + (double)(j + 1) * (((double)M.nu_hi - (double)M.nu_lo) / kCellsNu);
+    double tlo, thi;
+    int N;
+    bool raised;
+    decode_window(M, y[0], y[1], y[2], num, xm, Lq, tlo, thi, N, raised);
+    const bool valid = thi > tlo && isfinite(thi);
+    float4_t a;
+    a[0] = (float)tlo;                    // exact: the window ends are FP32 values
+    a[1] = (float)thi;
+    a[2] = __int_as_float(valid ? N : -1);
+    a[3] = __int_as_float(raised ? 1 : 0);
+    pa[c] = a;
+    double4_t b = {0.0, 1.0, 1.0, 2.0};
+    if (valid) {
+        const double h = (thi - tlo) * (double)__builtin_amdgcn_rcpf((float)N);
+        b[0] = h;
+        b[1] = cosh(tlo);
+        b[2] = cosh(tlo + h);
+        b[3] = 2.0 * cosh(h);
+    }
+    pb[c] = b;
 }
 
 // c e^r for the FP32-term forms: r log2 e = k + f is split in FP64 (|f| <= 1/2),
@@ -450,14 +531,17 @@ __device__ void block_stats_w(unsigned long long* stats, const unsigned long lon
     }
 }
 
-// Learned K_nu. Phase 1 (entry order): range check, the entry's prediction cell,
-// window decode. Phase 2: the block's entries are counting-sorted by node count
+// Learned K_nu. Phase 1 (entry order): range check, the entry's prediction cell
+// and, with kPlan (the call's node target is the one the cells' plans were built
+// for), the cell's quadrature plan, else the window decoded for this entry.
+// Phase 2: the block's entries are counting-sorted by node count
 // through LDS, so each wave walks entries of similar N (the wave runs as many
 // node steps as its largest N). Phase 3 (sorted order): node sums, tail checks,
 // stores to the entry's own index or the fallback queue.
 constexpr int kLearnedBlock = 256;
 constexpr int kSortBins = 64;
 
+template <bool kPlan>
 __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, const double* __restrict__ nu,
                                                                    const double* __restrict__ x,
                                                                    double* __restrict__ out, int64_t n, int result,
@@ -471,8 +555,10 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
     __shared__ double s_v[kLearnedBlock], s_z[kLearnedBlock], s_tlo[kLearnedBlock], s_thi[kLearnedBlock];
     __shared__ int s_N[kLearnedBlock];
     __shared__ unsigned int s_idx[kLearnedBlock];
+    __shared__ int s_cell[kLearnedBlock];        // plan path only
     const int tid = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * kLearnedBlock + tid;
+    int cell = 0;
     const bool live = i < n;
     double v = 0.0, z = 1.0;
     if (live) { v = fabs(nu[i]); z = x[i]; }
@@ -493,13 +579,23 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
                 reject = true;
                 c_range = 1;
             } else {
-                bool raised;
-                int Nd;
-                const float4_t y = cell_of(M, lx, (float)v);
-                decode_window(M, y[0], y[1], y[2], v, z, Lq, tlo, thi, Nd, raised);
-                c_raised = raised ? 1u : 0u;
-                if (!(thi > tlo) || !isfinite(thi)) { reject = true; c_nonfin = 1; }
-                else N = Nd;
+                if constexpr (kPlan) {
+                    cell = cell_index(M, lx, (float)v);
+                    const float4_t a = M.plan_a[cell];
+                    tlo = (double)a[0];
+                    const int Nd = __float_as_int(a[2]);
+                    c_raised = (unsigned int)(__float_as_int(a[3]) & 1);
+                    if (Nd < 0) { reject = true; c_nonfin = 1; }
+                    else N = Nd;
+                } else {
+                    bool raised;
+                    int Nd;
+                    const float4_t y = M.cells[cell_index(M, lx, (float)v)];
+                    decode_window(M, y[0], y[1], y[2], v, z, Lq, tlo, thi, Nd, raised);
+                    c_raised = raised ? 1u : 0u;
+                    if (!(thi > tlo) || !isfinite(thi)) { reject = true; c_nonfin = 1; }
+                    else N = Nd;
+                }
             }
             if (reject) {
                 const unsigned int slot = atomicAdd(qcount, 1u);
@@ -526,7 +622,8 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
     s_v[dst] = v;
     s_z[dst] = z;
     s_tlo[dst] = tlo;
-    s_thi[dst] = thi;
+    if constexpr (kPlan) s_cell[dst] = cell;
+    else s_thi[dst] = thi;
     s_N[dst] = N;
     s_idx[dst] = (unsigned int)i;
     __syncthreads();
@@ -534,7 +631,19 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
     if (Ns >= 0) {
         const double vs = s_v[tid], zs = s_z[tid];
         const unsigned int idx = s_idx[tid];
-        LearnedOut lo = learned_sum(vs, zs, s_tlo[tid], s_thi[tid], Ns, s_exp2);
+        LearnedPlan P;
+        if constexpr (kPlan) {
+            const double4_t b = M.plan_b[s_cell[tid]];
+            P.tlo = s_tlo[tid];
+            P.h = b[0];
+            P.c0 = b[1];
+            P.c1 = b[2];
+            P.kappa = b[3];
+            P.N = Ns;
+        } else {
+            P = learned_plan(s_tlo[tid], s_thi[tid], Ns, s_exp2);
+        }
+        LearnedOut lo = learned_walk(vs, zs, P, s_exp2);
         c_nodes = (unsigned int)(Ns + 1);
         c_ent = 1;
         if (lo.reason == 0) {
@@ -965,20 +1074,29 @@ static int model_alloc(bk_model* m)
     if (hipMalloc((void**)&m->bias, sizeof(float) * 68) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->table, sizeof(float) * 4 * kTableSize) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->cells, sizeof(float) * 4 * kCells) != hipSuccess) return BK_ENOMEM;
+    if (hipMalloc((void**)&m->plan_a, sizeof(float) * 4 * kCells) != hipSuccess) return BK_ENOMEM;
+    if (hipMalloc((void**)&m->plan_b, sizeof(double) * 4 * kCells) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->mlist, sizeof(unsigned int) * (64 + (size_t)kMaternWavesPerLaunch)) != hipSuccess)
         return BK_ENOMEM;
     return BK_OK;
 }
 
-// Prediction cells for the current parameters, normalisation and box (synchronous,
-// on the null stream; nothing to do before the parameters exist).
+// Prediction cells and their quadrature plans (at the default node target) for the
+// current parameters, normalisation, box and margins (synchronous, on the null
+// stream; nothing to do before the parameters exist).
 static int model_cells(bk_model* m)
 {
     if (!m->params) return BK_OK;
+    m->plan_Lq = -1.0;
     hipLaunchKernelGGL(k_cell_table, dim3((kCells + 255) / 256), dim3(256), 0, nullptr, make_dev(m),
                        reinterpret_cast<float4_t*>(m->cells));
+    hipLaunchKernelGGL(k_cell_plans, dim3((kCells + 255) / 256), dim3(256), 0, nullptr, make_dev(m),
+                       kDefaultLqMixed, reinterpret_cast<float4_t*>(m->plan_a),
+                       reinterpret_cast<double4_t*>(m->plan_b));
     if (hipGetLastError() != hipSuccess) return BK_EHIP;
-    return hip_ok(hipStreamSynchronize(nullptr));
+    const int st = hip_ok(hipStreamSynchronize(nullptr));
+    if (st == BK_OK) m->plan_Lq = kDefaultLqMixed;
+    return st;
 }
 
 // Upload host parameters: master copy and inference pack, then the prediction
@@ -1031,8 +1149,12 @@ int bk_besselk_learned(const double* nu, const double* x, double* out, int64_t n
     if (!R) return BK_EHIP;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, qcount);
     const unsigned blocks = (unsigned)((n + kLearnedBlock - 1) / kLearnedBlock);
-    hipLaunchKernelGGL(k_besselk_learned, dim3(blocks), dim3(kLearnedBlock), 0, stream, M, nu, x, out, n,
-                       prm->result, Lq, R, qcount, queue, prm->stats);
+    if (m->plan_Lq == Lq)
+        hipLaunchKernelGGL(k_besselk_learned<true>, dim3(blocks), dim3(kLearnedBlock), 0, stream, M, nu, x, out, n,
+                           prm->result, Lq, R, qcount, queue, prm->stats);
+    else
+        hipLaunchKernelGGL(k_besselk_learned<false>, dim3(blocks), dim3(kLearnedBlock), 0, stream, M, nu, x, out, n,
+                           prm->result, Lq, R, qcount, queue, prm->stats);
     hipLaunchKernelGGL(k_besselk_fallback, dim3(1024), dim3(256), 0, stream, nu, x, out, prm->result, qcount, queue, L,
                        Lq, R, prm->stats);
     return hipGetLastError() == hipSuccess ? BK_OK : BK_EHIP;
@@ -1108,6 +1230,8 @@ extern "C" void bk_model_destroy(bk_model* m)
     if (m->bias) (void)hipFree(m->bias);
     if (m->table) (void)hipFree(m->table);
     if (m->cells) (void)hipFree(m->cells);
+    if (m->plan_a) (void)hipFree(m->plan_a);
+    if (m->plan_b) (void)hipFree(m->plan_b);
     if (m->mlist) (void)hipFree(m->mlist);
     delete m;
 }
@@ -1167,7 +1291,7 @@ extern "C" int bk_model_set_margins(bk_model* m, double d_lo, double d_hi, doubl
     m->margins[1] = d_hi;
     m->margins[2] = eta;
     m->margins[3] = n_add;
-    return BK_OK;
+    return model_cells(m);
 }
 
 extern "C" int bk_model_get_params(const bk_model* m, float* host)
@@ -1401,6 +1525,7 @@ extern "C" int bk_model_train(bk_model* m, const double* nu, const double* x, in
             m->margins[3] = 0.0;
         }
     }
+    if (st == BK_OK) st = model_cells(m);     // the plans depend on the margins just set
     cleanup();
     if (st == BK_OK) m->trained = true;
     if (final_loss) *final_loss = last;

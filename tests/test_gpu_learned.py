@@ -191,6 +191,30 @@ def test_learned_parity(api, orc, trained):
     assert fb < 0.02 * nu.size
 
 
+def test_learned_plan_and_per_entry_paths_agree(api, orc, trained):
+    """At the default node target the kernel takes each cell's precomputed plan
+    (window, node count raised to the floor at the cell's largest-x, largest-nu
+    corner, walk start in FP64); at any other target it decodes the window per
+    entry. Both meet the bar; the plan path only adds nodes (up to the few entries
+    whose fallbacks differ)."""
+    import torch
+    from paper_2502_00356_amd import workloads
+    nu, x, _ = workloads.grid_pairs(1 << 15, seed=14)
+    _, _, ks = orc.besselk(nu, x)
+    res = {}
+    for lq in (0.0, 14.5000001):              # 0 selects the default 14.5: the plan path
+        stats = torch.zeros(api.STATS_LEN, dtype=torch.int64, device="cuda")
+        out = api.besselk(to_dev(nu), to_dev(x), mode="learned", model=trained, result=api.RESULT_SCALED,
+                          L_quad=lq, stats=stats)
+        torch.cuda.synchronize()
+        assert rel_err(out.cpu().numpy(), ks).max() <= TOL_MIXED, lq
+        res[lq] = stats.cpu().numpy()
+    plan, entry = res[0.0], res[14.5000001]
+    ratio = plan[api.STAT_NODES] / entry[api.STAT_NODES]
+    print("plan / per-entry nodes: %.4f" % ratio)
+    assert 0.999 <= ratio <= 1.03
+
+
 def test_learned_out_of_range_falls_back(api, orc, trained):
     """Pairs outside the training box all take the plain-solver path and stay exact."""
     import torch
