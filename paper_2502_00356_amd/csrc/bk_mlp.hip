@@ -87,6 +87,8 @@ struct bk_model {
     half4_t* pack = nullptr;      // device FP16 operand pack (a1, a2, a3)
     float* bias = nullptr;        // device b2 (64) and b3 (3)
     float* table = nullptr;       // device Matern window table [kTableSize][4]
+    float* mplan_a = nullptr;     // device Matern cell plans (float4 part) [kTableSize - 1]
+    double* mplan_b = nullptr;    // device Matern cell plans (two double4 parts) [kTableSize - 1][2]
     float* cells = nullptr;       // device prediction cells [kCellsLx][kCellsNu][4]
     float* plan_a = nullptr;      // device per-cell quadrature plans (float4 part)
     double* plan_b = nullptr;     // device per-cell quadrature plans (double4 part)
@@ -291,12 +293,25 @@ struct LearnedOut {
     int reason;     // 0 accepted, else a BK_STAT_FB_* index
 };
 
-// Quadrature plan of a learned window: nodes t_lo + m h, m = 0..N, and the start of
-// the cosh recurrence, c0 = cosh t_lo, c1 = cosh(t_lo + h), kappa = 2 cosh h.
+// Quadrature plan of a learned window: nodes t_lo + m h, m = 0..N, the start of the
+// cosh recurrence, c0 = cosh t_lo, c1 = cosh(t_lo + h), kappa = 2 cosh h, and the
+// parts that depend on nu as well: rho = e^(-2 nu h), Q0 = 1 + e^(-2 nu t_lo),
+// b2 = nu h log2 e, dnu = nu t_lo - ln 2.
 struct LearnedPlan {
     double tlo, h, c0, c1, kappa;
+    double rho, Q0, b2, dnu;
     int N;
 };
+
+// The nu-dependent part of a plan (T: the table 2^(j/64) of exp_tab). Q only needs
+// FP32 accuracy: e^(-2 nu t_lo) in FP32 moves it by < 6e-8 relative.
+__device__ __forceinline__ void plan_for_nu(LearnedPlan& P, double nu, const double* T)
+{
+    P.rho = exp_tab(-2.0 * nu * P.h, T);
+    P.Q0 = 1.0 + (double)__expf((float)(-2.0 * nu * P.tlo));
+    P.b2 = nu * P.h * kLog2e;
+    P.dnu = nu * P.tlo - kLn2;
+}
 
 // The plan of the window [t_lo, t_hi] with N intervals. Any step works as long as
 // the walk uses it consistently: an FP32 reciprocal of N puts the last node within
@@ -315,8 +330,8 @@ __device__ inline LearnedPlan learned_plan(double tlo, double thi, int N, const 
     return P;
 }
 
-// The node sum of a plan for one (nu, x), its prefactor and the acceptance tests.
-__device__ inline LearnedOut learned_walk(double nu, double x, const LearnedPlan& P, const double* T)
+// The node sum of a plan (for its nu) at one x, its prefactor and the acceptance tests.
+__device__ inline LearnedOut learned_walk(double x, const LearnedPlan& P)
 {
     LearnedOut o;
     o.reason = 0;
@@ -324,17 +339,17 @@ __device__ inline LearnedOut learned_walk(double nu, double x, const LearnedPlan
     const int N = P.N;
     // reference t_ref = t_lo; sinh^2(t/2) = (cosh t - 1) / 2 loses ~1e-16 absolute,
     // i.e. at most ~2e-13 relative in the scale for x <= 1e3, far inside this form's budget
-    o.delta = nu * tlo - kLn2 - x * (P.c0 - 1.0);
+    o.delta = P.dnu - x * (P.c0 - 1.0);
     WalkF w;
     w.kappa = P.kappa;
     w.c = P.c0;
     w.cn = P.c1;
     w.a2 = -x * kLog2e;
-    w.b2 = nu * h * kLog2e;
+    w.b2 = P.b2;
     w.e = x * P.c0 * kLog2e;
-    w.rho = exp_tab(-2.0 * nu * h, T);
-    w.omr = 1.0 - w.rho;
-    w.Q = 1.0 + (double)__expf((float)(-2.0 * nu * tlo));
+    w.rho = P.rho;
+    w.omr = 1.0 - P.rho;
+    w.Q = P.Q0;
     // the exponent is not bounded above here (t_lo is not the peak), so the FP32
     // exponential is split as 2^k 2^f with k, f formed in FP64; the FP32 terms are
     // summed in FP64, whose rounding is negligible next to theirs
@@ -384,7 +399,9 @@ __device__ inline LearnedOut learned_walk(double nu, double x, const LearnedPlan
 
 __device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double thi, int N, const double* T)
 {
-    return learned_walk(nu, x, learned_plan(tlo, thi, N, T), T);
+    LearnedPlan P = learned_plan(tlo, thi, N, T);
+    plan_for_nu(P, nu, T);
+    return learned_walk(x, P);
 }
 
 // Step floor for the learned forms: the strip bound of node_step at a single
@@ -643,7 +660,8 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
         } else {
             P = learned_plan(s_tlo[tid], s_thi[tid], Ns, s_exp2);
         }
-        LearnedOut lo = learned_walk(vs, zs, P, s_exp2);
+        plan_for_nu(P, vs, s_exp2);
+        LearnedOut lo = learned_walk(zs, P);
         c_nodes = (unsigned int)(Ns + 1);
         c_ent = 1;
         if (lo.reason == 0) {
@@ -696,9 +714,10 @@ __global__ __launch_bounds__(256) void k_besselk_fallback(const double* __restri
 
 // ---------------------------------------------------------------------------
 // Matern, learned form: the MLP is tabulated once per launch over log10 x on
-// kTableSize points of the training box at the launch's nu; an entry takes the
-// conservative union of the two bracketing predictions. Entries that fail the
-// acceptance checks fall back inside the kernel.
+// kTableSize points of the training box at the launch's nu, and each interval
+// between two points gets the quadrature plan of the union of their predictions
+// (k_matern_plans). An entry takes its interval's plan; entries that fail the
+// acceptance checks are marked and recomputed by k_matern_fallback.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_matern_table(MlpDev M, float nu, float* __restrict__ table)
 {
@@ -712,6 +731,48 @@ __global__ __launch_bounds__(256) void k_matern_table(MlpDev M, float nu, float*
         table[4 * i + 2] = y2;
         table[4 * i + 3] = 0.0f;
     }
+}
+
+// Quadrature plans of the Matern table's cells (between rows k and k + 1) at the
+// launch's nu and node target, one lane per cell: the union of the two rows'
+// windows with the model's margins, the node count raised to the strip-bound floor
+// at the cell's larger x (the floor falls with x, so it holds over the cell), and
+// the whole walk set-up, nu included. Layout as the prediction cells' plans, with
+// the nu-dependent part (rho, Q0, b2, dnu) in a second double4.
+__global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, double Lq, const float* __restrict__ table,
+                                                      const RuleTable* __restrict__ Rp, float4_t* __restrict__ pa,
+                                                      double4_t* __restrict__ pb)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= kTableSize - 1) return;
+    const float* t0 = table + 4 * k;
+    const float* t1 = t0 + 4;
+    const double lxm = (double)M.lx_lo + (double)(k + 1) * (((double)M.lx_hi - (double)M.lx_lo) / (kTableSize - 1));
+    double tlo, thi;
+    int N;
+    bool raised;
+    decode_window(M, fminf(t0[0], t1[0]), fmaxf(t0[1], t1[1]), fmaxf(t0[2], t1[2]), nu, exp10(lxm), Lq, tlo, thi,
+                  N, raised);
+    const bool valid = thi > tlo && isfinite(thi);
+    float4_t a;
+    a[0] = (float)tlo;
+    a[1] = (float)thi;
+    a[2] = __int_as_float(valid ? N : -1);
+    a[3] = __int_as_float(raised ? 1 : 0);
+    pa[k] = a;
+    LearnedPlan P = {};
+    if (valid) {
+        P.tlo = tlo;
+        P.N = N;
+        P.h = (thi - tlo) * (double)__builtin_amdgcn_rcpf((float)N);
+        P.c0 = cosh(tlo);
+        P.c1 = cosh(tlo + P.h);
+        P.kappa = 2.0 * cosh(P.h);
+        plan_for_nu(P, nu, Rp->exp2_64);
+    }
+    const double4_t b0 = {P.h, P.c0, P.c1, P.kappa}, b1 = {P.rho, P.Q0, P.b2, P.dnu};
+    pb[2 * k] = b0;
+    pb[2 * k + 1] = b1;
 }
 
 struct TileGeomL {
@@ -746,11 +807,11 @@ __device__ inline void tile_of_l(int64_t p, const TileGeomL& g, int64_t& I, int6
 // the NaN entries of the listed waves with the mixed form. Keeping the fallback out
 // of this kernel keeps its registers (and so its occupancy) those of the learned pass.
 template <typename OutT>
-__global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float* __restrict__ table,
+__global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float4_t* __restrict__ plan_a,
+                                                        const double4_t* __restrict__ plan_b,
                                                         const double* __restrict__ lx_, const double* __restrict__ ly_,
                                                         TileGeomL g, int64_t tile_base, double sigma2,
-                                                        double inv_beta, double nu, double pref, double Lq,
-                                                        const RuleTable* __restrict__ Rp,
+                                                        double inv_beta, double nu, double pref,
                                                         unsigned int* __restrict__ mlist, OutT* __restrict__ out)
 {
     constexpr int kColsPerWave = 8, kColsPerGroup = 32;
@@ -786,15 +847,22 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
             if (ok) {
                 float fpos = (lz - M.lx_lo) * tscale;
                 int k0 = min(max((int)fpos, 0), kTableSize - 2);
-                const float* t0 = table + 4 * k0;
-                const float* t1 = t0 + 4;
-                double tlo, thi;
-                int N;
-                bool raised;
-                decode_window(M, fminf(t0[0], t1[0]), fmaxf(t0[1], t1[1]), fmaxf(t0[2], t1[2]), nu, z, Lq, tlo, thi,
-                              N, raised);
-                if (thi > tlo && isfinite(thi)) {
-                    LearnedOut lo = learned_sum(nu, z, tlo, thi, N, Rp->exp2_64);
+                const float4_t a = plan_a[k0];
+                const int N = __float_as_int(a[2]);
+                if (N >= 0) {
+                    const double4_t b0 = plan_b[2 * k0], b1 = plan_b[2 * k0 + 1];
+                    LearnedPlan P;
+                    P.tlo = (double)a[0];
+                    P.N = N;
+                    P.h = b0[0];
+                    P.c0 = b0[1];
+                    P.c1 = b0[2];
+                    P.kappa = b0[3];
+                    P.rho = b1[0];
+                    P.Q0 = b1[1];
+                    P.b2 = b1[2];
+                    P.dnu = b1[3];
+                    LearnedOut lo = learned_walk(z, P);
                     ok = lo.reason == 0;
                     hs = lo.hs;
                     delta = lo.delta;
@@ -1073,6 +1141,8 @@ static int model_alloc(bk_model* m)
     if (hipMalloc((void**)&m->pack, sizeof(_Float16) * 24 * 64 * 4) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->bias, sizeof(float) * 68) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->table, sizeof(float) * 4 * kTableSize) != hipSuccess) return BK_ENOMEM;
+    if (hipMalloc((void**)&m->mplan_a, sizeof(float) * 4 * kTableSize) != hipSuccess) return BK_ENOMEM;
+    if (hipMalloc((void**)&m->mplan_b, sizeof(double) * 8 * kTableSize) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->cells, sizeof(float) * 4 * kCells) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->plan_a, sizeof(float) * 4 * kCells) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->plan_b, sizeof(double) * 4 * kCells) != hipSuccess) return BK_ENOMEM;
@@ -1170,6 +1240,8 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
     if (!R) return BK_EHIP;
     hipLaunchKernelGGL(k_matern_table, dim3((kTableSize + 255) / 256), dim3(256), 0, stream, M, (float)prm->nu,
                        m->table);
+    hipLaunchKernelGGL(k_matern_plans, dim3((kTableSize + 254) / 256), dim3(256), 0, stream, M, prm->nu, Lq, m->table,
+                       R, reinterpret_cast<float4_t*>(m->mplan_a), reinterpret_cast<double4_t*>(m->mplan_b));
     TileGeomL g;
     g.n = locs->n;
     g.ts = tile_size;
@@ -1190,13 +1262,17 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
         const dim3 grid((unsigned)(nt * wg_per_tile));
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, m->mlist);
         if (prm->out_dtype == BK_OUT_F32) {
-            hipLaunchKernelGGL(k_matern_learned<float>, grid, dim3(256), 0, stream, M, m->table, locs->x, locs->y, g,
-                               t0, prm->sigma2, ib, nu, pref, Lq, R, m->mlist, (float*)out);
+            hipLaunchKernelGGL(k_matern_learned<float>, grid, dim3(256), 0, stream, M,
+                               reinterpret_cast<const float4_t*>(m->mplan_a),
+                               reinterpret_cast<const double4_t*>(m->mplan_b), locs->x, locs->y, g,
+                               t0, prm->sigma2, ib, nu, pref, m->mlist, (float*)out);
             hipLaunchKernelGGL(k_matern_fallback<float>, dim3(1024), dim3(256), 0, stream, locs->x, locs->y, g, t0,
                                prm->sigma2, ib, nu, pref, L, Lq, R, m->mlist, (float*)out);
         } else {
-            hipLaunchKernelGGL(k_matern_learned<double>, grid, dim3(256), 0, stream, M, m->table, locs->x, locs->y, g,
-                               t0, prm->sigma2, ib, nu, pref, Lq, R, m->mlist, (double*)out);
+            hipLaunchKernelGGL(k_matern_learned<double>, grid, dim3(256), 0, stream, M,
+                               reinterpret_cast<const float4_t*>(m->mplan_a),
+                               reinterpret_cast<const double4_t*>(m->mplan_b), locs->x, locs->y, g,
+                               t0, prm->sigma2, ib, nu, pref, m->mlist, (double*)out);
             hipLaunchKernelGGL(k_matern_fallback<double>, dim3(1024), dim3(256), 0, stream, locs->x, locs->y, g, t0,
                                prm->sigma2, ib, nu, pref, L, Lq, R, m->mlist, (double*)out);
         }
@@ -1229,6 +1305,8 @@ extern "C" void bk_model_destroy(bk_model* m)
     if (m->pack) (void)hipFree(m->pack);
     if (m->bias) (void)hipFree(m->bias);
     if (m->table) (void)hipFree(m->table);
+    if (m->mplan_a) (void)hipFree(m->mplan_a);
+    if (m->mplan_b) (void)hipFree(m->mplan_b);
     if (m->cells) (void)hipFree(m->cells);
     if (m->plan_a) (void)hipFree(m->plan_a);
     if (m->plan_b) (void)hipFree(m->plan_b);
