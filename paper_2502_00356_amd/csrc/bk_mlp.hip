@@ -88,7 +88,7 @@ struct bk_model {
     float* bias = nullptr;        // device b2 (64) and b3 (3)
     float* table = nullptr;       // device Matern window table [kTableSize][4]
     float* mplan_a = nullptr;     // device Matern cell plans (float4 part) [kTableSize - 1]
-    double* mplan_b = nullptr;    // device Matern cell plans (two double4 parts) [kTableSize - 1][2]
+    double* mplan_b = nullptr;    // device Matern cell plans (three double4 parts) [kTableSize - 1][3]
     float* cells = nullptr;       // device prediction cells [kCellsLx][kCellsNu][4]
     float* plan_a = nullptr;      // device per-cell quadrature plans (float4 part)
     double* plan_b = nullptr;     // device per-cell quadrature plans (double4 part)
@@ -738,8 +738,12 @@ __global__ __launch_bounds__(256) void k_matern_table(MlpDev M, float nu, float*
 // windows with the model's margins, the node count raised to the strip-bound floor
 // at the cell's larger x (the floor falls with x, so it holds over the cell), and
 // the whole walk set-up, nu included. Layout as the prediction cells' plans, with
-// the nu-dependent part (rho, Q0, b2, dnu) in a second double4.
-__global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, double Lq, const float* __restrict__ table,
+// the nu-dependent part (rho, Q0, b2, dnu) in a second double4 and, in a third, the
+// prefactor's pieces at the interval's lower end z_k: K = pref + nu log z_k +
+// nu t_lo - ln 2 and 1 / z_k, so that an entry needs only log1p(z / z_k - 1),
+// |z / z_k - 1| < 0.017, for log z.
+__global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, double Lq, double pref,
+                                                      const float* __restrict__ table,
                                                       const RuleTable* __restrict__ Rp, float4_t* __restrict__ pa,
                                                       double4_t* __restrict__ pb)
 {
@@ -747,7 +751,8 @@ __global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, doubl
     if (k >= kTableSize - 1) return;
     const float* t0 = table + 4 * k;
     const float* t1 = t0 + 4;
-    const double lxm = (double)M.lx_lo + (double)(k + 1) * (((double)M.lx_hi - (double)M.lx_lo) / (kTableSize - 1));
+    const double dlx = ((double)M.lx_hi - (double)M.lx_lo) / (kTableSize - 1);
+    const double lxm = (double)M.lx_lo + (double)(k + 1) * dlx;
     double tlo, thi;
     int N;
     bool raised;
@@ -770,9 +775,28 @@ __global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, doubl
         P.kappa = 2.0 * cosh(P.h);
         plan_for_nu(P, nu, Rp->exp2_64);
     }
+    const double zk = exp10((double)M.lx_lo + (double)k * dlx);
     const double4_t b0 = {P.h, P.c0, P.c1, P.kappa}, b1 = {P.rho, P.Q0, P.b2, P.dnu};
-    pb[2 * k] = b0;
-    pb[2 * k + 1] = b1;
+    const double4_t b2 = {pref + nu * log(zk) + P.dnu, 1.0 / zk, 0.0, 0.0};
+    pb[3 * k] = b0;
+    pb[3 * k + 1] = b1;
+    pb[3 * k + 2] = b2;
+}
+
+// log(1 + u) for |u| <= 0.02 by its Taylor series through u^9 (truncation below
+// 2e-17 relative).
+__device__ __forceinline__ double log1p_small(double u)
+{
+    double p = 1.0 / 9.0;
+    p = fma(p, -u, 1.0 / 8.0);
+    p = fma(p, -u, 1.0 / 7.0);
+    p = fma(p, -u, 1.0 / 6.0);
+    p = fma(p, -u, 1.0 / 5.0);
+    p = fma(p, -u, 1.0 / 4.0);
+    p = fma(p, -u, 1.0 / 3.0);
+    p = fma(p, -u, 1.0 / 2.0);
+    p = fma(p, -u, 1.0);
+    return p * u;
 }
 
 struct TileGeomL {
@@ -843,14 +867,14 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
             const double z = rr * inv_beta;
             const float lz = __log2f((float)z) * 0.30102999566f;
             bool ok = nu_ok && lz >= M.lx_lo && lz <= M.lx_hi;
-            double hs = 0.0, delta = 0.0;
+            double hs = 0.0, lexp = 0.0;
             if (ok) {
                 float fpos = (lz - M.lx_lo) * tscale;
                 int k0 = min(max((int)fpos, 0), kTableSize - 2);
                 const float4_t a = plan_a[k0];
                 const int N = __float_as_int(a[2]);
                 if (N >= 0) {
-                    const double4_t b0 = plan_b[2 * k0], b1 = plan_b[2 * k0 + 1];
+                    const double4_t b0 = plan_b[3 * k0], b1 = plan_b[3 * k0 + 1], b2 = plan_b[3 * k0 + 2];
                     LearnedPlan P;
                     P.tlo = (double)a[0];
                     P.N = N;
@@ -865,13 +889,14 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
                     LearnedOut lo = learned_walk(z, P);
                     ok = lo.reason == 0;
                     hs = lo.hs;
-                    delta = lo.delta;
+                    // pref + nu log z + Delta - z = K + nu log(z / z_k) - z cosh t_lo
+                    lexp = fma(nu, log1p_small(fma(z, b2[1], -1.0)), fma(-z, P.c0, b2[0]));
                 } else {
                     ok = false;
                 }
             }
             if (ok) {
-                val = scaled_exp(pref + nu * log(z) + (delta - z), sigma2 * hs);
+                val = scaled_exp(lexp, sigma2 * hs);
             } else {
                 val = __builtin_nan("");
                 rejected = true;
@@ -1142,7 +1167,7 @@ static int model_alloc(bk_model* m)
     if (hipMalloc((void**)&m->bias, sizeof(float) * 68) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->table, sizeof(float) * 4 * kTableSize) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->mplan_a, sizeof(float) * 4 * kTableSize) != hipSuccess) return BK_ENOMEM;
-    if (hipMalloc((void**)&m->mplan_b, sizeof(double) * 8 * kTableSize) != hipSuccess) return BK_ENOMEM;
+    if (hipMalloc((void**)&m->mplan_b, sizeof(double) * 12 * kTableSize) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->cells, sizeof(float) * 4 * kCells) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->plan_a, sizeof(float) * 4 * kCells) != hipSuccess) return BK_ENOMEM;
     if (hipMalloc((void**)&m->plan_b, sizeof(double) * 4 * kCells) != hipSuccess) return BK_ENOMEM;
@@ -1238,10 +1263,13 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
     const MlpDev M = make_dev(m);
     const RuleTable* R = rule_table_dev();
     if (!R) return BK_EHIP;
+    const double nu = prm->nu;
+    const double pref = (1.0 - nu) * kLn2 - lgamma(nu);
     hipLaunchKernelGGL(k_matern_table, dim3((kTableSize + 255) / 256), dim3(256), 0, stream, M, (float)prm->nu,
                        m->table);
-    hipLaunchKernelGGL(k_matern_plans, dim3((kTableSize + 254) / 256), dim3(256), 0, stream, M, prm->nu, Lq, m->table,
-                       R, reinterpret_cast<float4_t*>(m->mplan_a), reinterpret_cast<double4_t*>(m->mplan_b));
+    hipLaunchKernelGGL(k_matern_plans, dim3((kTableSize + 254) / 256), dim3(256), 0, stream, M, prm->nu, Lq, pref,
+                       m->table, R, reinterpret_cast<float4_t*>(m->mplan_a),
+                       reinterpret_cast<double4_t*>(m->mplan_b));
     TileGeomL g;
     g.n = locs->n;
     g.ts = tile_size;
@@ -1251,8 +1279,6 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
     g.cb_per_tile = (tile_size + 31) / 32;
     const int64_t T = g.T;
     const int64_t ntiles = g.lower ? T * (T + 1) / 2 : T * T;
-    const double nu = prm->nu;
-    const double pref = (1.0 - nu) * kLn2 - lgamma(nu);
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
     const int64_t tiles_per_launch = kMaternWgPerLaunch / wg_per_tile > 0 ? kMaternWgPerLaunch / wg_per_tile : 1;
     if (wg_per_tile > kMaternWgPerLaunch) return BK_EINVAL;   // a tile side beyond 2^14 rows / 2^12 column blocks
