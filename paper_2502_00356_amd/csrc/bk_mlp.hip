@@ -57,7 +57,7 @@ static_assert(kNParam == BK_MLP_NPARAM, "parameter count");
 constexpr float kTailTol = 3e-7f;
 constexpr int kTableSize = 1024;       // Matern: MLP tabulated over log10 x at fixed nu
 // Standalone K_nu: prediction cells over the training box, log10 x by nu.
-constexpr int kCellsLx = 512, kCellsNu = 128, kCells = kCellsLx * kCellsNu;
+constexpr int kCellsLx = 512, kCellsNu = 64, kCells = kCellsLx * kCellsNu;
 // Matern learned launches: at most 2^21 workgroups (2^23 waves) each, so the
 // model's fallback list (one entry per wave with a rejected entry) never overflows.
 constexpr int64_t kMaternWgPerLaunch = 1LL << 21;
