@@ -193,12 +193,7 @@ __device__ unsigned int block_sort_slot(int key, unsigned int* hist)
     __syncthreads();
     if (tid < 64) {
         const unsigned int h = hist[tid];
-        unsigned int incl = h;
-        for (int d = 1; d < 64; d <<= 1) {
-            const unsigned int up = __shfl_up(incl, d, 64);
-            if (tid >= d) incl += up;
-        }
-        hist[tid] = incl - h;
+        hist[tid] = wave_incl_scan(h) - h;
     }
     __syncthreads();
     const unsigned int slot = hist[key] + rank;

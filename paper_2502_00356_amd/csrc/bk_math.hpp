@@ -53,6 +53,22 @@ struct Plan {
     int mc;        // index of the reference node (0 <= mc <= N)
 };
 
+// Inclusive prefix sum over the 64 lanes of a wave (all active) with DPP lane
+// moves instead of LDS: a scan within each 16-lane row by shifts of 1, 2, 4 and 8
+// (lanes shifted in from outside the row add 0), then the last lane of row 0 is
+// added to row 1 and of row 2 to row 3 (row_bcast:15), and the last lane of row 1
+// to rows 2 and 3 (row_bcast:31).
+__device__ __forceinline__ unsigned int wave_incl_scan(unsigned int v)
+{
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+    return v;
+}
+
 // 1/a for a normal nonzero double: hardware reciprocal refined by two Newton
 // steps (within about an ulp; no IEEE division sequence).
 __device__ __forceinline__ double recip(double a)

@@ -627,12 +627,7 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
     __syncthreads();
     if (tid < 64) {
         const unsigned int h = hist[tid];
-        unsigned int incl = h;
-        for (int d = 1; d < 64; d <<= 1) {
-            const unsigned int up = __shfl_up(incl, d, 64);
-            if (tid >= d) incl += up;
-        }
-        hist[tid] = incl - h;                 // exclusive prefix: first slot of the bin
+        hist[tid] = wave_incl_scan(h) - h;    // exclusive prefix: first slot of the bin
     }
     __syncthreads();
     const unsigned int dst = hist[key] + rank;
