@@ -397,13 +397,6 @@ __device__ inline LearnedOut learned_walk(double x, const LearnedPlan& P)
     return o;
 }
 
-__device__ inline LearnedOut learned_sum(double nu, double x, double tlo, double thi, int N, const double* T)
-{
-    LearnedPlan P = learned_plan(tlo, thi, N, T);
-    plan_for_nu(P, nu, T);
-    return learned_walk(x, P);
-}
-
 // Step floor for the learned forms: the strip bound of node_step at a single
 // half-width, a = min(sqrt(2 (Lq + ln 2) / (x + nu + 1)), 1.3) (the maximiser of
 // the bound's small-a expansion, capped), in FP32 with 1 - cos a = 2 sin^2(a/2),

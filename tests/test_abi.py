@@ -77,6 +77,35 @@ def test_argument_validation_is_host_side(lib):
     assert m(ctypes.byref(locs0), ctypes.byref(q), 4, 1, None, None) == 0
 
 
+def test_model_handle_host_calls(lib):
+    """Model calls that need no device memory: create/destroy, the prediction-cell
+    dimensions, and the argument checks of the cell copy (runs without a GPU)."""
+    vp = ctypes.c_void_p
+    lib.bk_model_create.argtypes = [ctypes.POINTER(vp)]
+    lib.bk_model_create.restype = ctypes.c_int
+    lib.bk_model_destroy.argtypes = [vp]
+    lib.bk_model_get_cells.argtypes = [vp, vp, ctypes.c_int64, vp]
+    lib.bk_model_get_cells.restype = ctypes.c_int
+    lib.bk_model_set_margins.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.bk_model_set_margins.restype = ctypes.c_int
+    h = vp()
+    assert lib.bk_model_create(ctypes.byref(h)) == 0
+    try:
+        dims = (ctypes.c_int32 * 2)()
+        assert lib.bk_model_get_cells(h, None, 0, dims) == 0
+        assert dims[0] > 0 and dims[1] > 0
+        buf = (ctypes.c_float * 4)()
+        assert lib.bk_model_get_cells(h, buf, 4, dims) == 1                     # capacity too small
+        big = (ctypes.c_float * (4 * dims[0] * dims[1]))()
+        assert lib.bk_model_get_cells(h, big, 4 * dims[0] * dims[1], dims) == 4  # BK_ENOMODEL: no parameters yet
+        assert lib.bk_model_get_cells(None, None, 0, dims) == 1
+        assert lib.bk_model_get_cells(h, None, 0, None) == 1
+        assert lib.bk_model_set_margins(h, -1.0, 0.0, 0.0, 0.0) == 1
+        assert lib.bk_model_set_margins(h, 0.05, 0.05, 0.0, 0.0) == 0           # no parameters: host only
+    finally:
+        lib.bk_model_destroy(h)
+
+
 def test_derivative_entry_points_validate_on_host(lib):
     from paper_2502_00356_amd import api
     d = lib.bk_besselk_deriv
