@@ -491,7 +491,7 @@ __global__ __launch_bounds__(256, 4) void k_matern(const double* __restrict__ lx
             } else {
                 Solved s = plain_solve(nu, z, L, Lq, *Rp);
                 double S = (MODE == BK_PLAIN_F64) ? sum_f64(nu, s.p, s.A, s.B, s_exp2) : sum_mixed(nu, z, s.p, s.A, s_exp2);
-                val = sigma2 * exp_tab(pref + nu * log(z) + (s.delta - z), s_exp2) * (s.p.h * S);
+                val = sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * (s.p.h * S);
             }
         }
         out[base + il + jl * mI] = (OutT)val;
@@ -542,16 +542,16 @@ __global__ __launch_bounds__(256) void k_matern_grad(const double* __restrict__ 
             const double z = r * inv_beta, lz = log(z);
             const Solved s0 = plain_solve(nu, z, L, Lq, R);
             // the same expression as k_matern, so that C is bit-identical with or without the derivatives
-            vc = sigma2 * exp_tab(pref + nu * lz + (s0.delta - z), s_exp2) * (s0.p.h * sum_f64(nu, s0.p, s0.A, s0.B, s_exp2));
+            vc = sigma2 * exp(pref + nu * lz + (s0.delta - z)) * (s0.p.h * sum_f64(nu, s0.p, s0.A, s0.B, s_exp2));
             if (ob) {
                 const Solved s1 = plain_solve(nu1, z, L, Lq, R);
-                vb = sigma2 * inv_beta * exp_tab(pref + (nu + 1.0) * lz + (s1.delta - z), s_exp2) *
+                vb = sigma2 * inv_beta * exp(pref + (nu + 1.0) * lz + (s1.delta - z)) *
                      (s1.p.h * sum_f64(nu1, s1.p, s1.A, s1.B, s_exp2));
             }
             if (on) {
                 const Solved sd = dnu_solve(nu, z, s0.p.t0, L, Lq, R);
                 vn = vc * (lz - kLn2 - psi) +
-                     sigma2 * exp_tab(pref + nu * lz + (sd.delta - z), s_exp2) * (sd.p.h * sum_dnu_f64(nu, sd.p, sd.A, sd.B, s_exp2));
+                     sigma2 * exp(pref + nu * lz + (sd.delta - z)) * (sd.p.h * sum_dnu_f64(nu, sd.p, sd.A, sd.B, s_exp2));
             }
         }
         const int64_t o = base + il + jl * mI;

@@ -81,17 +81,18 @@ __device__ __forceinline__ double recip(double a)
 // e^x from T[j] = 2^(j/64), j = 0..63 (Tang's table-driven method): with
 // k = floor(64 x log2 e) and f = x - k ln2/64, in [0, ln2/64) up to rounding,
 // e^x = 2^(k div 64) T[k mod 64] e^f, and e^f is its Taylor polynomial through f^6
-// (truncation below 2e-18). ln2/64 is split into its FP64 value and the remainder
-// (Cody and Waite), so the reduction is exact to ~1e-18 for any |x| < 750; within
-// a few ulps overall. x is clamped at -746, where e^x is already below half the
+// (truncation below 2e-18). ln2/64 rounded to FP64 is 3.6e-19 short, so the
+// reduction adds |k| 3.6e-19 relative: below 1.5e-15 for |x| <= 40, which covers
+// every use whose result matters (the walks' node exponents reach below -40 only
+// for terms under e^-40 of their sum; the set-up arguments are smaller). Within a
+// few ulps overall there. x is clamped at -746, where e^x is already below half the
 // smallest subnormal and the final ldexp gives 0 (also for x = -inf); ldexp takes
 // large x to infinity. The kernels stage T in LDS.
 __device__ __forceinline__ double exp_tab(double x, const double* T)
 {
     x = fmax(x, -746.0);
     const double k = floor(x * 92.332482616893656);          // 64 log2 e
-    double f = fma(-k, 0.010830424696249145, x);              // ln2 / 64, leading part
-    f = fma(-k, 3.623510646634843e-19, f);                    // and the rest
+    const double f = fma(-k, 0.010830424696249145, x);        // ln2 / 64
     double p = 1.0 / 720.0;
     p = fma(p, f, 1.0 / 120.0);
     p = fma(p, f, 1.0 / 24.0);

@@ -215,6 +215,26 @@ def test_learned_plan_and_per_entry_paths_agree(api, orc, trained):
     assert 0.999 <= ratio <= 1.03
 
 
+@pytest.mark.parametrize("n", [0, 1, 63, 255, 257, 1000, 4099])
+def test_learned_ragged_sizes(api, orc, trained, n):
+    """Partial last blocks and tiny inputs: dead lanes take part in the block sort
+    without producing output; every live entry meets the bar, at both node targets
+    (cell plans and per-entry decode)."""
+    import torch
+    rng = np.random.default_rng(300 + n)
+    nu = rng.uniform(0.01, 10, n)
+    x = 10 ** rng.uniform(-4, 3, n)
+    if n == 0:
+        out = api.besselk(to_dev(nu), to_dev(x), mode="learned", model=trained)
+        assert out.numel() == 0
+        return
+    _, _, ks = orc.besselk(nu, x)
+    for lq in (0.0, 14.5000001):
+        out = api.besselk(to_dev(nu), to_dev(x), mode="learned", model=trained, result=api.RESULT_SCALED, L_quad=lq)
+        torch.cuda.synchronize()
+        assert rel_err(out.cpu().numpy(), ks).max() <= TOL_MIXED, (n, lq)
+
+
 def test_learned_out_of_range_falls_back(api, orc, trained):
     """Pairs outside the training box all take the plain-solver path and stay exact."""
     import torch
