@@ -261,7 +261,8 @@ int bk_model_save(const bk_model* model, const char* path);
 /* Train the model on n (nu, x) pairs (device arrays): targets come from
  * bk_window at cfg's thresholds, then minibatch Adam on the expectile loss.
  * Synchronises the stream; *final_loss (host, may be NULL) receives the mean
- * loss of the last epoch. Sets the training box from the data range. */
+ * loss of the last epoch. Sets the training box from the data range, rounded
+ * outward to multiples of 1e-3. */
 int bk_model_train(bk_model* model, const double* nu, const double* x, int64_t n,
                    const bk_train_cfg* cfg, float* final_loss, hipStream_t stream);
 

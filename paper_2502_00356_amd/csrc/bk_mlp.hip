@@ -415,7 +415,8 @@ __device__ __forceinline__ float node_step_learned(float nu, float x, float Lq)
 
 // Window from a prediction (normalised outputs y), with the model's margins; the
 // node count is the prediction or the step floor's count for this window,
-// whichever is larger (raised says which).
+// whichever is larger (raised says which). N = -1 if the floor asks for more than
+// kNodeMax intervals (no admissible step within the cap).
 __device__ __forceinline__ void decode_window(const MlpDev& M, float y0, float y1, float y2, double nu, double x,
                                               double Lq, double& tlo, double& thi, int& N, bool& raised)
 {
@@ -425,8 +426,8 @@ __device__ __forceinline__ void decode_window(const MlpDev& M, float y0, float y
     if (!(nf >= (float)kNodeMin)) nf = (float)kNodeMin;
     if (nf > (float)kNodeMax) nf = (float)kNodeMax;
     float nr = ceilf((float)(thi - tlo) * __builtin_amdgcn_rcpf(node_step_learned((float)nu, (float)x, (float)Lq)));
+    if (nr > (float)kNodeMax) { raised = true; N = -1; return; }
     if (!(nr >= (float)kNodeMin)) nr = (float)kNodeMin;
-    if (nr > (float)kNodeMax) nr = (float)kNodeMax;
     raised = nr > nf;
     N = (int)(raised ? nr : nf);
 }
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(256) void k_cell_plans(MlpDev M, double Lq, float4_
     int N;
     bool raised;
     decode_window(M, y[0], y[1], y[2], num, xm, Lq, tlo, thi, N, raised);
-    const bool valid = thi > tlo && isfinite(thi);
+    const bool valid = thi > tlo && isfinite(thi) && N >= 0;
     float4_t a;
     a[0] = (float)tlo;                    // exact: the window ends are FP32 values
     a[1] = (float)thi;
@@ -603,7 +604,7 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
                     const float4_t y = M.cells[cell_index(M, lx, (float)v)];
                     decode_window(M, y[0], y[1], y[2], v, z, Lq, tlo, thi, Nd, raised);
                     c_raised = raised ? 1u : 0u;
-                    if (!(thi > tlo) || !isfinite(thi)) { reject = true; c_nonfin = 1; }
+                    if (!(thi > tlo) || !isfinite(thi) || Nd < 0) { reject = true; c_nonfin = 1; }
                     else N = Nd;
                 }
             }
@@ -746,7 +747,7 @@ __global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, doubl
     bool raised;
     decode_window(M, fminf(t0[0], t1[0]), fmaxf(t0[1], t1[1]), fmaxf(t0[2], t1[2]), nu, exp10(lxm), Lq, tlo, thi,
                   N, raised);
-    const bool valid = thi > tlo && isfinite(thi);
+    const bool valid = thi > tlo && isfinite(thi) && N >= 0;
     float4_t a;
     a[0] = (float)tlo;
     a[1] = (float)thi;
@@ -1537,7 +1538,13 @@ extern "C" int bk_model_train(bk_model* m, const double* nu, const double* x, in
                 lo = std::min(lo, lx); hi = std::max(hi, lx);
                 nlo = std::min(nlo, fabs(hn[i])); nhi = std::max(nhi, fabs(hn[i]));
             }
-            m->box[0] = lo; m->box[1] = hi; m->box[2] = nlo; m->box[3] = nhi;
+            // rounded outward to 1e-3, so that inputs from the same law just past the
+            // sample's extremes still use the model (a sliver of extrapolation that the
+            // acceptance tests guard)
+            m->box[0] = floor(lo * 1e3) / 1e3;
+            m->box[1] = ceil(hi * 1e3) / 1e3;
+            m->box[2] = std::max(0.0, floor(nlo * 1e3) / 1e3);
+            m->box[3] = ceil(nhi * 1e3) / 1e3;
         }
     }
     // He initialisation from a seeded host generator
