@@ -50,14 +50,18 @@ const RuleTable& rule_table()
             t.omc[k] = 1.0 - cos(a);
             t.lsec[k] = -log(cos(a));
         }
-        for (int j = 0; j < 64; ++j) t.exp2_64[j] = (double)exp2l((long double)j / 64.0L);
+        for (int j = 0; j < 64; ++j) t.tab[j] = (double)exp2l((long double)j / 64.0L);
+        for (int j = 0; j <= 64; ++j) {
+            t.tab[kTabLog1p + j] = (double)log1pl((long double)j / 64.0L);
+            t.tab[kTabInv1p + j] = (double)(1.0L / (1.0L + (long double)j / 64.0L));
+        }
         return t;
     }();
     return R;
 }
 
 // Device copy of the rule table, one per GPU, made on first use and kept for the
-// life of the process (872 bytes). Kernels read it through a pointer, so its
+// life of the process (1912 bytes). Kernels read it through a pointer, so its
 // values are scalar loads rather than 90 kernel-argument SGPRs.
 const RuleTable* rule_table_dev()
 {
@@ -162,14 +166,6 @@ __device__ __forceinline__ bool special_value(double v, double z, int result, do
     return false;
 }
 
-// exp_tab's table into LDS; every thread of the block must call it (it ends with
-// a barrier).
-__device__ __forceinline__ void stage_exp2(double* s, const RuleTable* R)
-{
-    if (threadIdx.x < 64) s[threadIdx.x] = R->exp2_64[threadIdx.x];
-    __syncthreads();
-}
-
 // Final assembly from exp(-x) exp(Delta) h S (see bk_math.hpp).
 __device__ __forceinline__ double assemble(double z, double delta, double hs, int result)
 {
@@ -220,11 +216,11 @@ __global__ __launch_bounds__(kSolveBlock) void k_besselk(const double* __restric
                                                          unsigned long long* __restrict__ stats)
 {
     __shared__ unsigned int hist[64];
-    __shared__ double s_exp2[64];
+    __shared__ double s_tab[kTabLen];
     __shared__ double s_d[8][kSolveBlock];
     __shared__ int s_i[3][kSolveBlock];
     const int tid = threadIdx.x;
-    if (tid < 64) s_exp2[tid] = Rp->exp2_64[tid];   // read after the sorts' barriers
+    if (tid < kTabLen) s_tab[tid] = Rp->tab[tid];   // read after the sorts' barriers
     const int64_t i = (int64_t)blockIdx.x * kSolveBlock + tid;
     double v = 0.0, z = 1.0;
     bool work = false;
@@ -248,7 +244,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_besselk(const double* __restric
     __syncthreads();
     Solved sv;
     sv.p.N = -1;
-    if (li >= 0) sv = plain_solve(v2, z2, L, Lq, *Rp);
+    if (li >= 0) sv = plain_solve(v2, z2, L, Lq, *Rp, s_tab);
     // phase 2 -> 3: sort by node count
     const int nkey = li < 0 ? 0 : (sv.p.N < 63 ? sv.p.N : 63);
     slot = block_sort_slot<kSolveBlock>(nkey, hist);
@@ -275,7 +271,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_besselk(const double* __restric
         p.N = s_i[1][tid];
         p.mc = s_i[2][tid];
         const double A = s_d[6][tid], B = s_d[7][tid];
-        const double S = (MODE == BK_PLAIN_F64) ? sum_f64(v3, p, A, B, s_exp2) : sum_mixed(v3, z3, p, A, s_exp2);
+        const double S = (MODE == BK_PLAIN_F64) ? sum_f64(v3, p, A, B, s_tab) : sum_mixed(v3, z3, p, A, s_tab);
         out[(int64_t)blockIdx.x * kSolveBlock + l3] = assemble(z3, s_d[5][tid], p.h * S, result);
         nodes = (unsigned long long)(p.N + 1);
         ents = 1;
@@ -294,8 +290,8 @@ __global__ __launch_bounds__(256) void k_besselk_paper(const double* __restrict_
                                                        const RuleTable* __restrict__ Rp,
                                                        unsigned long long* __restrict__ stats)
 {
-    __shared__ double s_exp2[64];
-    stage_exp2(s_exp2, Rp);
+    __shared__ double s_tab[kTabLen];
+    stage_tab(s_tab, Rp);
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long nodes = 0, ents = 0;
     if (i < n) {
@@ -306,7 +302,7 @@ __global__ __launch_bounds__(256) void k_besselk_paper(const double* __restrict_
                 // K directly; written as exp(-z) exp(0) (e^z K) for the shared assembly
                 r = assemble(z, 0.0, temme_k(v, z, *Cp) * exp(z), result);
             } else {
-                const FixedOut f = paper_fixed(v, z, bins, T, s_exp2);
+                const FixedOut f = paper_fixed(v, z, bins, T, s_tab);
                 // K = exp(lscale) h S, written through Delta = lscale + z so that the
                 // shared assembly (exp(-z) exp(Delta) h S) applies
                 r = assemble(z, f.lscale + z, f.hs, result);
@@ -335,7 +331,7 @@ __global__ __launch_bounds__(256) void k_window(const double* __restrict__ nu,
         tlo[i] = __builtin_nan(""); thi[i] = __builtin_nan(""); nodes[i] = 0;
         return;
     }
-    Solved s = plain_solve(v, z, L, Lq, *Rp);
+    Solved s = plain_solve(v, z, L, Lq, *Rp, Rp->tab);
     tlo[i] = s.p.t0;
     thi[i] = s.t1;
     nodes[i] = s.p.N;
@@ -358,8 +354,8 @@ __global__ __launch_bounds__(256, 3) void k_besselk_deriv(const double* __restri
                                                        double Lq, const RuleTable* __restrict__ Rp,
                                                        unsigned long long* __restrict__ stats)
 {
-    __shared__ double s_exp2[64];
-    stage_exp2(s_exp2, Rp);
+    __shared__ double s_tab[kTabLen];
+    stage_tab(s_tab, Rp);
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long nodes = 0, ents = 0;
     if (i < n) {
@@ -377,22 +373,22 @@ __global__ __launch_bounds__(256, 3) void k_besselk_deriv(const double* __restri
             rn = copysign(0.0, nr);
         } else {
             const RuleTable& R = *Rp;
-            const Solved s0 = plain_solve(v, z, L, Lq, R);
-            const double hs0 = s0.p.h * sum_f64(v, s0.p, s0.A, s0.B, s_exp2);
+            const Solved s0 = plain_solve(v, z, L, Lq, R, s_tab);
+            const double hs0 = s0.p.h * sum_f64(v, s0.p, s0.A, s0.B, s_tab);
             rk = assemble(z, s0.delta, hs0, result);
             nodes += (unsigned long long)(s0.p.N + 1);
             rx = 0.0;
             if (dkdx) {
                 const double v1 = fabs(v - 1.0);
-                const Solved s1 = plain_solve(v1, z, L, Lq, R);
-                const double hs1 = s1.p.h * sum_f64(v1, s1.p, s1.A, s1.B, s_exp2);
+                const Solved s1 = plain_solve(v1, z, L, Lq, R, s_tab);
+                const double hs1 = s1.p.h * sum_f64(v1, s1.p, s1.A, s1.B, s_tab);
                 nodes += (unsigned long long)(s1.p.N + 1);
                 rx = -unscale(z, exp(s1.delta) * hs1 + (v / z) * (exp(s0.delta) * hs0), result);
             }
             rn = 0.0;
             if (dkdnu && v > 0.0) {
                 const Solved sd = dnu_solve(v, z, s0.p.t0, L, Lq, R);
-                const double hsd = sd.p.h * sum_dnu_f64(v, sd.p, sd.A, sd.B, s_exp2);
+                const double hsd = sd.p.h * sum_dnu_f64(v, sd.p, sd.A, sd.B, s_tab);
                 nodes += (unsigned long long)(sd.p.N + 1);
                 rn = copysign(assemble(z, sd.delta, hsd, result), nr);
             } else if (dkdnu) {
@@ -453,8 +449,8 @@ __global__ __launch_bounds__(256, 4) void k_matern(const double* __restrict__ lx
                                                 const RuleTable* __restrict__ Rp, int bins, double T,
                                                 const TemmeCoef* __restrict__ Cp, OutT* __restrict__ out)
 {
-    __shared__ double s_exp2[64];
-    stage_exp2(s_exp2, Rp);                   // before any wave leaves
+    __shared__ double s_tab[kTabLen];
+    stage_tab(s_tab, Rp);                   // before any wave leaves
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
     const int64_t p = tile_base + (int64_t)blockIdx.x / wg_per_tile;
     const int64_t local = (int64_t)blockIdx.x % wg_per_tile;
@@ -485,12 +481,12 @@ __global__ __launch_bounds__(256, 4) void k_matern(const double* __restrict__ lx
                 if (z < kPaperTemmeX) {
                     val = sigma2 * exp(pref + nu * log(z)) * temme_k(nu, z, *Cp);
                 } else {
-                    const FixedOut f = paper_fixed(nu, z, bins, T, s_exp2);
+                    const FixedOut f = paper_fixed(nu, z, bins, T, s_tab);
                     val = sigma2 * exp(pref + nu * log(z) + f.lscale) * f.hs;
                 }
             } else {
-                Solved s = plain_solve(nu, z, L, Lq, *Rp);
-                double S = (MODE == BK_PLAIN_F64) ? sum_f64(nu, s.p, s.A, s.B, s_exp2) : sum_mixed(nu, z, s.p, s.A, s_exp2);
+                Solved s = plain_solve(nu, z, L, Lq, *Rp, s_tab);
+                double S = (MODE == BK_PLAIN_F64) ? sum_f64(nu, s.p, s.A, s.B, s_tab) : sum_mixed(nu, z, s.p, s.A, s_tab);
                 val = sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * (s.p.h * S);
             }
         }
@@ -512,8 +508,8 @@ __global__ __launch_bounds__(256) void k_matern_grad(const double* __restrict__ 
                                                      const RuleTable* __restrict__ Rp, OutT* __restrict__ oc,
                                                      OutT* __restrict__ ob, OutT* __restrict__ on)
 {
-    __shared__ double s_exp2[64];
-    stage_exp2(s_exp2, Rp);                   // before any wave leaves
+    __shared__ double s_tab[kTabLen];
+    stage_tab(s_tab, Rp);                   // before any wave leaves
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
     const int64_t p = tile_base + (int64_t)blockIdx.x / wg_per_tile;
     const int64_t local = (int64_t)blockIdx.x % wg_per_tile;
@@ -540,18 +536,18 @@ __global__ __launch_bounds__(256) void k_matern_grad(const double* __restrict__ 
         if (r != 0.0) {
             const RuleTable& R = *Rp;
             const double z = r * inv_beta, lz = log(z);
-            const Solved s0 = plain_solve(nu, z, L, Lq, R);
+            const Solved s0 = plain_solve(nu, z, L, Lq, R, s_tab);
             // the same expression as k_matern, so that C is bit-identical with or without the derivatives
-            vc = sigma2 * exp(pref + nu * lz + (s0.delta - z)) * (s0.p.h * sum_f64(nu, s0.p, s0.A, s0.B, s_exp2));
+            vc = sigma2 * exp(pref + nu * lz + (s0.delta - z)) * (s0.p.h * sum_f64(nu, s0.p, s0.A, s0.B, s_tab));
             if (ob) {
-                const Solved s1 = plain_solve(nu1, z, L, Lq, R);
+                const Solved s1 = plain_solve(nu1, z, L, Lq, R, s_tab);
                 vb = sigma2 * inv_beta * exp(pref + (nu + 1.0) * lz + (s1.delta - z)) *
-                     (s1.p.h * sum_f64(nu1, s1.p, s1.A, s1.B, s_exp2));
+                     (s1.p.h * sum_f64(nu1, s1.p, s1.A, s1.B, s_tab));
             }
             if (on) {
                 const Solved sd = dnu_solve(nu, z, s0.p.t0, L, Lq, R);
                 vn = vc * (lz - kLn2 - psi) +
-                     sigma2 * exp(pref + nu * lz + (sd.delta - z)) * (sd.p.h * sum_dnu_f64(nu, sd.p, sd.A, sd.B, s_exp2));
+                     sigma2 * exp(pref + nu * lz + (sd.delta - z)) * (sd.p.h * sum_dnu_f64(nu, sd.p, sd.A, sd.B, s_tab));
             }
         }
         const int64_t o = base + il + jl * mI;

@@ -34,14 +34,17 @@ constexpr int kNodeMin = 4;
 constexpr int kNodeMax = 512;
 constexpr int kRuleCand = 15;
 
+// Tables of the table-driven exponential and log1p (kernels stage them in LDS):
+// [0, 64): 2^(j/64); [64, 129): log(1 + j/64); [129, 194): 1 / (1 + j/64).
+constexpr int kTabLog1p = 64, kTabInv1p = 129, kTabLen = 194;
+
 // Node-count rule constants, filled on the host: for each strip half-width a_k,
-// a_k, 1 - cos a_k and log sec a_k (see node_step); and 2^(j/64), j = 0..63, for
-// exp_tab.
+// a_k, 1 - cos a_k and log sec a_k (see node_step); and the tables above.
 struct RuleTable {
     double a[kRuleCand];
     double omc[kRuleCand];
     double lsec[kRuleCand];
-    double exp2_64[64];
+    double tab[kTabLen];
 };
 
 // Per-entry quadrature plan.
@@ -104,6 +107,42 @@ __device__ __forceinline__ double exp_tab(double x, const double* T)
     return ldexp(T[ki & 63] * p, ki >> 6);
 }
 
+// log(1 + p) for 0 <= p <= 1 from the same tables: with j = floor(64 p) and
+// c = 1 + j/64, log(1 + p) = log c + log(1 + r), r = (p - j/64) / c in [0, 1/64)
+// (p - j/64 is exact), the second by its Taylor series through r^9 (truncation
+// below 1e-18); a few ulps.
+__device__ __forceinline__ double log1p_tab(double p, const double* T)
+{
+    const int j = min(max((int)(p * 64.0), 0), 64);
+    const double r = (p - (double)j * 0.015625) * T[kTabInv1p + j];
+    double q = 1.0 / 9.0;
+    q = fma(q, -r, 1.0 / 8.0);
+    q = fma(q, -r, 1.0 / 7.0);
+    q = fma(q, -r, 1.0 / 6.0);
+    q = fma(q, -r, 1.0 / 5.0);
+    q = fma(q, -r, 1.0 / 4.0);
+    q = fma(q, -r, 1.0 / 3.0);
+    q = fma(q, -r, 0.5);
+    q = fma(q, -r, 1.0);
+    return fma(q, r, T[kTabLog1p + j]);
+}
+
+// The tables into LDS; every thread of the block must call it (it ends with a
+// barrier).
+__device__ __forceinline__ void stage_tab(double* s, const RuleTable* R)
+{
+    for (int j = threadIdx.x; j < kTabLen; j += blockDim.x) s[j] = R->tab[j];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void cosh_sinh_tab(double t, double& ch, double& sh, const double* T)
+{
+    const double e = exp_tab(t, T);
+    const double ei = recip(e);
+    ch = 0.5 * (e + ei);
+    sh = 0.5 * (e - ei);
+}
+
 __device__ __forceinline__ void cosh_sinh(double t, double& ch, double& sh)
 {
     double e = exp(t);
@@ -113,9 +152,9 @@ __device__ __forceinline__ void cosh_sinh(double t, double& ch, double& sh)
 }
 
 // log cosh(y) for y >= 0 without overflow: y + log1p(exp(-2y)) - ln 2.
-__device__ __forceinline__ double logcosh_pos(double y)
+__device__ __forceinline__ double logcosh_pos(double y, const double* T)
 {
-    return y + log1p(exp(-2.0 * y)) - kLn2;
+    return y + log1p_tab(exp_tab(-2.0 * y, T), T) - kLn2;
 }
 
 // g and its first three derivatives at t >= 0 (g''' for Halley's method on g').
@@ -123,16 +162,16 @@ struct GDer {
     double g, g1, g2, g3;
 };
 
-__device__ __forceinline__ GDer g_derivs(double nu, double x, double t)
+__device__ __forceinline__ GDer g_derivs(double nu, double x, double t, const double* T)
 {
     GDer d;
-    const double p = exp(-2.0 * nu * t);
+    const double p = exp_tab(-2.0 * nu * t, T);
     const double ip = recip(1.0 + p);
     const double th = (1.0 - p) * ip;                 // tanh(nu t)
     const double s2 = 4.0 * p * ip * ip;              // sech^2(nu t)
     double ch, sh;
-    cosh_sinh(t, ch, sh);
-    d.g = nu * t + log1p(p) - kLn2 - x * ch;
+    cosh_sinh_tab(t, ch, sh, T);
+    d.g = nu * t + log1p_tab(p, T) - kLn2 - x * ch;
     d.g1 = nu * th - x * sh;
     d.g2 = nu * nu * s2 - x * ch;
     d.g3 = -2.0 * nu * nu * nu * th * s2 - x * sh;
@@ -157,11 +196,11 @@ __device__ __forceinline__ double halley_step(double f, double f1, double f2)
 // asinh(nu/x), where the iteration starts (the bracket search of FINDRANGE is
 // replaced by this analytic upper bound); g' is decreasing right of t* and steps
 // that would leave t > 0 are halved.
-__device__ inline double peak_solve(double nu, double x)
+__device__ inline double peak_solve(double nu, double x, const double* T)
 {
     double t = asinh(fmin(nu / x, 1e300));
     for (int it = 0; it < 64; ++it) {
-        const GDer d = g_derivs(nu, x, t);
+        const GDer d = g_derivs(nu, x, t, T);
         const double dt = halley_step(d.g1, d.g2, d.g3);
         double tn = t - dt;
         if (!(tn > 0.0)) tn = 0.5 * t;
@@ -176,12 +215,12 @@ __device__ inline double peak_solve(double nu, double x)
 // log cosh term has grown, so G >= 0 (FINDRANGE's lower end). Iterates are kept
 // in (t*, t* + 4 (start - t*) + 1].
 __device__ inline double window_right(double nu, double x, double tstar, double chstar,
-                                      double gstar, double L)
+                                      double gstar, double L, const double* T)
 {
     double t = acosh(chstar + L / x);
     const double tcap = tstar + 4.0 * (t - tstar) + 1.0;
     for (int it = 0; it < 64; ++it) {
-        const GDer d = g_derivs(nu, x, t);
+        const GDer d = g_derivs(nu, x, t, T);
         const double dt = halley_step(d.g - gstar + L, d.g1, d.g2);
         double tn = fmin(t - dt, tcap);
         if (!(tn > tstar)) tn = 0.5 * (t + tstar);
@@ -195,12 +234,12 @@ __device__ inline double window_right(double nu, double x, double tstar, double 
 // Root t0 in (0, t*) of G when G(0) < 0 (only possible if nu t* > L, since g' <= nu).
 // Bracket: G(0) < 0 and G(t* - L/nu) >= 0, shrunk at every iterate; a step that
 // would leave it is replaced by bisection.
-__device__ inline double window_left(double nu, double x, double tstar, double gstar, double L)
+__device__ inline double window_left(double nu, double x, double tstar, double gstar, double L, const double* T)
 {
     double lo = 0.0, hi = fmax(tstar - L / nu, 0.0);
     double t = hi;
     for (int it = 0; it < 100; ++it) {
-        const GDer d = g_derivs(nu, x, t);
+        const GDer d = g_derivs(nu, x, t, T);
         const double G = d.g - gstar + L;
         if (G >= 0.0) hi = t; else lo = t;
         const double dt = halley_step(G, d.g1, d.g2);
@@ -280,16 +319,17 @@ __device__ inline Solved plan_window(double nu, double x, double t0, double t1, 
     return s;
 }
 
-__device__ inline Solved plain_solve(double nu, double x, double L, double Lq, const RuleTable& R)
+__device__ inline Solved plain_solve(double nu, double x, double L, double Lq, const RuleTable& R,
+                                     const double* T)
 {
     double tstar = 0.0;
-    if (nu * nu > x) tstar = peak_solve(nu, x);
+    if (nu * nu > x) tstar = peak_solve(nu, x, T);
     double chs, shs;
-    cosh_sinh(tstar, chs, shs);
-    double gstar = logcosh_pos(nu * tstar) - x * chs;
-    double t1 = window_right(nu, x, tstar, chs, gstar, L);
+    cosh_sinh_tab(tstar, chs, shs, T);
+    double gstar = logcosh_pos(nu * tstar, T) - x * chs;
+    double t1 = window_right(nu, x, tstar, chs, gstar, L, T);
     double t0 = 0.0;
-    if (-x < gstar - L) t0 = window_left(nu, x, tstar, gstar, L);
+    if (-x < gstar - L) t0 = window_left(nu, x, tstar, gstar, L, T);
     Solved s = plan_window(nu, x, t0, t1, tstar, node_step(nu, x, Lq, R));
     s.gstar = gstar;
     return s;
@@ -605,7 +645,7 @@ __device__ inline double fixed_sum(double nu, const Plan& p, double A, double B,
 
 __device__ inline FixedOut paper_fixed(double nu, double x, int bins, double T, const double* E)
 {
-    const double tstar = (nu * nu > x) ? peak_solve(nu, x) : 0.0;
+    const double tstar = (nu * nu > x) ? peak_solve(nu, x, E) : 0.0;
     Plan p;
     p.t0 = 0.0;
     p.h = T / (double)bins;

@@ -574,7 +574,7 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
     double v = 0.0, z = 1.0;
     if (live) { v = fabs(nu[i]); z = x[i]; }
     if (tid < kSortBins) hist[tid] = 0u;
-    if (tid < 64) s_exp2[tid] = Rp->exp2_64[tid];     // read after the sort's barriers
+    if (tid < 64) s_exp2[tid] = Rp->tab[tid];         // 2^(j/64); read after the sort's barriers
     const float lx = __log2f((float)(z > 0.0 ? z : 1.0)) * 0.30102999566f;   // log10 x in FP32
     // per-lane statistics as scalars (a dynamically indexed array would live in scratch)
     unsigned int c_range = 0, c_tail = 0, c_raised = 0, c_nonfin = 0, c_nodes = 0, c_ent = 0;
@@ -681,16 +681,15 @@ __global__ __launch_bounds__(256) void k_besselk_fallback(const double* __restri
                                                           const RuleTable* __restrict__ Rp,
                                                           unsigned long long* __restrict__ stats)
 {
-    __shared__ double s_exp2[64];
-    if (threadIdx.x < 64) s_exp2[threadIdx.x] = Rp->exp2_64[threadIdx.x];
-    __syncthreads();
+    __shared__ double s_tab[kTabLen];
+    stage_tab(s_tab, Rp);
     const unsigned int cnt = *qcount;
     unsigned long long nodes = 0, ents = 0;
     for (unsigned int j = blockIdx.x * 256 + threadIdx.x; j < cnt; j += gridDim.x * 256) {
         const unsigned int i = queue[j];
         const double v = fabs(nu[i]), z = x[i];
-        Solved s = plain_solve(v, z, L, Lq, *Rp);
-        const double S = sum_mixed(v, z, s.p, s.A, s_exp2);
+        Solved s = plain_solve(v, z, L, Lq, *Rp, s_tab);
+        const double S = sum_mixed(v, z, s.p, s.A, s_tab);
         out[i] = assemble_k(z, s.delta, s.p.h * S, result);
         nodes += (unsigned long long)(s.p.N + 1);
         ents += 1;
@@ -762,7 +761,7 @@ __global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, doubl
         P.c0 = cosh(tlo);
         P.c1 = cosh(tlo + P.h);
         P.kappa = 2.0 * cosh(P.h);
-        plan_for_nu(P, nu, Rp->exp2_64);
+        plan_for_nu(P, nu, Rp->tab);
     }
     const double zk = exp10((double)M.lx_lo + (double)k * dlx);
     const double4_t b0 = {P.h, P.c0, P.c1, P.kappa}, b1 = {P.rho, P.Q0, P.b2, P.dnu};
@@ -911,9 +910,8 @@ __global__ __launch_bounds__(256) void k_matern_fallback(const double* __restric
                                                          const unsigned int* __restrict__ mlist, OutT* __restrict__ out)
 {
     constexpr int kColsPerWave = 8, kColsPerGroup = 32;
-    __shared__ double s_exp2[64];
-    if (threadIdx.x < 64) s_exp2[threadIdx.x] = Rp->exp2_64[threadIdx.x];
-    __syncthreads();
+    __shared__ double s_tab[kTabLen];
+    stage_tab(s_tab, Rp);
     const unsigned int cnt = mlist[0];
     const int lane = threadIdx.x & 63;
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
@@ -940,8 +938,8 @@ __global__ __launch_bounds__(256) void k_matern_fallback(const double* __restric
             const int64_t jl = jl0 + c;
             const double dx = lx_[J * g.ts + jl] - xi, dy = ly_[J * g.ts + jl] - yi;
             const double z = sqrt(dx * dx + dy * dy) * inv_beta;
-            const Solved s = plain_solve(nu, z, L, Lq, *Rp);
-            const double hs = s.p.h * sum_mixed(nu, z, s.p, s.A, s_exp2);
+            const Solved s = plain_solve(nu, z, L, Lq, *Rp, s_tab);
+            const double hs = s.p.h * sum_mixed(nu, z, s.p, s.A, s_tab);
             out[o] = (OutT)(sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * hs);
         }
     }
