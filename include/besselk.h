@@ -93,7 +93,12 @@ typedef struct bk_model bk_model;
  *  model    : trained model, required for BK_LEARNED.
  *  stats    : device array of BK_STATS_LEN counters, or NULL.
  *  workspace, workspace_bytes : device scratch owned by the caller; BK_LEARNED
- *             needs at least bk_workspace_bytes(n) bytes (the fallback queue). */
+ *             needs at least bk_workspace_bytes(n) bytes (the fallback queue).
+ *  kernel_events : optional pair of hipEvent_t handles (cast to void*), owned by
+ *             the caller. When both are set, bk_besselk_ex records [0] just before
+ *             and [1] just after the form's main kernel on the call's stream, so that
+ *             kernel can be timed alone (BK_LEARNED's counter reset and fallback
+ *             launches fall outside the pair). A failed record returns BK_EHIP. */
 typedef struct {
     int32_t mode;
     int32_t result;
@@ -109,6 +114,7 @@ typedef struct {
     void* workspace;
     size_t workspace_bytes;
     double t_upper;      /* BK_PAPER_REFINED: upper end of the window (0 selects 9) */
+    void* kernel_events[2];
 } bk_params;
 
 /* Human-readable name of a status code (static string). */

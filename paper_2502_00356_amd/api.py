@@ -37,7 +37,7 @@ class Params(ctypes.Structure):
     _fields_ = [("mode", _i32), ("result", _i32), ("out_dtype", _i32), ("bins", _i32),
                 ("L_window", _dbl), ("L_quad", _dbl), ("sigma2", _dbl), ("beta", _dbl), ("nu", _dbl),
                 ("model", _vp), ("stats", _vp), ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t),
-                ("t_upper", _dbl)]
+                ("t_upper", _dbl), ("kernel_events", _vp * 2)]
 
 
 class Locs(ctypes.Structure):
@@ -138,8 +138,10 @@ def workspace_bytes(n):
 
 
 def besselk(nu, x, out=None, mode="plain", result=RESULT_K, L_window=0.0, L_quad=0.0,
-            stats=None, model=None, workspace=None, stream=None, bins=0, t_upper=0.0):
-    """K_nu(x) (or e^x K, log K) for device float64 tensors nu, x of equal size."""
+            stats=None, model=None, workspace=None, stream=None, bins=0, t_upper=0.0, kernel_events=None):
+    """K_nu(x) (or e^x K, log K) for device float64 tensors nu, x of equal size.
+    kernel_events: optional pair of torch.cuda.Event (timing enabled, recorded once
+    already so that they exist), recorded around the form's main kernel."""
     n = x.numel()
     if nu.numel() != n:
         raise ValueError("nu and x differ in size")
@@ -156,6 +158,9 @@ def besselk(nu, x, out=None, mode="plain", result=RESULT_K, L_window=0.0, L_quad
                stats=(_dev(stats, torch.int64) if stats is not None else None),
                workspace=(workspace.data_ptr() if workspace is not None else None),
                workspace_bytes=(workspace.numel() * workspace.element_size() if workspace is not None else 0))
+    if kernel_events is not None:
+        p.kernel_events[0] = kernel_events[0].cuda_event
+        p.kernel_events[1] = kernel_events[1].cuda_event
     _check(_besselk_ex(_dev(nu, torch.float64), _dev(x, torch.float64), _dev(out, torch.float64), n,
                        ctypes.byref(p), _stream(stream)))
     return out

@@ -30,6 +30,14 @@ const TemmeCoef& temme_coef();
 const TemmeCoef* temme_coef_dev();
 void resolve_thresholds(int mode, double L_in, double Lq_in, double* L, double* Lq);
 
+// Records the caller's kernel_events[k] on stream when both events are set
+// (hipSuccess otherwise).
+inline hipError_t mark_kernel_event(const bk_params* p, int k, hipStream_t stream)
+{
+    if (!p->kernel_events[0] || !p->kernel_events[1]) return hipSuccess;
+    return hipEventRecord((hipEvent_t)p->kernel_events[k], stream);
+}
+
 int bk_besselk_learned(const double* nu, const double* x, double* out, int64_t n, const bk_params* prm,
                        double L, double Lq, hipStream_t stream);
 int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_size, int32_t lower_only,

@@ -606,13 +606,17 @@ extern "C" int bk_besselk_ex(const double* nu, const double* x, double* out, int
     if (!R) return BK_EHIP;
     switch (prm->mode) {
     case BK_PLAIN_F64:
+        if (mark_kernel_event(prm, 0, stream) != hipSuccess) return BK_EHIP;
         hipLaunchKernelGGL(k_besselk<BK_PLAIN_F64>, dim3((unsigned)blocks), dim3(kSolveBlock), 0, stream,
                            nu, x, out, n, prm->result, L, Lq, R, prm->stats);
-        return launch_status();
+        if (launch_status() != BK_OK) return BK_EHIP;
+        return mark_kernel_event(prm, 1, stream) == hipSuccess ? BK_OK : BK_EHIP;
     case BK_MIXED_F32C:
+        if (mark_kernel_event(prm, 0, stream) != hipSuccess) return BK_EHIP;
         hipLaunchKernelGGL(k_besselk<BK_MIXED_F32C>, dim3((unsigned)blocks), dim3(kSolveBlock), 0, stream,
                            nu, x, out, n, prm->result, L, Lq, R, prm->stats);
-        return launch_status();
+        if (launch_status() != BK_OK) return BK_EHIP;
+        return mark_kernel_event(prm, 1, stream) == hipSuccess ? BK_OK : BK_EHIP;
     case BK_LEARNED:
         return bk_besselk_learned(nu, x, out, n, prm, L, Lq, stream);
     case BK_PAPER_REFINED: {
@@ -620,10 +624,12 @@ extern "C" int bk_besselk_ex(const double* nu, const double* x, double* out, int
         const TemmeCoef* Cp = temme_coef_dev();
         if (!Cp) return BK_EHIP;
         const int64_t b256 = (n + 255) / 256;
+        if (mark_kernel_event(prm, 0, stream) != hipSuccess) return BK_EHIP;
         hipLaunchKernelGGL(k_besselk_paper, dim3((unsigned)b256), dim3(256), 0, stream, nu, x, out, n, prm->result,
                            prm->bins > 0 ? prm->bins : kPaperBins, prm->t_upper > 0.0 ? prm->t_upper : kPaperT, Cp,
                            R, prm->stats);
-        return launch_status();
+        if (launch_status() != BK_OK) return BK_EHIP;
+        return mark_kernel_event(prm, 1, stream) == hipSuccess ? BK_OK : BK_EHIP;
     }
     default:
         return BK_EINVAL;

@@ -1231,12 +1231,14 @@ int bk_besselk_learned(const double* nu, const double* x, double* out, int64_t n
     if (!R) return BK_EHIP;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, qcount);
     const unsigned blocks = (unsigned)((n + kLearnedBlock - 1) / kLearnedBlock);
+    if (mark_kernel_event(prm, 0, stream) != hipSuccess) return BK_EHIP;
     if (m->plan_Lq == Lq)
         hipLaunchKernelGGL(k_besselk_learned<true>, dim3(blocks), dim3(kLearnedBlock), 0, stream, M, nu, x, out, n,
                            prm->result, Lq, R, qcount, queue, prm->stats);
     else
         hipLaunchKernelGGL(k_besselk_learned<false>, dim3(blocks), dim3(kLearnedBlock), 0, stream, M, nu, x, out, n,
                            prm->result, Lq, R, qcount, queue, prm->stats);
+    if (hipGetLastError() != hipSuccess || mark_kernel_event(prm, 1, stream) != hipSuccess) return BK_EHIP;
     hipLaunchKernelGGL(k_besselk_fallback, dim3(1024), dim3(256), 0, stream, nu, x, out, prm->result, qcount, queue, L,
                        Lq, R, prm->stats);
     return hipGetLastError() == hipSuccess ? BK_OK : BK_EHIP;

@@ -177,3 +177,26 @@ def test_window_matches_oracle(api, orc):
         mism = N != Nref
         assert np.all(~mism | (tie & (np.abs(N - Nref) <= 1))), (nu[mism][:5], x[mism][:5], N[mism][:5], Nref[mism][:5])
         print("L=%g: mean N %.2f max N %d" % (L, N.mean(), N.max()))
+
+
+@pytest.mark.parametrize("mode", ["plain", "mixed", "paper"])
+def test_kernel_events_bracket_the_kernel(api, mode):
+    """The optional event pair is recorded around the form's main kernel: results are
+    unchanged, and the pair's time is positive and within the whole call's."""
+    import torch
+    from paper_2502_00356_amd import workloads as w
+    nu, x = w.small_pairs(4096, seed=5)
+    ref = _gpu(api, nu, x, mode, 1)
+    dnu, dx = to_dev(nu), to_dev(x)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    outer = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    for e in ev + outer:
+        e.record()
+    torch.cuda.synchronize()
+    outer[0].record()
+    got = api.besselk(dnu, dx, mode=mode, result=1, kernel_events=ev)
+    outer[1].record()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got.cpu().numpy(), ref)
+    t_k, t_all = ev[0].elapsed_time(ev[1]), outer[0].elapsed_time(outer[1])
+    assert 0.0 < t_k <= t_all, (t_k, t_all)

@@ -358,3 +358,25 @@ def test_learned_gain_over_mixed(api, trained):
     print("2^22 pairs: mixed %.3f ms, learned %.3f ms, gain %.2fx" % (
         times["mixed"] * 1e3, times["learned"] * 1e3, times["mixed"] / times["learned"]))
     assert times["learned"] < times["mixed"]
+
+
+def test_learned_kernel_events(api, trained):
+    """The optional event pair brackets the learned kernel alone (the queue reset and
+    the fallback launch fall outside): results unchanged, pair time within the call's."""
+    import torch
+    from paper_2502_00356_amd import workloads
+    nu, x, _ = workloads.grid_pairs(1 << 16, seed=4)
+    dnu, dx = to_dev(nu), to_dev(x)
+    ref = api.besselk(dnu, dx, mode="learned", model=trained)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    outer = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    for e in ev + outer:
+        e.record()
+    torch.cuda.synchronize()
+    outer[0].record()
+    got = api.besselk(dnu, dx, mode="learned", model=trained, kernel_events=ev)
+    outer[1].record()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got.cpu().numpy(), ref.cpu().numpy())
+    t_k, t_all = ev[0].elapsed_time(ev[1]), outer[0].elapsed_time(outer[1])
+    assert 0.0 < t_k <= t_all, (t_k, t_all)
