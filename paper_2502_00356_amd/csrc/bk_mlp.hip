@@ -331,7 +331,12 @@ __device__ inline LearnedPlan learned_plan(double tlo, double thi, int N, const 
 }
 
 // The node sum of a plan (for its nu) at one x, its prefactor and the acceptance tests.
-__device__ inline LearnedOut learned_walk(double x, const LearnedPlan& P)
+// kBias: the terms are taken relative to 2^eb (eb in log2 units, an estimate of the
+// largest node's exponent, from the cell), so every FP32 exponential sees an argument
+// of moderate size and the 2^k 2^f split is not needed; the prefactor carries 2^eb.
+// Else the split is made at every node.
+template <bool kBias>
+__device__ inline LearnedOut learned_walk(double x, const LearnedPlan& P, double eb = 0.0)
 {
     LearnedOut o;
     o.reason = 0;
@@ -340,6 +345,7 @@ __device__ inline LearnedOut learned_walk(double x, const LearnedPlan& P)
     // reference t_ref = t_lo; sinh^2(t/2) = (cosh t - 1) / 2 loses ~1e-16 absolute,
     // i.e. at most ~2e-13 relative in the scale for x <= 1e3, far inside this form's budget
     o.delta = P.dnu - x * (P.c0 - 1.0);
+    if (kBias) o.delta = fma(eb, kLn2, o.delta);
     WalkF w;
     w.kappa = P.kappa;
     w.c = P.c0;
@@ -347,16 +353,25 @@ __device__ inline LearnedOut learned_walk(double x, const LearnedPlan& P)
     w.a2 = -x * kLog2e;
     w.b2 = P.b2;
     w.e = x * P.c0 * kLog2e;
+    if (kBias) w.e -= eb;
     w.rho = P.rho;
     w.omr = 1.0 - P.rho;
     w.Q = P.Q0;
     // the exponent is not bounded above here (t_lo is not the peak), so the FP32
     // exponential is split as 2^k 2^f with k, f formed in FP64; the FP32 terms are
     // summed in FP64, whose rounding is negligible next to theirs
+    // With the bias, an argument d converts to FP32 with an absolute error of
+    // |d| 2^-24; the terms that carry the sum lie within a few units of eb, the
+    // others are smaller by 2^-|d|, so this adds a few 1e-8 to the sum.
     auto node = [&]() {
         const double d = walkf_exponent2(w);
-        const double kf = rint(d);
-        const float t = ldexpf(__builtin_amdgcn_exp2f((float)(d - kf)) * (float)w.Q, (int)kf);
+        float t;
+        if (kBias) {
+            t = __builtin_amdgcn_exp2f((float)d) * (float)w.Q;
+        } else {
+            const double kf = rint(d);
+            t = ldexpf(__builtin_amdgcn_exp2f((float)(d - kf)) * (float)w.Q, (int)kf);
+        }
         walkf_step(w);
         return t;
     };
@@ -442,8 +457,12 @@ __device__ __forceinline__ bool in_box(const MlpDev& M, float lx, float v)
 // count from the prediction, raised to the strip-bound floor taken at the cell's
 // corner of largest x and nu (at any point of the cell the half-width of that
 // corner gives a larger admissible step, so this floor holds over the whole cell);
-// and the start of the walk in FP64. plan_a: t_lo, t_hi, N (-1 if the window is
-// empty or not finite) and flags (bit 0: N raised), the last two as int bits.
+// and the start of the walk in FP64. plan_a: t_lo; dc = cosh t_pk - cosh t_lo for
+// the node t_pk = t_lo + m_pk h of the largest term at the cell's centre (without
+// the bounded log(1 + e^(-2 nu t)) part); N (-1 if the window is empty or not
+// finite); flags (bit 0: N raised; bits 1 up: m_pk); the last two as int bits.
+// The walk scales its FP32 terms by the term at t_pk, so that no node needs the
+// 2^k 2^f split of an unbounded exponent.
 __global__ __launch_bounds__(256) void k_cell_plans(MlpDev M, double Lq, float4_t* __restrict__ pa,
                                                     double4_t* __restrict__ pb)
 {
@@ -461,10 +480,9 @@ __global__ __launch_bounds__(256) void k_cell_plans(MlpDev M, double Lq, float4_
     const bool valid = thi > tlo && isfinite(thi) && N >= 0;
     float4_t a;
     a[0] = (float)tlo;                    // exact: the window ends are FP32 values
-    a[1] = (float)thi;
+    a[1] = 0.0f;
     a[2] = __int_as_float(valid ? N : -1);
-    a[3] = __int_as_float(raised ? 1 : 0);
-    pa[c] = a;
+    int flags = raised ? 1 : 0;
     double4_t b = {0.0, 1.0, 1.0, 2.0};
     if (valid) {
         const double h = (thi - tlo) * (double)__builtin_amdgcn_rcpf((float)N);
@@ -472,7 +490,19 @@ __global__ __launch_bounds__(256) void k_cell_plans(MlpDev M, double Lq, float4_
         b[1] = cosh(tlo);
         b[2] = cosh(tlo + h);
         b[3] = 2.0 * cosh(h);
+        const double xc = exp10(lxm - 0.5 * (((double)M.lx_hi - (double)M.lx_lo) / kCellsLx));
+        const double nuc = num - 0.5 * (((double)M.nu_hi - (double)M.nu_lo) / kCellsNu);
+        int mpk = 0;
+        double best = 0.0;
+        for (int m = 1; m <= N; ++m) {
+            const double d = nuc * (double)m * h - xc * (cosh(tlo + (double)m * h) - b[1]);
+            if (d > best) { best = d; mpk = m; }
+        }
+        a[1] = (float)(cosh(tlo + (double)mpk * h) - b[1]);
+        flags |= mpk << 1;
     }
+    a[3] = __int_as_float(flags);
+    pa[c] = a;
     pb[c] = b;
 }
 
@@ -578,8 +608,8 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
     const float lx = __log2f((float)(z > 0.0 ? z : 1.0)) * 0.30102999566f;   // log10 x in FP32
     // per-lane statistics as scalars (a dynamically indexed array would live in scratch)
     unsigned int c_range = 0, c_tail = 0, c_raised = 0, c_nonfin = 0, c_nodes = 0, c_ent = 0;
-    double tlo = 0.0, thi = 0.0;
-    int N = -1;
+    double tlo = 0.0, thi = 0.0;             // plan path: thi holds the cell's dc
+    int N = -1, mpk = 0;
     if (live) {
         double r;
         if (special_k(v, z, result, r)) {
@@ -594,10 +624,11 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
                     cell = cell_index(M, lx, (float)v);
                     const float4_t a = M.plan_a[cell];
                     tlo = (double)a[0];
-                    const int Nd = __float_as_int(a[2]);
-                    c_raised = (unsigned int)(__float_as_int(a[3]) & 1);
+                    thi = (double)a[1];
+                    const int Nd = __float_as_int(a[2]), fl = __float_as_int(a[3]);
+                    c_raised = (unsigned int)(fl & 1);
                     if (Nd < 0) { reject = true; c_nonfin = 1; }
-                    else N = Nd;
+                    else { N = Nd; mpk = fl >> 1; }
                 } else {
                     bool raised;
                     int Nd;
@@ -628,13 +659,14 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
     s_v[dst] = v;
     s_z[dst] = z;
     s_tlo[dst] = tlo;
+    s_thi[dst] = thi;
     if constexpr (kPlan) s_cell[dst] = cell;
-    else s_thi[dst] = thi;
-    s_N[dst] = N;
+    s_N[dst] = N < 0 ? -1 : (N | (mpk << 16));   // N <= kNodeMax < 2^16
     s_idx[dst] = (unsigned int)i;
     __syncthreads();
-    const int Ns = s_N[tid];
-    if (Ns >= 0) {
+    const int Np = s_N[tid];
+    if (Np >= 0) {
+        const int Ns = Np & 0xffff;
         const double vs = s_v[tid], zs = s_z[tid];
         const unsigned int idx = s_idx[tid];
         LearnedPlan P;
@@ -650,7 +682,14 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
             P = learned_plan(s_tlo[tid], s_thi[tid], Ns, s_exp2);
         }
         plan_for_nu(P, vs, s_exp2);
-        LearnedOut lo = learned_walk(zs, P);
+        LearnedOut lo;
+        if constexpr (kPlan) {
+            // log2 of the term at the cell's peak node t_pk relative to node 0, at this entry
+            const double eb = (vs * ((double)(Np >> 16) * P.h) - zs * s_thi[tid]) * kLog2e;
+            lo = learned_walk<true>(zs, P, eb);
+        } else {
+            lo = learned_walk<false>(zs, P);
+        }
         c_nodes = (unsigned int)(Ns + 1);
         c_ent = 1;
         if (lo.reason == 0) {
@@ -729,7 +768,9 @@ __global__ __launch_bounds__(256) void k_matern_table(MlpDev M, float nu, float*
 // the nu-dependent part (rho, Q0, b2, dnu) in a second double4 and, in a third, the
 // prefactor's pieces at the interval's lower end z_k: K = pref + nu log z_k +
 // nu t_lo - ln 2 and 1 / z_k, so that an entry needs only log1p(z / z_k - 1),
-// |z / z_k - 1| < 0.017, for log z.
+// |z / z_k - 1| < 0.017, for log z; and the walk's bias 2^eb, eb = B0 - z B1 (log2
+// of the term at the node m_pk of the largest term at the interval's middle,
+// relative to node 0: B0 = nu m_pk h log2 e, B1 = (cosh t_pk - cosh t_lo) log2 e).
 __global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, double Lq, double pref,
                                                       const float* __restrict__ table,
                                                       const RuleTable* __restrict__ Rp, float4_t* __restrict__ pa,
@@ -764,8 +805,20 @@ __global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, doubl
         plan_for_nu(P, nu, Rp->tab);
     }
     const double zk = exp10((double)M.lx_lo + (double)k * dlx);
+    double B0 = 0.0, B1 = 0.0;
+    if (valid) {
+        const double zc = exp10((double)M.lx_lo + ((double)k + 0.5) * dlx);
+        int mpk = 0;
+        double best = 0.0;
+        for (int m = 1; m <= N; ++m) {
+            const double d = nu * (double)m * P.h - zc * (cosh(tlo + (double)m * P.h) - P.c0);
+            if (d > best) { best = d; mpk = m; }
+        }
+        B0 = nu * (double)mpk * P.h * kLog2e;
+        B1 = (cosh(tlo + (double)mpk * P.h) - P.c0) * kLog2e;
+    }
     const double4_t b0 = {P.h, P.c0, P.c1, P.kappa}, b1 = {P.rho, P.Q0, P.b2, P.dnu};
-    const double4_t b2 = {pref + nu * log(zk) + P.dnu, 1.0 / zk, 0.0, 0.0};
+    const double4_t b2 = {pref + nu * log(zk) + P.dnu, 1.0 / zk, B0, B1};
     pb[3 * k] = b0;
     pb[3 * k + 1] = b1;
     pb[3 * k + 2] = b2;
@@ -874,11 +927,13 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
                     P.Q0 = b1[1];
                     P.b2 = b1[2];
                     P.dnu = b1[3];
-                    LearnedOut lo = learned_walk(z, P);
+                    const double eb = fma(-z, b2[3], b2[2]);
+                    LearnedOut lo = learned_walk<true>(z, P, eb);
                     ok = lo.reason == 0;
                     hs = lo.hs;
-                    // pref + nu log z + Delta - z = K + nu log(z / z_k) - z cosh t_lo
-                    lexp = fma(nu, log1p_small(fma(z, b2[1], -1.0)), fma(-z, P.c0, b2[0]));
+                    // pref + nu log z + Delta - z = K + nu log(z / z_k) - z cosh t_lo, and
+                    // the walk's bias eb ln 2
+                    lexp = fma(nu, log1p_small(fma(z, b2[1], -1.0)), fma(-z, P.c0, fma(eb, kLn2, b2[0])));
                 } else {
                     ok = false;
                 }
