@@ -44,7 +44,9 @@ NODE_SLOTS = load_node_slots()
 # HBM bytes per launch of the learned kernel on the 2^24 grid, from the FETCH_SIZE and
 # WRITE_SIZE counter runs scaled by a plain 1 GiB copy (profiles/besselk_grid_2e24_hbm_traffic.txt),
 # valid only for the kernel code they were taken on (hash below, comments ignored); else null.
-TRAFFIC = {"src_sha": "eadcecf15ba702d0", "n": 1 << 24, "bytes": 418.9e6}
+TRAFFIC = {"src_sha": "4c667b4128e0c4cc", "n": 1 << 24, "bytes": 416.5e6,
+           # SQ_INSTS_VALU of one launch without statistics (profiles/besselk_grid_2e24_valu_counters.txt)
+           "valu_insts": 101.1e6}
 KERNEL_SOURCES = ("bk_mlp.hip", "bk_math.hpp", "bk_internal.hpp")
 
 
@@ -268,7 +270,13 @@ def main():
                      "kernel_ms": head["kernel_ms"],
                      "work": "%.2f VALU issue clocks (full-rate lane-op slots) per trapezoid node x %d nodes per step"
                              % (NODE_SLOTS[form], head["node_total"]),
-                     "hbm_gbps": 24.0 * a.n / (head["kernel_ms"] * 1e-3) / 1e9},
+                     "hbm_gbps": 24.0 * a.n / (head["kernel_ms"] * 1e-3) / 1e9,
+                     # all VALU instructions of the launch (counter run) per CU-clock of
+                     # the kernel's time; one wave64 instruction per CU-clock is the
+                     # full-rate issue limit
+                     "valu_issue_per_cu_clock": (TRAFFIC["valu_insts"] / (head["kernel_ms"] * 1e-3 * 256 * 2.4e9)
+                                                 if (form == "learned" and a.n == TRAFFIC["n"]
+                                                     and kernel_src_sha() == TRAFFIC["src_sha"]) else None)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
