@@ -880,10 +880,12 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
                                                         unsigned int* __restrict__ mlist, OutT* __restrict__ out)
 {
     constexpr int kColsPerWave = 8, kColsPerGroup = 32;
-    const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
-    const int64_t p = tile_base + (int64_t)blockIdx.x / wg_per_tile;
-    const int64_t local = (int64_t)blockIdx.x % wg_per_tile;
-    const int rb = (int)(local % g.rb_per_tile), cb = (int)(local / g.rb_per_tile);
+    // block -> (tile, row block, column block) in 32-bit arithmetic (a 64-bit
+    // division is a long instruction sequence)
+    const unsigned wg_per_tile = (unsigned)g.rb_per_tile * (unsigned)g.cb_per_tile;
+    const unsigned tq = blockIdx.x / wg_per_tile, local = blockIdx.x - tq * wg_per_tile;
+    const int64_t p = tile_base + (int64_t)tq;
+    const int rb = (int)(local % (unsigned)g.rb_per_tile), cb = (int)(local / (unsigned)g.rb_per_tile);
     int64_t I, J;
     tile_of_l(p, g, I, J);
     const int64_t mI = min((int64_t)g.ts, g.n - I * g.ts);
