@@ -610,9 +610,13 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
     unsigned int c_range = 0, c_tail = 0, c_raised = 0, c_nonfin = 0, c_nodes = 0, c_ent = 0;
     double tlo = 0.0, thi = 0.0;             // plan path: thi holds the cell's dc
     int N = -1, mpk = 0;
+    // the ordinary case (finite nu, 0 < x < inf) in three compares; special_k covers
+    // every other input
+    const bool ordinary = z > 0.0 && z < __builtin_inf() && v < __builtin_inf();
     if (live) {
         double r;
-        if (special_k(v, z, result, r)) {
+        if (!ordinary) {
+            special_k(v, z, result, r);
             out[i] = r;
         } else {
             bool reject = false;
@@ -721,8 +725,9 @@ __global__ __launch_bounds__(256) void k_besselk_fallback(const double* __restri
                                                           unsigned long long* __restrict__ stats)
 {
     __shared__ double s_tab[kTabLen];
-    stage_tab(s_tab, Rp);
     const unsigned int cnt = *qcount;
+    if (blockIdx.x * 256u >= cnt) return;      // the whole block has no entry (uniform)
+    stage_tab(s_tab, Rp);
     unsigned long long nodes = 0, ents = 0;
     for (unsigned int j = blockIdx.x * 256 + threadIdx.x; j < cnt; j += gridDim.x * 256) {
         const unsigned int i = queue[j];
