@@ -163,3 +163,30 @@ def test_workload_sizes():
     assert api.matern_out_elems(40000, 960, 1) == 819097600
     assert api.matern_out_elems(99856, 1024, 1) == 5036605696
     assert api.matern_out_elems(1024, 1024, 0) == 1024 * 1024
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of bk_params, bk_locs and bk_train_cfg have the sizes and
+    field offsets the C compiler gives the header's structs."""
+    import ctypes
+    import subprocess
+    from paper_2502_00356_amd import api
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    checks = [("bk_params", api.Params), ("bk_locs", api.Locs), ("bk_train_cfg", api.TrainCfg)]
+    lines = ['#include "besselk.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void) {"]
+    for cname, cls in checks:
+        lines.append('printf("%%zu\\n", sizeof(%s));' % cname)
+        for fname, _ in cls._fields_:
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (cname, fname))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(root, "include"), "-I", "/opt/rocm/include",
+                    str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    want = []
+    for _, cls in checks:
+        want.append(ctypes.sizeof(cls))
+        want.extend(getattr(cls, f).offset for f, _ in cls._fields_)
+    assert got == want
