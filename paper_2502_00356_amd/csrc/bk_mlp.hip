@@ -75,7 +75,7 @@ struct MlpDev {
     float lx_lo, lx_hi, nu_lo, nu_hi;   // training box
     float d_lo, d_hi, eta, n_add;       // margins
     const float4_t* cells;              // [kCellsLx][kCellsNu] cell windows (normalised y0, y1, y2, 0)
-    const float4_t* plan_a;             // [cell] quadrature plan: t_lo, t_hi, N (int bits), flags (int bits)
+    const float4_t* plan_a;             // [cell] quadrature plan: t_lo, dc, N (int bits), flags | m_pk << 1 (int bits)
     const double4_t* plan_b;            // [cell] quadrature plan: h, cosh t_lo, cosh(t_lo + h), 2 cosh h
     float cl_scale, cn_scale;           // cells per unit of log10 x and of nu
 };
