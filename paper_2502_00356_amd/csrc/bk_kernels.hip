@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256, 3) void k_besselk_deriv(const double* __restri
             }
             rn = 0.0;
             if (dkdnu && v > 0.0) {
-                const Solved sd = dnu_solve(v, z, s0.p.t0, L, Lq, R);
+                const Solved sd = dnu_solve(v, z, s0.p.t0, L, Lq, R, s_tab);
                 const double hsd = sd.p.h * sum_dnu_f64(v, sd.p, sd.A, sd.B, s_tab);
                 nodes += (unsigned long long)(sd.p.N + 1);
                 rn = copysign(assemble(z, sd.delta, hsd, result), nr);
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(256) void k_matern_grad(const double* __restrict__ 
                      (s1.p.h * sum_f64(nu1, s1.p, s1.A, s1.B, s_tab));
             }
             if (on) {
-                const Solved sd = dnu_solve(nu, z, s0.p.t0, L, Lq, R);
+                const Solved sd = dnu_solve(nu, z, s0.p.t0, L, Lq, R, s_tab);
                 vn = vc * (lz - kLn2 - psi) +
                      sigma2 * exp(pref + nu * lz + (sd.delta - z)) * (sd.p.h * sum_dnu_f64(nu, sd.p, sd.A, sd.B, s_tab));
             }

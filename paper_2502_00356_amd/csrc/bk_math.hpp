@@ -135,6 +135,15 @@ __device__ __forceinline__ void stage_tab(double* s, const RuleTable* R)
     __syncthreads();
 }
 
+// log y for a positive normal y: y = 2^e m with m in [1/2, 1), log y = (e - 1) ln 2
+// + log1p(2m - 1), the second from the tables (a few ulps).
+__device__ __forceinline__ double log_tab(double y, const double* T)
+{
+    int e;
+    const double m = frexp(y, &e);
+    return fma((double)(e - 1), kLn2, log1p_tab(2.0 * m - 1.0, T));
+}
+
 __device__ __forceinline__ void cosh_sinh_tab(double t, double& ch, double& sh, const double* T)
 {
     const double e = exp_tab(t, T);
@@ -498,7 +507,7 @@ struct DDer {
     double d, d1, d2, d3;
 };
 
-__device__ __forceinline__ DDer dnu_derivs(double nu, double x, double t)
+__device__ __forceinline__ DDer dnu_derivs(double nu, double x, double t, const double* T)
 {
     DDer r;
     const double omp = -expm1(-2.0 * nu * t);        // 1 - e^(-2 nu t)
@@ -507,8 +516,8 @@ __device__ __forceinline__ DDer dnu_derivs(double nu, double x, double t)
     const double cth = (2.0 - omp) * io;               // coth(nu t)
     const double cs2 = 4.0 * p * io * io;              // csch^2(nu t)
     double ch, sh;
-    cosh_sinh(t, ch, sh);
-    r.d = log(t) + nu * t + log(omp) - kLn2 - x * ch;
+    cosh_sinh_tab(t, ch, sh, T);
+    r.d = log_tab(t, T) + nu * t + log_tab(omp, T) - kLn2 - x * ch;
     r.d1 = it + nu * cth - x * sh;
     r.d2 = -it * it - nu * nu * cs2 - x * ch;
     r.d3 = 2.0 * it * it * it + 2.0 * nu * nu * nu * cth * cs2 - x * sh;
@@ -517,13 +526,13 @@ __device__ __forceinline__ DDer dnu_derivs(double nu, double x, double t)
 
 // Maximiser t_d of d: Halley on d' inside the bracket above (bisection when a step
 // leaves it), stopped once a step is below 1e-7 of t.
-__device__ inline double dnu_peak(double nu, double x)
+__device__ inline double dnu_peak(double nu, double x, const double* T)
 {
     double lo = fmax(asinh(nu / x), fmin(1.0, sqrt(1.70 / x)));
     double hi = asinh((2.0 / lo + nu) / x);
     double t = 0.5 * (lo + hi);
     for (int it = 0; it < 100; ++it) {
-        const DDer r = dnu_derivs(nu, x, t);
+        const DDer r = dnu_derivs(nu, x, t, T);
         if (r.d1 > 0.0) lo = t; else hi = t;
         const double dt = halley_step(r.d1, r.d2, r.d3);
         double tn = t - dt;
@@ -538,12 +547,13 @@ __device__ inline double dnu_peak(double nu, double x)
 // Root t1 > t_d of d(t) = dstar - L by Halley, from acosh(cosh t_d + L/x): there
 // the x term alone has dropped by L while log t + log sinh(nu t) grew, so the start
 // is left of the root. Iterates are kept in (t_d, t_d + 4 (start - t_d) + 1].
-__device__ inline double dnu_window_right(double nu, double x, double td, double chd, double dstar, double L)
+__device__ inline double dnu_window_right(double nu, double x, double td, double chd, double dstar, double L,
+                                          const double* T)
 {
     double t = acosh(chd + L / x);
     const double tcap = td + 4.0 * (t - td) + 1.0;
     for (int it = 0; it < 64; ++it) {
-        const DDer r = dnu_derivs(nu, x, t);
+        const DDer r = dnu_derivs(nu, x, t, T);
         const double dt = halley_step(r.d - dstar + L, r.d1, r.d2);
         double tn = fmin(t - dt, tcap);
         if (!(tn > td)) tn = 0.5 * (t + td);
@@ -558,13 +568,14 @@ __device__ inline double dnu_window_right(double nu, double x, double td, double
 // the strip bound of K with the extra factor of D's integrand on the strip,
 // |t + i a| |sinh(nu (t + i a))| / (t sinh(nu t)) <= (1 + a/t) coth(nu t),
 // taken at the maximiser with a = pi/2.
-__device__ inline Solved dnu_solve(double nu, double x, double t0, double L, double Lq, const RuleTable& R)
+__device__ inline Solved dnu_solve(double nu, double x, double t0, double L, double Lq, const RuleTable& R,
+                                   const double* T)
 {
-    const double td = dnu_peak(nu, x);
-    const DDer r = dnu_derivs(nu, x, td);
+    const double td = dnu_peak(nu, x, T);
+    const DDer r = dnu_derivs(nu, x, td, T);
     double chd, shd;
     cosh_sinh(td, chd, shd);
-    const double t1 = dnu_window_right(nu, x, td, chd, r.d, L);
+    const double t1 = dnu_window_right(nu, x, td, chd, r.d, L, T);
     const double extra = log1p(1.5707963267948966 / td) - log(tanh(nu * td));
     return plan_window(nu, x, t0, t1, td, node_step(nu, x, Lq + extra, R));
 }
