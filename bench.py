@@ -1,10 +1,16 @@
-"""Benchmark: K_nu evaluations per second on the standalone grid workload.
+"""Benchmark: Matern covariance entries per second (K_nu evaluations fused into
+tiled Matern generation), learned window with FP32 terms against plain FP64.
 
-Workload (one step): 2^24 (nu, x) pairs, nu ~ U[0.01, 10], x log-uniform on
-[1e-4, 1e3], 1% exact half-integer orders (seed 2), inputs resident in HBM,
-FP64 output. A step evaluates every pair once with the headline form (learned
-window when a trained model file is present, else the mixed FP32-compensated
-form); the plain FP64 form is timed on the same inputs and reported beside it.
+Default workload (one step): the 316 x 316 jittered grid in [0, 1]^2 (jitter
+U[-0.4, 0.4] cell, seed 7, Morton order; n = 99,856), sigma^2 = 1, beta = 0.02,
+nu = 3.7, lower-triangle 1,024-tiles, 5,036,605,696 entries, locations resident
+in HBM. A step is one bk_matern_tiles call in the learned form with FP32 output
+(window table, interval plans, main kernel, fallback). The mixed form (FP32
+output) and the plain FP64 form (FP64 output) are timed on the same inputs and
+reported beside it.
+
+Other workloads (--workload): grid (2^24 standalone (nu, x) pairs), matern-medium,
+deriv-grid, matern-grad-medium, loglik, paper-grid.
 
 Prints one JSON line. Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -32,21 +38,22 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # build (paper_2502_00356_amd/build.py writes node_slots.json).
 def load_node_slots():
     path = os.path.join(ROOT, "paper_2502_00356_amd", "node_slots.json")
-    slots = {"plain": 41.25, "mixed": 13.75, "learned": 14.5}
-    if os.path.exists(path):
-        with open(path) as f:
-            slots.update({k: float(v) for k, v in json.load(f).items()})
-    return slots
+    if not os.path.exists(path):
+        sys.exit("bench.py: %s is missing; build the library first (python -c 'import __graft_entry__ as g; "
+                 "g.build()'), which writes it from the gfx950 assembly" % path)
+    with open(path) as f:
+        return {k: float(v) for k, v in json.load(f).items()}
 
 
 NODE_SLOTS = load_node_slots()
 
-# HBM bytes per launch of the learned kernel on the 2^24 grid, from the FETCH_SIZE and
-# WRITE_SIZE counter runs scaled by a plain 1 GiB copy (profiles/besselk_grid_2e24_hbm_traffic.txt),
-# valid only for the kernel code they were taken on (hash below, comments ignored); else null.
-TRAFFIC = {"src_sha": "8430eca83b444f74", "n": 1 << 24, "bytes": 416.6e6,
-           # SQ_INSTS_VALU of one launch without statistics (profiles/besselk_grid_2e24_valu_counters.txt)
-           "valu_insts": 100.8e6}
+# Counter figures per launch of a dominant kernel (profiles/), valid only for the
+# kernel code they were taken on (hash of the sources with comments removed), else
+# null: HBM bytes from the FETCH_SIZE and WRITE_SIZE runs scaled by a plain 1 GiB
+# copy, and SQ_INSTS_VALU of one launch without statistics.
+TRAFFIC = {
+    "grid": {"src_sha": "8430eca83b444f74", "n": 1 << 24, "bytes": 416.6e6, "valu_insts": 100.8e6},
+}
 KERNEL_SOURCES = ("bk_mlp.hip", "bk_math.hpp", "bk_internal.hpp")
 
 
@@ -75,9 +82,12 @@ def parse():
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2502_00356_amd", "models", "window_mlp.bin"))
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="grid", choices=["grid", "matern-medium", "matern-large", "deriv-grid",
-                                                           "matern-grad-medium", "loglik", "paper-grid"],
-                    help="grid: the headline standalone workload; matern-*: tiled covariance generation")
+    ap.add_argument("--workload", default="matern-large",
+                    choices=["matern-large", "grid", "matern-medium", "deriv-grid", "matern-grad-medium", "loglik",
+                             "paper-grid"],
+                    help="matern-large: the headline (316 x 316 grid, nu = 3.7, FP32 learned vs FP64 plain)")
+    ap.add_argument("--cpu-tiles", type=int, default=4,
+                    help="matern-large: whole tiles of the last tile row in the CPU baseline sample (0-4)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device-to-device copy instead (HBM reference for counters)")
     return ap.parse_args()
@@ -180,23 +190,191 @@ def main():
     if a.workload == "paper-grid":
         paper_bench(a, torch, api, workloads)
         return
+    if a.workload == "matern-large":
+        matern_headline(a, torch, api, workloads)
+        return
     if a.workload != "grid":
         matern_bench(a, torch, api, workloads)
         return
+    grid_bench(a, torch, api, workloads)
 
+
+def traffic_entry(key, n=None):
+    """The counter figures of TRAFFIC[key] if they were taken on the current kernel
+    sources (and size), else None."""
+    t = TRAFFIC.get(key)
+    if t is None or kernel_src_sha() != t["src_sha"] or (n is not None and t.get("n") != n):
+        return None
+    return t
+
+
+def load_model(a, api):
+    if os.path.exists(a.model):
+        return api.Model(a.model)
+    # no stored model: train one on the GPU (2^20 pairs, about a second), outside the timed region
+    from paper_2502_00356_amd import train_window_mlp
+    model, _ = train_window_mlp.train(out=None, verbose=False)
+    return model
+
+
+def cpu_sample_entries(n, ts, count, tiles, seed):
+    """The CPU baseline sample of the tiled Matern workload: count stored entries
+    drawn uniformly, then whole tiles of the last tile row (the diagonal tile, the one
+    left of it, a middle one and the farthest one), as (row, column) index arrays."""
+    rng = np.random.default_rng(seed)
+    T = (n + ts - 1) // ts
+    i = rng.integers(0, n, count)
+    j = rng.integers(0, n, count)
+    swap = (i // ts) < (j // ts)
+    i[swap], j[swap] = j[swap], i[swap]
+    parts_i, parts_j = [i], [j]
+    I = T - 1
+    for J in (T - 1, T - 2, T // 2, 0)[:tiles]:
+        m, w = n - I * ts, min(ts, n - J * ts)
+        ii, jj = np.meshgrid(np.arange(m) + I * ts, np.arange(w) + J * ts, indexing="ij")
+        parts_i.append(ii.ravel())
+        parts_j.append(jj.ravel())
+    return np.concatenate(parts_i), np.concatenate(parts_j)
+
+
+def packed_index(api, n, ts, i, j):
+    """Offsets in the packed lower-tile output of entries (i, j), i's tile >= j's."""
+    I, J = i // ts, j // ts
+    T = (n + ts - 1) // ts
+    offs = np.array([[api.matern_tile_offset(n, ts, 1, r, c) if c <= r else -1 for c in range(T)] for r in range(T)],
+                    dtype=np.int64)
+    mI = np.minimum(ts, n - I * ts)
+    return offs[I, J] + (i - I * ts) + (j - J * ts) * mI
+
+
+def matern_headline(a, torch, api, workloads):
+    """The headline line: the 316 x 316 grid Matern build (see the module docstring)."""
+    dev = torch.device("cuda:0")
+    c = workloads.MATERN_LARGE
+    xy = workloads.jittered_grid_locations(c["side"], c["seed"])
+    n, ts, nu, beta, s2 = xy.shape[0], c["tile"], c["nu"], c["beta"], c["sigma2"]
+    lx = torch.from_numpy(np.ascontiguousarray(xy[:, 0])).to(dev)
+    ly = torch.from_numpy(np.ascontiguousarray(xy[:, 1])).to(dev)
+    elems = api.matern_out_elems(n, ts, 1)
+    model = load_model(a, api)
+    ws = torch.empty(api.matern_workspace_bytes(n, ts, 1), dtype=torch.uint8, device=dev)
+    outs = {torch.float32: torch.empty(elems, dtype=torch.float32, device=dev),
+            torch.float64: torch.empty(elems, dtype=torch.float64, device=dev)}
+    forms = (("learned", api.OUT_F32, "matern_learned"), ("mixed", api.OUT_F32, "matern_mixed"),
+             ("plain", api.OUT_F64, "matern_plain"))
+    stream = torch.cuda.current_stream()
+    res = {}
+    for f, odt, slot_key in forms:
+        out = outs[torch.float32 if odt == api.OUT_F32 else torch.float64]
+        kw = dict(mode=f, out_dtype=odt, out=out, model=model, workspace=ws)
+        steps = a.steps if f == "learned" else max(1, min(a.steps, 5))
+        for _ in range(a.warmup):
+            api.matern_tiles(lx, ly, s2, beta, nu, ts, 1, **kw)
+        kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for e0, e1 in kev:                  # create the events; the library records them again
+            e0.record(stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for k in range(steps):
+            api.matern_tiles(lx, ly, s2, beta, nu, ts, 1, kernel_events=kev[k], **kw)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps * 1e3
+        ms = ev0.elapsed_time(ev1) / steps
+        kms = sum(e0.elapsed_time(e1) for e0, e1 in kev) / steps
+        # the counting variant, once, outside the timed region
+        st = torch.zeros(api.STATS_LEN, dtype=torch.int64, device=dev)
+        api.matern_tiles(lx, ly, s2, beta, nu, ts, 1, stats=st, **kw)
+        torch.cuda.synchronize()
+        st = st.cpu().numpy()
+        nodes_main = int(st[api.STAT_NODES] - st[api.STAT_FB_NODES])
+        quad_main = int(st[api.STAT_ENTRIES])
+        fb = int(st[api.STAT_FB_RANGE] + st[api.STAT_FB_TAIL] + st[api.STAT_FB_NONFINITE]) if f == "learned" else 0
+        if f == "learned":
+            quad_main -= fb - int(st[api.STAT_FB_RANGE])     # fallback recomputations are counted in ENTRIES too
+        res[f] = dict(ms_per_step=ms, wall_ms_per_step=wall, kernel_ms=kms, steps=steps,
+                      entries_per_s=elems / (ms * 1e-3),
+                      write_gbps=elems * out.element_size() / (ms * 1e-3) / 1e9,
+                      out_dtype="f32" if odt == api.OUT_F32 else "f64",
+                      mean_nodes=nodes_main / max(1, quad_main), node_total_main=nodes_main,
+                      fallbacks=fb, fallback_nodes=int(st[api.STAT_FB_NODES]),
+                      node_slots=NODE_SLOTS.get(slot_key),
+                      node_work_frac=(NODE_SLOTS[slot_key] * nodes_main / (kms * 1e-3) / 1e12 / VALU_PEAK_TOPS
+                                      if slot_key in NODE_SLOTS else None))
+    head = res["learned"]
+
+    # accuracy of each form's timed output on the CPU sample, and the oracle's own
+    # throughput on it (the CPU baseline)
+    cpu, acc = None, {}
+    if not a.no_cpu:
+        import oracle
+        i, j = cpu_sample_entries(n, ts, a.cpu_sample // 4, max(0, min(4, a.cpu_tiles)), seed=99)
+        t0 = time.perf_counter()
+        ref = oracle.matern_entries(xy, xy, i, j, s2, beta, nu)
+        dt = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = dict(value=i.size / dt, unit="entries/s", cores=cores, kind="oracle",
+                   sample="%d stored entries drawn uniformly plus the %d whole tiles of the last tile row (diagonal, "
+                          "its left neighbour, middle, farthest): %d entries; long-double adaptive Gauss-Kronrod, "
+                          "OpenMP over entries, %.1f s" % (a.cpu_sample // 4, max(0, min(4, a.cpu_tiles)), i.size, dt))
+        pidx = torch.from_numpy(packed_index(api, n, ts, i, j)).to(dev)
+        m = ref > 1e-30
+        for f, odt, _ in forms:
+            out = outs[torch.float32 if odt == api.OUT_F32 else torch.float64]
+            api.matern_tiles(lx, ly, s2, beta, nu, ts, 1, mode=f, out_dtype=odt, out=out, model=model, workspace=ws)
+            got = out[pidx].double().cpu().numpy()
+            acc[f] = float((np.abs(got[m] - ref[m]) / ref[m]).max())
+    kms = head["kernel_ms"]
+    achieved = NODE_SLOTS["matern_learned"] * head["node_total_main"] / (kms * 1e-3) / 1e12
+    tr = traffic_entry("matern_large")
+    line = {
+        "metric": "K_nu evals/s (Matern entries/s) mixed+learned vs FP64 at <=2e-6 rel err",
+        "value": head["entries_per_s"],
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 solve and distance + f32 node terms, f32 out",
+        "data": "synthetic",
+        "config": {"workload": "Matern build on a 316x316 jittered grid in [0,1]^2 (jitter U[-0.4,0.4] cell, seed 7, "
+                               "Morton order), n=99856, sigma2=1, beta=0.02, nu=3.7, lower-triangle 1024-tiles, "
+                               "5036605696 entries, FP32 output; plain FP64 (FP64 output) on the same inputs",
+                   "n": n, "tile": ts, "entries": elems, "form": "learned",
+                   "also": "bench.py --workload grid: the 2^24-pair standalone K_nu grid"},
+        "forms": {f: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in d.items()} for f, d in res.items()},
+        "speedup_vs_plain_f64": res["plain"]["ms_per_step"] / head["ms_per_step"],
+        "speedup_vs_mixed": res["mixed"]["ms_per_step"] / head["ms_per_step"],
+        "max_rel_err_sample": acc,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "TOP/s (full-rate VALU lane-op slots)", "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": tr["bytes"] if tr else None,
+                     "kernel": "k_matern_learned<float>", "kernel_ms": kms,
+                     "work": "%.2f VALU issue clocks (full-rate lane-op slots) per trapezoid node x %d nodes per step"
+                             % (NODE_SLOTS["matern_learned"], head["node_total_main"]),
+                     "hbm_gbps": 4.0 * elems / (kms * 1e-3) / 1e9,
+                     "hbm_frac": 4.0 * elems / (kms * 1e-3) / 8e12,
+                     "valu_issue_per_cu_clock": (tr["valu_insts"] / (kms * 1e-3 * 256 * 2.4e9) if tr else None)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def grid_bench(a, torch, api, workloads):
+    """The 2^24-pair standalone K_nu grid: learned (or mixed) beside plain FP64."""
     dev = torch.device("cuda:0")
     nu_h, x_h, half_idx = workloads.grid_pairs(a.n, seed=2)
     nu = torch.from_numpy(nu_h).to(dev)
     x = torch.from_numpy(x_h).to(dev)
     out = torch.empty_like(x)
 
-    model = None
-    if os.path.exists(a.model):
-        model = api.Model(a.model)
-    elif a.form in ("auto", "learned"):
-        # no stored model: train one on the GPU (2^20 pairs, about a second), outside the timed region
-        from paper_2502_00356_amd import train_window_mlp
-        model, _ = train_window_mlp.train(out=None, verbose=False)
+    model = load_model(a, api) if (os.path.exists(a.model) or a.form in ("auto", "learned")) else None
     form = a.form
     if form == "auto":
         form = "learned" if model is not None else "mixed"
@@ -240,8 +418,20 @@ def main():
             e = np.abs(o.cpu().numpy() - ks_ref) / ks_ref
             acc[f] = float(e.max())
             region[f] = per_region(nu_h[idx], x_h[idx], e, half_idx, idx)
+            # the timed output itself (K) at the sampled entries: relative error where K
+            # is normal; where it underflows, the worst excess over one subnormal unit
+            if f == form:
+                api.besselk(nu, x, out=out, mode=f, model=model, workspace=ws)     # the timed call
+                torch.cuda.synchronize()
+                full = out[sel].cpu().numpy()
+                nrm = k_ref >= np.finfo(np.float64).tiny
+                acc[f + " K (timed output), normal range"] = float((np.abs(full[nrm] - k_ref[nrm]) / k_ref[nrm]).max())
+                sub = ~nrm
+                acc[f + " K, underflow zone: max |dK| / (2e-6 K + 2^-1074)"] = float(
+                    (np.abs(full[sub] - k_ref[sub]) / (2e-6 * k_ref[sub] + 2.0 ** -1074)).max()) if sub.any() else None
 
     achieved = NODE_SLOTS[form] * head["node_total"] / (head["kernel_ms"] * 1e-3) / 1e12
+    tr = traffic_entry("grid", a.n) if form == "learned" else None
     line = {
         "metric": "K_nu evals/s (Matern entries/s) mixed+learned vs FP64 at <=2e-6 rel err",
         "value": head["evals_per_s"],
@@ -264,8 +454,7 @@ def main():
         "max_rel_err_by_region": region,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (full-rate VALU lane-op slots)",
                      "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": (TRAFFIC["bytes"] if (form == "learned" and a.n == TRAFFIC["n"]
-                                                      and kernel_src_sha() == TRAFFIC["src_sha"]) else None),
+                     "traffic": (tr["bytes"] if tr else None),
                      "kernel": "k_besselk_learned" if form == "learned" else "k_besselk<%s>" % form,
                      "kernel_ms": head["kernel_ms"],
                      "work": "%.2f VALU issue clocks (full-rate lane-op slots) per trapezoid node x %d nodes per step"
@@ -274,9 +463,8 @@ def main():
                      # all VALU instructions of the launch (counter run) per CU-clock of
                      # the kernel's time; one wave64 instruction per CU-clock is the
                      # full-rate issue limit
-                     "valu_issue_per_cu_clock": (TRAFFIC["valu_insts"] / (head["kernel_ms"] * 1e-3 * 256 * 2.4e9)
-                                                 if (form == "learned" and a.n == TRAFFIC["n"]
-                                                     and kernel_src_sha() == TRAFFIC["src_sha"]) else None)},
+                     "valu_issue_per_cu_clock": (tr["valu_insts"] / (head["kernel_ms"] * 1e-3 * 256 * 2.4e9)
+                                                 if tr else None)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -67,7 +67,10 @@ typedef enum { BK_OUT_F64 = 0, BK_OUT_F32 = 1 } bk_dtype;
 typedef enum { BK_RESULT_K = 0, BK_RESULT_SCALED = 1, BK_RESULT_LOG = 2 } bk_result;
 
 /* Indices into the optional statistics array (device, unsigned 64-bit counters,
- * accumulated, never cleared by the library). */
+ * accumulated, never cleared by the library). bk_besselk_ex and bk_matern_tiles
+ * fill them for every form (the paper form counts its integral branch only).
+ * Counting costs time (the Matern kernels have counting variants), so time
+ * calls without it. */
 enum {
     BK_STAT_ENTRIES = 0,      /* entries evaluated by quadrature               */
     BK_STAT_NODES = 1,        /* sum over entries of (N + 1) trapezoid nodes    */
@@ -76,6 +79,9 @@ enum {
     BK_STAT_NODE_RAISED = 4,  /* learned: predicted N below the strip-bound rule
                                  for the predicted window, raised (not a fallback) */
     BK_STAT_FB_NONFINITE = 5, /* learned: non-finite prediction or sum          */
+    BK_STAT_FB_NODES = 6,     /* learned: nodes of the entries the fallback launch
+                                 recomputed (already counted in BK_STAT_NODES,
+                                 as are those entries in BK_STAT_ENTRIES)     */
     BK_STATS_LEN = 8
 };
 
@@ -92,13 +98,18 @@ typedef struct bk_model bk_model;
  *  out_dtype: bk_dtype of the Matern output, for bk_matern_tiles only.
  *  model    : trained model, required for BK_LEARNED.
  *  stats    : device array of BK_STATS_LEN counters, or NULL.
- *  workspace, workspace_bytes : device scratch owned by the caller; BK_LEARNED
- *             needs at least bk_workspace_bytes(n) bytes (the fallback queue).
+ *  workspace, workspace_bytes : device scratch owned by the caller, for BK_LEARNED
+ *             only: bk_besselk_ex needs bk_workspace_bytes(n) bytes (the fallback
+ *             queue), bk_matern_tiles bk_matern_workspace_bytes(n, tile_size,
+ *             lower_only) bytes (window table, interval plans, fallback bitmap).
+ *             Its contents need not be initialised and are undefined afterwards;
+ *             calls that share a workspace must not overlap.
  *  kernel_events : optional pair of hipEvent_t handles (cast to void*), owned by
- *             the caller. When both are set, bk_besselk_ex records [0] just before
- *             and [1] just after the form's main kernel on the call's stream, so that
- *             kernel can be timed alone (BK_LEARNED's counter reset and fallback
- *             launches fall outside the pair). A failed record returns BK_EHIP. */
+ *             the caller. When both are set, bk_besselk_ex and bk_matern_tiles
+ *             record [0] just before and [1] just after the form's main kernel
+ *             launches on the call's stream, so that they can be timed alone
+ *             (BK_LEARNED's table, plan, reset and fallback launches fall outside
+ *             the pair). A failed record returns BK_EHIP. */
 typedef struct {
     int32_t mode;
     int32_t result;
@@ -161,12 +172,17 @@ typedef struct {
  * (both triangles). With tile_size >= n and lower_only == 0 the output is the
  * whole n x n column-major matrix.
  * out : device buffer of bk_matern_out_elems(n, tile_size, lower_only) elements
- *       of params->out_dtype. params->mode selects the form (BK_LEARNED needs a
- *       model; the Matern path uses no caller workspace: the learned form rebuilds
- *       the model's window table for params->nu and uses the model's fallback list,
- *       so learned Matern calls that share a model must not overlap). */
+ *       of params->out_dtype. params->mode selects the form; BK_LEARNED needs a
+ *       model and a workspace of bk_matern_workspace_bytes(...) bytes, and only
+ *       reads the model, so calls on different streams may share one model. */
 int bk_matern_tiles(const bk_locs* locs, const bk_params* params, int32_t tile_size,
                     int32_t lower_only, void* out, hipStream_t stream);
+
+/* Device workspace bk_matern_tiles needs for BK_LEARNED (bytes; the other forms
+ * need none): a 128 KiB window table and interval plans for the call's nu, then
+ * one bit per wave of 512 entries (about 1/16384 of an FP32 output). 0 if the
+ * sizes are invalid. */
+size_t bk_matern_workspace_bytes(int64_t n, int32_t tile_size, int32_t lower_only);
 
 /* Number of output elements bk_matern_tiles writes (host computation). */
 int64_t bk_matern_out_elems(int64_t n, int32_t tile_size, int32_t lower_only);

@@ -22,7 +22,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 PLAIN_F64, MIXED_F32C, LEARNED, PAPER_REFINED = 0, 1, 2, 3
 RESULT_K, RESULT_SCALED, RESULT_LOG = 0, 1, 2
 OUT_F64, OUT_F32 = 0, 1
-STAT_ENTRIES, STAT_NODES, STAT_FB_RANGE, STAT_FB_TAIL, STAT_NODE_RAISED, STAT_FB_NONFINITE = range(6)
+STAT_ENTRIES, STAT_NODES, STAT_FB_RANGE, STAT_FB_TAIL, STAT_NODE_RAISED, STAT_FB_NONFINITE, STAT_FB_NODES = range(7)
 STATS_LEN = 8
 MLP_NPARAM = 4547
 MODES = {"plain": PLAIN_F64, "mixed": MIXED_F32C, "learned": LEARNED, "paper": PAPER_REFINED}
@@ -63,6 +63,7 @@ _version = _sig("bk_version", ctypes.c_int, [])
 _besselk = _sig("bk_besselk", ctypes.c_int, [_vp, _vp, _vp, _i64, _vp])
 _besselk_ex = _sig("bk_besselk_ex", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(Params), _vp])
 _ws_bytes = _sig("bk_workspace_bytes", ctypes.c_size_t, [_i64])
+_mws_bytes = _sig("bk_matern_workspace_bytes", ctypes.c_size_t, [_i64, _i32, _i32])
 _matern = _sig("bk_matern_tiles", ctypes.c_int, [ctypes.POINTER(Locs), ctypes.POINTER(Params), _i32, _i32, _vp, _vp])
 _out_elems = _sig("bk_matern_out_elems", _i64, [_i64, _i32, _i32])
 _tile_off = _sig("bk_matern_tile_offset", _i64, [_i64, _i32, _i32, _i32, _i32])
@@ -121,12 +122,30 @@ def _stream(stream):
     return stream.cuda_stream
 
 
-def _dev(t, dtype):
-    if not t.is_cuda:
-        raise ValueError("expected a device tensor")
+def _dev(t, dtype, numel=None):
+    """Device pointer of a caller buffer after checking that it is a contiguous
+    device tensor of the given dtype with at least numel elements."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("expected a tensor")
     if t.dtype != dtype or not t.is_contiguous():
         raise ValueError("expected a contiguous %s tensor" % dtype)
+    if numel is not None and t.numel() < numel:
+        raise ValueError("buffer holds %d elements, %d needed" % (t.numel(), numel))
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
     return t.data_ptr()
+
+
+def _stats(stats):
+    return _dev(stats, torch.int64, STATS_LEN) if stats is not None else None
+
+
+def _ws(ws, need):
+    """Workspace pointer and size (a device uint8 tensor of at least need bytes)."""
+    if ws is None:
+        return None, 0
+    _dev(ws, torch.uint8, need)
+    return ws.data_ptr(), ws.numel()
 
 
 def _mode(mode):
@@ -135,6 +154,11 @@ def _mode(mode):
 
 def workspace_bytes(n):
     return int(_ws_bytes(int(n)))
+
+
+def matern_workspace_bytes(n, tile_size, lower_only):
+    """Workspace of bk_matern_tiles in the learned form (bytes)."""
+    return int(_mws_bytes(int(n), int(tile_size), int(lower_only)))
 
 
 def besselk(nu, x, out=None, mode="plain", result=RESULT_K, L_window=0.0, L_quad=0.0,
@@ -152,24 +176,26 @@ def besselk(nu, x, out=None, mode="plain", result=RESULT_K, L_window=0.0, L_quad
     m = _mode(mode)
     if m == LEARNED and workspace is None and n > 0:
         workspace = torch.empty(workspace_bytes(n), dtype=torch.uint8, device=x.device)
+    wp, wb = _ws(workspace, workspace_bytes(n) if m == LEARNED else 0)
+    sp = _stats(stats)
+    op = _dev(out, torch.float64, n)
     p = Params(mode=m, result=int(result), L_window=float(L_window), L_quad=float(L_quad),
                bins=int(bins), t_upper=float(t_upper),
                model=(model.handle if model is not None else None),
-               stats=(_dev(stats, torch.int64) if stats is not None else None),
-               workspace=(workspace.data_ptr() if workspace is not None else None),
-               workspace_bytes=(workspace.numel() * workspace.element_size() if workspace is not None else 0))
+               stats=sp, workspace=wp, workspace_bytes=wb)
     if kernel_events is not None:
         p.kernel_events[0] = kernel_events[0].cuda_event
         p.kernel_events[1] = kernel_events[1].cuda_event
-    _check(_besselk_ex(_dev(nu, torch.float64), _dev(x, torch.float64), _dev(out, torch.float64), n,
-                       ctypes.byref(p), _stream(stream)))
+    _check(_besselk_ex(_dev(nu, torch.float64), _dev(x, torch.float64), op, n, ctypes.byref(p), _stream(stream)))
     return out
 
 
 def besselk_plain(nu, x, out, stream=None):
     """The fixed-signature entry point bk_besselk (plain FP64, default window)."""
-    _check(_besselk(_dev(nu, torch.float64), _dev(x, torch.float64), _dev(out, torch.float64),
-                    x.numel(), _stream(stream)))
+    n = x.numel()
+    if nu.numel() != n:
+        raise ValueError("nu and x differ in size")
+    _check(_besselk(_dev(nu, torch.float64), _dev(x, torch.float64), _dev(out, torch.float64, n), n, _stream(stream)))
     return out
 
 
@@ -193,8 +219,11 @@ def matern_tile_offset(n, tile_size, lower_only, I, J):
 
 
 def matern_tiles(lx, ly, sigma2, beta, nu, tile_size, lower_only, mode="plain", out_dtype=OUT_F64,
-                 out=None, model=None, L_window=0.0, L_quad=0.0, stream=None, bins=0, t_upper=0.0):
-    """Tiled Matern covariance (packed tiles, see bk_matern_tiles)."""
+                 out=None, model=None, L_window=0.0, L_quad=0.0, stream=None, bins=0, t_upper=0.0,
+                 workspace=None, stats=None, kernel_events=None):
+    """Tiled Matern covariance (packed tiles, see bk_matern_tiles). The learned form
+    takes a workspace of matern_workspace_bytes(n, tile_size, lower_only) bytes
+    (allocated here when not given)."""
     n = lx.numel()
     if ly.numel() != n:
         raise ValueError("lx and ly differ in size")
@@ -202,14 +231,21 @@ def matern_tiles(lx, ly, sigma2, beta, nu, tile_size, lower_only, mode="plain", 
     dt = torch.float32 if int(out_dtype) == OUT_F32 else torch.float64
     if out is None:
         out = torch.empty(max(elems, 0), dtype=dt, device=lx.device)
-    if out.numel() < elems or out.dtype != dt:
-        raise ValueError("out too small or of the wrong dtype")
+    m = _mode(mode)
+    need = matern_workspace_bytes(n, tile_size, lower_only) if m == LEARNED else 0
+    if m == LEARNED and workspace is None and n > 0:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=lx.device)
+    wp, wb = _ws(workspace, need)
+    op = _dev(out, dt, max(elems, 0))
     locs = Locs(x=_dev(lx, torch.float64), y=_dev(ly, torch.float64), n=n)
-    p = Params(mode=_mode(mode), out_dtype=int(out_dtype), sigma2=float(sigma2), beta=float(beta), nu=float(nu),
+    p = Params(mode=m, out_dtype=int(out_dtype), sigma2=float(sigma2), beta=float(beta), nu=float(nu),
                L_window=float(L_window), L_quad=float(L_quad), bins=int(bins), t_upper=float(t_upper),
-               model=(model.handle if model is not None else None))
-    _check(_matern(ctypes.byref(locs), ctypes.byref(p), int(tile_size), int(lower_only), out.data_ptr(),
-                   _stream(stream)))
+               model=(model.handle if model is not None else None), stats=_stats(stats),
+               workspace=wp, workspace_bytes=wb)
+    if kernel_events is not None:
+        p.kernel_events[0] = kernel_events[0].cuda_event
+        p.kernel_events[1] = kernel_events[1].cuda_event
+    _check(_matern(ctypes.byref(locs), ctypes.byref(p), int(tile_size), int(lower_only), op, _stream(stream)))
     return out
 
 
@@ -224,12 +260,10 @@ def besselk_deriv(nu, x, want=("k", "dx", "dnu"), result=RESULT_K, L_window=0.0,
     if any(k not in ("k", "dx", "dnu") for k in want):
         raise ValueError("unknown output")
     outs = {k: (out[k] if out is not None and k in out else torch.empty_like(x)) for k in want}
-    for t in outs.values():
-        if t.numel() != n:
-            raise ValueError("output of the wrong size")
+    ptrs = {k: _dev(t, torch.float64, n) for k, t in outs.items()}
     p = Params(mode=PLAIN_F64, result=int(result), L_window=float(L_window), L_quad=float(L_quad),
-               stats=(_dev(stats, torch.int64) if stats is not None else None))
-    ptr = lambda k: outs[k].data_ptr() if k in outs else None
+               stats=_stats(stats))
+    ptr = lambda k: ptrs.get(k)
     _check(_deriv(_dev(nu, torch.float64), _dev(x, torch.float64), ptr("k"), ptr("dx"), ptr("dnu"), n,
                   ctypes.byref(p), _stream(stream)))
     return outs
@@ -249,13 +283,11 @@ def matern_grad_tiles(lx, ly, sigma2, beta, nu, tile_size, lower_only, out_dtype
     dt = torch.float32 if int(out_dtype) == OUT_F32 else torch.float64
     outs = {k: (out[k] if out is not None and k in out else torch.empty(max(elems, 0), dtype=dt, device=lx.device))
             for k in want}
-    for t in outs.values():
-        if t.numel() < elems or t.dtype != dt:
-            raise ValueError("output too small or of the wrong dtype")
+    ptrs = {k: _dev(t, dt, max(elems, 0)) for k, t in outs.items()}
     locs = Locs(x=_dev(lx, torch.float64), y=_dev(ly, torch.float64), n=n)
     p = Params(mode=PLAIN_F64, out_dtype=int(out_dtype), sigma2=float(sigma2), beta=float(beta), nu=float(nu),
                L_window=float(L_window), L_quad=float(L_quad))
-    ptr = lambda k: outs[k].data_ptr() if k in outs else None
+    ptr = lambda k: ptrs.get(k)
     _check(_matern_grad(ctypes.byref(locs), ctypes.byref(p), int(tile_size), int(lower_only), ptr("c"),
                         ptr("dbeta"), ptr("dnu"), _stream(stream)))
     return outs
@@ -273,12 +305,13 @@ def matern_loglik(lx, ly, z, sigma2, beta, nu, grad=False, mode="plain", model=N
         raise ValueError("n out of range")
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=lx.device)
+    wp, wb = _ws(workspace, need)
     locs = Locs(x=_dev(lx, torch.float64), y=_dev(ly, torch.float64), n=n)
     p = Params(mode=_mode(mode), sigma2=float(sigma2), beta=float(beta), nu=float(nu), L_window=float(L_window),
                L_quad=float(L_quad), model=(model.handle if model is not None else None))
     res = (ctypes.c_double * 4)()
     _check(_loglik(ctypes.byref(locs), _dev(z, torch.float64), ctypes.byref(p), 1 if grad else 0, res,
-                   workspace.data_ptr(), workspace.numel() * workspace.element_size(), _stream(stream)))
+                   wp, wb, _stream(stream)))
     if grad:
         return res[0], [res[1], res[2], res[3]]
     return res[0]
@@ -384,7 +417,7 @@ class Model:
         """Raw MLP forward (FP16 matrix cores) on normalised inputs u (n x 2 float32)."""
         n = u.shape[0]
         y = torch.empty((n, 3), dtype=torch.float32, device=u.device)
-        _check(_mlp_infer(self.handle, _dev(u, torch.float32), y.data_ptr(), n, _stream(stream)))
+        _check(_mlp_infer(self.handle, _dev(u, torch.float32, 2 * n), y.data_ptr(), n, _stream(stream)))
         return y
 
 
@@ -395,12 +428,13 @@ def mlp_grad(params, u, target, tau, stream=None):
     loss = torch.empty(1, dtype=torch.float32, device=u.device)
     sb = int(_mlp_grad_scratch(B))
     scratch = torch.empty(max(sb, 1), dtype=torch.uint8, device=u.device)
-    _check(_mlp_grad(_dev(params, torch.float32), _dev(u, torch.float32), _dev(target, torch.float32),
-                     _dev(tau, torch.float32), B, grad.data_ptr(), loss.data_ptr(), scratch.data_ptr(), sb,
+    _check(_mlp_grad(_dev(params, torch.float32, MLP_NPARAM), _dev(u, torch.float32, 2 * B),
+                     _dev(target, torch.float32, 3 * B), _dev(tau, torch.float32, 3), B, grad.data_ptr(), loss.data_ptr(), scratch.data_ptr(), sb,
                      _stream(stream)))
     return loss, grad
 
 
 def adam_step(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
-    _check(_adam(_dev(p, torch.float32), _dev(g, torch.float32), _dev(m, torch.float32), _dev(v, torch.float32),
-                 p.numel(), int(step), float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
+    n = p.numel()
+    gp, mp, vp = (_dev(t, torch.float32, n) for t in (g, m, v))
+    _check(_adam(_dev(p, torch.float32), gp, mp, vp, n, int(step), float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))

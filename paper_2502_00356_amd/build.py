@@ -77,7 +77,10 @@ def node_slots(asm_path):
             funcs[cur] = []
         elif cur is not None:
             funcs[cur].append(l)
-    want = {"plain": "k_besselkILi0", "mixed": "k_besselkILi1", "learned": "k_besselk_learnedILb1"}
+    want = {"plain": "k_besselkILi0", "mixed": "k_besselkILi1", "learned": "k_besselk_learnedILb1",
+            # Matern kernels without statistics: FP64 output for plain, FP32 for the others
+            "matern_plain": "k_maternILi0EdLb0", "matern_mixed": "k_maternILi1EfLb0",
+            "matern_learned": "k_matern_learnedIfLb0"}
     out = {}
     for form, key in want.items():
         name = next((f for f in funcs if key in f), None)
@@ -88,14 +91,15 @@ def node_slots(asm_path):
         for a, b in _loops(body):
             seg = [x.strip() for x in body[a:b + 1]]
             ops = [x.split()[0] for x in seg if x.startswith("v_")]
-            if form == "plain":
+            if form in ("plain", "matern_plain"):
                 ok = ops.count("v_ldexp_f64") >= 1 and "v_div_scale_f64" not in ops and "v_frexp_mant_f64_e32" not in ops
             else:
                 ok = any(o.startswith("v_exp_f32") for o in ops) and "v_div_scale_f64" not in ops
             if ok:
                 slots = sum(issue_cost(o) for o in ops if not o.startswith("v_mfma"))
                 # an unrolled loop evaluates several nodes per trip: one node exponential each
-                per_trip = ops.count("v_ldexp_f64") if form == "plain" else sum(o.startswith("v_exp_f32") for o in ops)
+                per_trip = (ops.count("v_ldexp_f64") if form in ("plain", "matern_plain")
+                            else sum(o.startswith("v_exp_f32") for o in ops))
                 slots = slots / max(1, per_trip)
                 if best is None or (b - a) < best[0]:
                     best = (b - a, slots)

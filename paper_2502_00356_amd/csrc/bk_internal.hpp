@@ -3,6 +3,9 @@
 #include <stdint.h>
 #include <hip/hip_runtime.h>
 
+#include <tuple>
+#include <utility>
+
 #include "../../include/besselk.h"
 #include "bk_math.hpp"
 
@@ -24,10 +27,6 @@ constexpr int kPaperBins = 40;
 constexpr double kPaperT = 9.0;
 constexpr double kPaperTemmeX = 0.1;
 
-const RuleTable& rule_table();
-const RuleTable* rule_table_dev();
-const TemmeCoef& temme_coef();
-const TemmeCoef* temme_coef_dev();
 void resolve_thresholds(int mode, double L_in, double Lq_in, double* L, double* Lq);
 
 // Records the caller's kernel_events[k] on stream when both events are set
@@ -38,9 +37,32 @@ inline hipError_t mark_kernel_event(const bk_params* p, int k, hipStream_t strea
     return hipEventRecord((hipEvent_t)p->kernel_events[k], stream);
 }
 
+template <typename... P, size_t... I>
+inline int launch_args(void (*k)(P...), dim3 grid, dim3 block, hipStream_t stream, std::tuple<P...>& args,
+                       std::index_sequence<I...>)
+{
+    void* ptrs[] = {static_cast<void*>(&std::get<I>(args))...};
+    return hipLaunchKernel(reinterpret_cast<const void*>(k), grid, block, ptrs, 0, stream) == hipSuccess ? BK_OK
+                                                                                                       : BK_EHIP;
+}
+
+// Enqueues kernel k on stream, its arguments converted to the kernel's parameter
+// types. The status is the launch's own (BK_OK or BK_EHIP): no error state left by
+// other code is read or cleared.
+template <typename... P, typename... A>
+inline int launch(void (*k)(P...), dim3 grid, dim3 block, hipStream_t stream, A&&... a)
+{
+    static_assert(sizeof...(P) == sizeof...(A), "kernel argument count");
+    std::tuple<P...> args(std::forward<A>(a)...);
+    return launch_args(k, grid, block, stream, args, std::index_sequence_for<P...>{});
+}
+
 int bk_besselk_learned(const double* nu, const double* x, double* out, int64_t n, const bk_params* prm,
                        double L, double Lq, hipStream_t stream);
+// Workspace bytes of the learned Matern form for one call (window table, interval
+// plans, wave bitmap); 0 if the sizes are invalid.
+size_t matern_learned_workspace_bytes(int64_t n, int32_t tile_size, int32_t lower_only);
 int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_size, int32_t lower_only,
-                      void* out, double L, double Lq, hipStream_t stream);
+                      void* out, double L, double Lq, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 }  // namespace bk

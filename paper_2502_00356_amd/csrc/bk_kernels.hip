@@ -15,123 +15,11 @@
 #include <stdint.h>
 #include <string.h>
 
-#include <mutex>
-
 #include "../../include/besselk.h"
 #include "bk_math.hpp"
 #include "bk_internal.hpp"
 
 namespace bk {
-
-// ---------------------------------------------------------------------------
-// Host-side constants of the node-count rule: strip half-widths
-// a = (pi/2) 2^(-k/2) and (pi/2)(1 - 2^(-k/2)), k = 1..8 (15 distinct values).
-// ---------------------------------------------------------------------------
-const RuleTable& rule_table()
-{
-    static RuleTable R = [] {
-        RuleTable t;
-        double vals[16];
-        int n = 0;
-        for (int k = 1; k <= 8; ++k) {
-            double f = pow(2.0, -k / 2.0);
-            double c1 = 1.5707963267948966192 * f, c2 = 1.5707963267948966192 * (1.0 - f);
-            bool d1 = false, d2 = false;
-            for (int j = 0; j < n; ++j) {
-                if (fabs(vals[j] - c1) < 1e-15) d1 = true;
-                if (fabs(vals[j] - c2) < 1e-15) d2 = true;
-            }
-            if (!d1) vals[n++] = c1;
-            if (!d2 && fabs(c1 - c2) >= 1e-15) vals[n++] = c2;
-        }
-        for (int k = 0; k < kRuleCand; ++k) {
-            double a = vals[k < n ? k : n - 1];
-            t.a[k] = a;
-            t.omc[k] = 1.0 - cos(a);
-            t.lsec[k] = -log(cos(a));
-        }
-        for (int j = 0; j < 64; ++j) t.tab[j] = (double)exp2l((long double)j / 64.0L);
-        for (int j = 0; j <= 64; ++j) {
-            t.tab[kTabLog1p + j] = (double)log1pl((long double)j / 64.0L);
-            t.tab[kTabInv1p + j] = (double)(1.0L / (1.0L + (long double)j / 64.0L));
-        }
-        return t;
-    }();
-    return R;
-}
-
-// Device copy of the rule table, one per GPU, made on first use and kept for the
-// life of the process (1912 bytes). Kernels read it through a pointer, so its
-// values are scalar loads rather than 90 kernel-argument SGPRs.
-const RuleTable* rule_table_dev()
-{
-    static std::mutex mu;
-    static const RuleTable* dev_tab[64] = {nullptr};
-    int d = 0;
-    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return nullptr;
-    std::lock_guard<std::mutex> lk(mu);
-    if (!dev_tab[d]) {
-        RuleTable* p = nullptr;
-        if (hipMalloc((void**)&p, sizeof(RuleTable)) != hipSuccess) return nullptr;
-        if (hipMemcpy(p, &rule_table(), sizeof(RuleTable), hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(p);
-            return nullptr;
-        }
-        dev_tab[d] = p;
-    }
-    return dev_tab[d];
-}
-
-// Chebyshev coefficients of Temme's Gamma1 and Gamma2 (even in mu) in
-// u = 8 mu^2 - 1, by interpolation at kTemmeCheb Chebyshev nodes, in long double.
-const TemmeCoef& temme_coef()
-{
-    static TemmeCoef C = [] {
-        TemmeCoef c;
-        const int n = kTemmeCheb;
-        long double f1[kTemmeCheb], f2[kTemmeCheb];
-        const long double pi = 3.141592653589793238462643383279502884L;
-        for (int k = 0; k < n; ++k) {
-            const long double u = cosl(pi * ((long double)k + 0.5L) / (long double)n);
-            const long double mu = sqrtl((u + 1.0L) / 8.0L);
-            const long double gm = 1.0L / tgammal(1.0L - mu), gp = 1.0L / tgammal(1.0L + mu);
-            f1[k] = (gm - gp) / (2.0L * mu);
-            f2[k] = 0.5L * (gm + gp);
-        }
-        for (int j = 0; j < n; ++j) {
-            long double a1 = 0.0L, a2 = 0.0L;
-            for (int k = 0; k < n; ++k) {
-                const long double w = cosl(pi * (long double)j * ((long double)k + 0.5L) / (long double)n);
-                a1 += f1[k] * w;
-                a2 += f2[k] * w;
-            }
-            const long double sc = (j == 0 ? 1.0L : 2.0L) / (long double)n;
-            c.g1[j] = (double)(a1 * sc);
-            c.g2[j] = (double)(a2 * sc);
-        }
-        return c;
-    }();
-    return C;
-}
-
-const TemmeCoef* temme_coef_dev()
-{
-    static std::mutex mu;
-    static const TemmeCoef* dev_tab[64] = {nullptr};
-    int d = 0;
-    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return nullptr;
-    std::lock_guard<std::mutex> lk(mu);
-    if (!dev_tab[d]) {
-        TemmeCoef* p = nullptr;
-        if (hipMalloc((void**)&p, sizeof(TemmeCoef)) != hipSuccess) return nullptr;
-        if (hipMemcpy(p, &temme_coef(), sizeof(TemmeCoef), hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(p);
-            return nullptr;
-        }
-        dev_tab[d] = p;
-    }
-    return dev_tab[d];
-}
 
 void resolve_thresholds(int mode, double L_in, double Lq_in, double* L, double* Lq)
 {
@@ -155,6 +43,15 @@ __device__ void block_count_w(unsigned long long* dst, unsigned long long v, int
         for (int w = 0; w < nw; ++w) t += red[w];
         atomicAdd(dst, t);
     }
+}
+
+// Sum of a per-lane count over a wave (every lane active), added once to a global
+// counter by lane 0.
+__device__ inline void wave_count(unsigned long long* dst, unsigned int v)
+{
+    unsigned long long a = v;
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if ((threadIdx.x & 63) == 0 && a) atomicAdd(dst, a);
 }
 
 // Special values shared by every form; returns true if handled.
@@ -214,7 +111,7 @@ template <int MODE>
 __global__ __launch_bounds__(kSolveBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_besselk(const double* __restrict__ nu,
                                                          const double* __restrict__ x,
                                                          double* __restrict__ out, int64_t n, int result,
-                                                         double L, double Lq, const RuleTable* __restrict__ Rp,
+                                                         double L, double Lq, 
                                                          unsigned long long* __restrict__ stats)
 {
     __shared__ unsigned int hist[64];
@@ -222,7 +119,7 @@ __global__ __launch_bounds__(kSolveBlock) __attribute__((amdgpu_waves_per_eu(6, 
     __shared__ double s_d[8][kSolveBlock];
     __shared__ int s_i[3][kSolveBlock];
     const int tid = threadIdx.x;
-    if (tid < kTabLen) s_tab[tid] = Rp->tab[tid];   // read after the sorts' barriers
+    if (tid < kTabLen) s_tab[tid] = rule_tab().tab[tid];   // read after the sorts' barriers
     const int64_t i = (int64_t)blockIdx.x * kSolveBlock + tid;
     double v = 0.0, z = 1.0;
     bool work = false;
@@ -246,7 +143,7 @@ __global__ __launch_bounds__(kSolveBlock) __attribute__((amdgpu_waves_per_eu(6, 
     __syncthreads();
     Solved sv;
     sv.p.N = -1;
-    if (li >= 0) sv = plain_solve(v2, z2, L, Lq, *Rp, s_tab);
+    if (li >= 0) sv = plain_solve(v2, z2, L, Lq, rule_tab(), s_tab);
     // phase 2 -> 3: sort by node count
     const int nkey = li < 0 ? 0 : (sv.p.N < 63 ? sv.p.N : 63);
     slot = block_sort_slot<kSolveBlock>(nkey, hist);
@@ -288,12 +185,12 @@ __global__ __launch_bounds__(kSolveBlock) __attribute__((amdgpu_waves_per_eu(6, 
 // series with the forward recurrence for x < 0.1, the fixed-window sum otherwise.
 __global__ __launch_bounds__(256) void k_besselk_paper(const double* __restrict__ nu, const double* __restrict__ x,
                                                        double* __restrict__ out, int64_t n, int result, int bins,
-                                                       double T, const TemmeCoef* __restrict__ Cp,
-                                                       const RuleTable* __restrict__ Rp,
+                                                       double T, 
+                                                       
                                                        unsigned long long* __restrict__ stats)
 {
     __shared__ double s_tab[kTabLen];
-    stage_tab(s_tab, Rp);
+    stage_tab(s_tab);
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long nodes = 0, ents = 0;
     if (i < n) {
@@ -302,7 +199,7 @@ __global__ __launch_bounds__(256) void k_besselk_paper(const double* __restrict_
         if (!special_value(v, z, result, r)) {
             if (z < kPaperTemmeX) {
                 // K directly; written as exp(-z) exp(0) (e^z K) for the shared assembly
-                r = assemble(z, 0.0, temme_k(v, z, *Cp) * exp(z), result);
+                r = assemble(z, 0.0, temme_k(v, z, temme_tab()) * exp(z), result);
             } else {
                 const FixedOut f = paper_fixed(v, z, bins, T, s_tab);
                 // K = exp(lscale) h S, written through Delta = lscale + z so that the
@@ -324,7 +221,7 @@ __global__ __launch_bounds__(256) void k_window(const double* __restrict__ nu,
                                                 const double* __restrict__ x,
                                                 double* __restrict__ tlo, double* __restrict__ thi,
                                                 int32_t* __restrict__ nodes, int64_t n, double L,
-                                                double Lq, const RuleTable* __restrict__ Rp)
+                                                double Lq)
 {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
@@ -333,7 +230,7 @@ __global__ __launch_bounds__(256) void k_window(const double* __restrict__ nu,
         tlo[i] = __builtin_nan(""); thi[i] = __builtin_nan(""); nodes[i] = 0;
         return;
     }
-    Solved s = plain_solve(v, z, L, Lq, *Rp, Rp->tab);
+    Solved s = plain_solve(v, z, L, Lq, rule_tab(), rule_tab().tab);
     tlo[i] = s.p.t0;
     thi[i] = s.t1;
     nodes[i] = s.p.N;
@@ -353,11 +250,11 @@ __device__ __forceinline__ double unscale(double z, double s, int result)
 __global__ __launch_bounds__(256, 3) void k_besselk_deriv(const double* __restrict__ nu, const double* __restrict__ x,
                                                        double* __restrict__ k, double* __restrict__ dkdx,
                                                        double* __restrict__ dkdnu, int64_t n, int result, double L,
-                                                       double Lq, const RuleTable* __restrict__ Rp,
+                                                       double Lq, 
                                                        unsigned long long* __restrict__ stats)
 {
     __shared__ double s_tab[kTabLen];
-    stage_tab(s_tab, Rp);
+    stage_tab(s_tab);
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long nodes = 0, ents = 0;
     if (i < n) {
@@ -374,7 +271,7 @@ __global__ __launch_bounds__(256, 3) void k_besselk_deriv(const double* __restri
             rx = -0.0;
             rn = copysign(0.0, nr);
         } else {
-            const RuleTable& R = *Rp;
+            const RuleTable& R = rule_tab();
             const Solved s0 = plain_solve(v, z, L, Lq, R, s_tab);
             const double hs0 = s0.p.h * sum_f64(v, s0.p, s0.A, s0.B, s_tab);
             rk = assemble(z, s0.delta, hs0, result);
@@ -443,16 +340,19 @@ __device__ inline void tile_of(int64_t p, const TileGeom& g, int64_t& I, int64_t
     I = J + (p - (J * T - J * (J - 1) / 2));
 }
 
-template <int MODE, typename OutT>
+// kStats: the statistics variant, which also counts the entries evaluated by
+// quadrature and their nodes (lanes past a ragged tile's last row stay in the
+// wave, idle, so that the wave can sum its counts).
+template <int MODE, typename OutT, bool kStats>
 __global__ __launch_bounds__(256, 4) void k_matern(const double* __restrict__ lx,
                                                 const double* __restrict__ ly, TileGeom g,
                                                 int64_t tile_base, double sigma2, double inv_beta,
                                                 double nu, double pref, double L, double Lq,
-                                                const RuleTable* __restrict__ Rp, int bins, double T,
-                                                const TemmeCoef* __restrict__ Cp, OutT* __restrict__ out)
+                                                int bins, double T, OutT* __restrict__ out,
+                                                unsigned long long* __restrict__ stats)
 {
     __shared__ double s_tab[kTabLen];
-    stage_tab(s_tab, Rp);                   // before any wave leaves
+    stage_tab(s_tab);                   // before any wave leaves
     // block -> (tile, row block, column block) in 32-bit arithmetic (a 64-bit
     // division is a long instruction sequence)
     const unsigned wg_per_tile = (unsigned)g.rb_per_tile * (unsigned)g.cb_per_tile;
@@ -467,10 +367,13 @@ __global__ __launch_bounds__(256, 4) void k_matern(const double* __restrict__ lx
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t il = (int64_t)rb * kRowsPerWave + lane;
     const int64_t jl0 = (int64_t)cb * kColsPerGroup + (int64_t)wave * kColsPerWave;
-    if (il >= mI || jl0 >= nJ) return;
+    const bool row_ok = il < mI;
+    if (jl0 >= nJ || (!kStats && !row_ok)) return;
     const int64_t base = tile_offset(g.n, g.ts, g.T, g.lower, I, J);
-    const double xi = lx[I * g.ts + il], yi = ly[I * g.ts + il];
-    const int cend = (int)min((int64_t)kColsPerWave, nJ - jl0);
+    const int64_t ilr = row_ok ? il : 0;
+    const double xi = lx[I * g.ts + ilr], yi = ly[I * g.ts + ilr];
+    const int cend = (kStats && !row_ok) ? 0 : (int)min((int64_t)kColsPerWave, nJ - jl0);
+    unsigned int c_ent = 0, c_nodes = 0;
     for (int c = 0; c < cend; ++c) {
         const int64_t jl = jl0 + c;
         const double xj = lx[J * g.ts + jl], yj = ly[J * g.ts + jl];
@@ -483,18 +386,26 @@ __global__ __launch_bounds__(256, 4) void k_matern(const double* __restrict__ lx
             const double z = r * inv_beta;
             if (MODE == BK_PAPER_REFINED) {
                 if (z < kPaperTemmeX) {
-                    val = sigma2 * exp(pref + nu * log(z)) * temme_k(nu, z, *Cp);
+                    val = sigma2 * exp(pref + nu * log(z)) * temme_k(nu, z, temme_tab());
                 } else {
                     const FixedOut f = paper_fixed(nu, z, bins, T, s_tab);
                     val = sigma2 * exp(pref + nu * log(z) + f.lscale) * f.hs;
+                    c_nodes += (unsigned int)(bins + 1);
+                    c_ent += 1;
                 }
             } else {
-                Solved s = plain_solve(nu, z, L, Lq, *Rp, s_tab);
+                Solved s = plain_solve(nu, z, L, Lq, rule_tab(), s_tab);
                 double S = (MODE == BK_PLAIN_F64) ? sum_f64(nu, s.p, s.A, s.B, s_tab) : sum_mixed(nu, z, s.p, s.A, s_tab);
                 val = sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * (s.p.h * S);
+                c_nodes += (unsigned int)(s.p.N + 1);
+                c_ent += 1;
             }
         }
         out[base + il + jl * mI] = (OutT)val;
+    }
+    if (kStats) {
+        wave_count(stats + BK_STAT_ENTRIES, c_ent);
+        wave_count(stats + BK_STAT_NODES, c_nodes);
     }
 }
 
@@ -509,11 +420,11 @@ template <typename OutT>
 __global__ __launch_bounds__(256) void k_matern_grad(const double* __restrict__ lx, const double* __restrict__ ly,
                                                      TileGeom g, int64_t tile_base, double sigma2, double inv_beta,
                                                      double nu, double pref, double psi, double L, double Lq,
-                                                     const RuleTable* __restrict__ Rp, OutT* __restrict__ oc,
+                                                      OutT* __restrict__ oc,
                                                      OutT* __restrict__ ob, OutT* __restrict__ on)
 {
     __shared__ double s_tab[kTabLen];
-    stage_tab(s_tab, Rp);                   // before any wave leaves
+    stage_tab(s_tab);                   // before any wave leaves
     // block -> (tile, row block, column block) in 32-bit arithmetic (a 64-bit
     // division is a long instruction sequence)
     const unsigned wg_per_tile = (unsigned)g.rb_per_tile * (unsigned)g.cb_per_tile;
@@ -540,7 +451,7 @@ __global__ __launch_bounds__(256) void k_matern_grad(const double* __restrict__ 
         const double r = sqrt(dx * dx + dy * dy);
         double vc = sigma2, vb = 0.0, vn = 0.0;
         if (r != 0.0) {
-            const RuleTable& R = *Rp;
+            const RuleTable& R = rule_tab();
             const double z = r * inv_beta, lz = log(z);
             const Solved s0 = plain_solve(nu, z, L, Lq, R, s_tab);
             // the same expression as k_matern, so that C is bit-identical with or without the derivatives
@@ -586,14 +497,22 @@ extern "C" const char* bk_status_str(int status)
 
 extern "C" int bk_version(void) { return 10000; }
 
-static int launch_status() { return hipGetLastError() == hipSuccess ? BK_OK : BK_EHIP; }
-
 extern "C" int bk_besselk(const double* nu, const double* x, double* out, int64_t n, hipStream_t stream)
 {
     bk_params p;
     memset(&p, 0, sizeof(p));
     p.mode = BK_PLAIN_F64;
     return bk_besselk_ex(nu, x, out, n, &p, stream);
+}
+
+// One kernel between the caller's optional event pair.
+template <typename K, typename... A>
+static int launch_timed(const bk_params* prm, K k, dim3 grid, dim3 block, hipStream_t stream, A&&... a)
+{
+    if (mark_kernel_event(prm, 0, stream) != hipSuccess) return BK_EHIP;
+    const int st = launch(k, grid, block, stream, std::forward<A>(a)...);
+    if (st != BK_OK) return st;
+    return mark_kernel_event(prm, 1, stream) == hipSuccess ? BK_OK : BK_EHIP;
 }
 
 extern "C" int bk_besselk_ex(const double* nu, const double* x, double* out, int64_t n,
@@ -608,34 +527,21 @@ extern "C" int bk_besselk_ex(const double* nu, const double* x, double* out, int
     resolve_thresholds(prm->mode, prm->L_window, prm->L_quad, &L, &Lq);
     const int64_t blocks = (n + kSolveBlock - 1) / kSolveBlock;
     if (blocks > 0x7fffffffLL) return BK_EINVAL;
-    const RuleTable* R = rule_table_dev();
-    if (!R) return BK_EHIP;
     switch (prm->mode) {
     case BK_PLAIN_F64:
-        if (mark_kernel_event(prm, 0, stream) != hipSuccess) return BK_EHIP;
-        hipLaunchKernelGGL(k_besselk<BK_PLAIN_F64>, dim3((unsigned)blocks), dim3(kSolveBlock), 0, stream,
-                           nu, x, out, n, prm->result, L, Lq, R, prm->stats);
-        if (launch_status() != BK_OK) return BK_EHIP;
-        return mark_kernel_event(prm, 1, stream) == hipSuccess ? BK_OK : BK_EHIP;
+        return launch_timed(prm, k_besselk<BK_PLAIN_F64>, dim3((unsigned)blocks), dim3(kSolveBlock), stream, nu, x,
+                            out, n, prm->result, L, Lq, prm->stats);
     case BK_MIXED_F32C:
-        if (mark_kernel_event(prm, 0, stream) != hipSuccess) return BK_EHIP;
-        hipLaunchKernelGGL(k_besselk<BK_MIXED_F32C>, dim3((unsigned)blocks), dim3(kSolveBlock), 0, stream,
-                           nu, x, out, n, prm->result, L, Lq, R, prm->stats);
-        if (launch_status() != BK_OK) return BK_EHIP;
-        return mark_kernel_event(prm, 1, stream) == hipSuccess ? BK_OK : BK_EHIP;
+        return launch_timed(prm, k_besselk<BK_MIXED_F32C>, dim3((unsigned)blocks), dim3(kSolveBlock), stream, nu, x,
+                            out, n, prm->result, L, Lq, prm->stats);
     case BK_LEARNED:
         return bk_besselk_learned(nu, x, out, n, prm, L, Lq, stream);
     case BK_PAPER_REFINED: {
         if (prm->bins < 0 || prm->bins > 100000 || prm->t_upper < 0.0) return BK_EINVAL;
-        const TemmeCoef* Cp = temme_coef_dev();
-        if (!Cp) return BK_EHIP;
         const int64_t b256 = (n + 255) / 256;
-        if (mark_kernel_event(prm, 0, stream) != hipSuccess) return BK_EHIP;
-        hipLaunchKernelGGL(k_besselk_paper, dim3((unsigned)b256), dim3(256), 0, stream, nu, x, out, n, prm->result,
-                           prm->bins > 0 ? prm->bins : kPaperBins, prm->t_upper > 0.0 ? prm->t_upper : kPaperT, Cp,
-                           R, prm->stats);
-        if (launch_status() != BK_OK) return BK_EHIP;
-        return mark_kernel_event(prm, 1, stream) == hipSuccess ? BK_OK : BK_EHIP;
+        return launch_timed(prm, k_besselk_paper, dim3((unsigned)b256), dim3(256), stream, nu, x, out, n,
+                            prm->result, prm->bins > 0 ? prm->bins : kPaperBins,
+                            prm->t_upper > 0.0 ? prm->t_upper : kPaperT, prm->stats);
     }
     default:
         return BK_EINVAL;
@@ -652,11 +558,7 @@ extern "C" int bk_window(const double* nu, const double* x, double* t_lo, double
     resolve_thresholds(BK_MIXED_F32C, L_window, L_quad, &L, &Lq);
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7fffffffLL) return BK_EINVAL;
-    const RuleTable* R = rule_table_dev();
-    if (!R) return BK_EHIP;
-    hipLaunchKernelGGL(k_window, dim3((unsigned)blocks), dim3(256), 0, stream, nu, x, t_lo, t_hi, nodes,
-                       n, L, Lq, R);
-    return launch_status();
+    return launch(k_window, dim3((unsigned)blocks), dim3(256), stream, nu, x, t_lo, t_hi, nodes, n, L, Lq);
 }
 
 extern "C" int64_t bk_matern_out_elems(int64_t n, int32_t tile_size, int32_t lower_only)
@@ -677,6 +579,9 @@ extern "C" int64_t bk_matern_tile_offset(int64_t n, int32_t tile_size, int32_t l
     return tile_offset(n, ts, T, lower_only ? 1 : 0, I, J);
 }
 
+// Matern tiles of the plain, mixed and paper forms: launches of at most 2^23
+// workgroups (below 2^31 work-items each); the caller's event pair, if any,
+// brackets them all.
 template <int MODE, typename OutT>
 static int launch_matern(const bk_locs* locs, const bk_params* prm, const TileGeom& g, int64_t ntiles,
                          double L, double Lq, void* out, hipStream_t stream)
@@ -684,21 +589,22 @@ static int launch_matern(const bk_locs* locs, const bk_params* prm, const TileGe
     const double nu = prm->nu;
     const double pref = (1.0 - nu) * kLn2 - lgamma(nu);
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
-    const int64_t max_wg = 1LL << 23;                      // keeps a launch below 2^31 work-items
+    const int64_t max_wg = 1LL << 23;
     const int64_t tiles_per_launch = max_wg / wg_per_tile > 0 ? max_wg / wg_per_tile : 1;
-    const RuleTable* R = rule_table_dev();
-    const TemmeCoef* Cp = temme_coef_dev();
-    if (!R || !Cp) return BK_EHIP;
+    const int bins = prm->bins > 0 ? prm->bins : kPaperBins;
+    const double T = prm->t_upper > 0.0 ? prm->t_upper : kPaperT;
+    if (mark_kernel_event(prm, 0, stream) != hipSuccess) return BK_EHIP;
     for (int64_t t0 = 0; t0 < ntiles; t0 += tiles_per_launch) {
-        int64_t nt = ntiles - t0 < tiles_per_launch ? ntiles - t0 : tiles_per_launch;
-        hipLaunchKernelGGL((k_matern<MODE, OutT>), dim3((unsigned)(nt * wg_per_tile)), dim3(256), 0, stream,
-                           locs->x, locs->y, g, t0, prm->sigma2, 1.0 / prm->beta, nu, pref, L, Lq, R,
-                           prm->bins > 0 ? prm->bins : kPaperBins, prm->t_upper > 0.0 ? prm->t_upper : kPaperT,
-                           Cp, (OutT*)out);
-        int st = launch_status();
+        const int64_t nt = ntiles - t0 < tiles_per_launch ? ntiles - t0 : tiles_per_launch;
+        const dim3 grid((unsigned)(nt * wg_per_tile));
+        const int st = prm->stats
+            ? launch(k_matern<MODE, OutT, true>, grid, dim3(256), stream, locs->x, locs->y, g, t0, prm->sigma2,
+                     1.0 / prm->beta, nu, pref, L, Lq, bins, T, (OutT*)out, prm->stats)
+            : launch(k_matern<MODE, OutT, false>, grid, dim3(256), stream, locs->x, locs->y, g, t0, prm->sigma2,
+                     1.0 / prm->beta, nu, pref, L, Lq, bins, T, (OutT*)out, prm->stats);
         if (st != BK_OK) return st;
     }
-    return BK_OK;
+    return mark_kernel_event(prm, 1, stream) == hipSuccess ? BK_OK : BK_EHIP;
 }
 
 extern "C" int bk_matern_tiles(const bk_locs* locs, const bk_params* prm, int32_t tile_size,
@@ -731,7 +637,8 @@ extern "C" int bk_matern_tiles(const bk_locs* locs, const bk_params* prm, int32_
         return f32 ? launch_matern<BK_MIXED_F32C, float>(locs, prm, g, ntiles, L, Lq, out, stream)
                    : launch_matern<BK_MIXED_F32C, double>(locs, prm, g, ntiles, L, Lq, out, stream);
     case BK_LEARNED:
-        return bk_matern_learned(locs, prm, tile_size, lower_only, out, L, Lq, stream);
+        return bk_matern_learned(locs, prm, tile_size, lower_only, out, L, Lq, prm->workspace, prm->workspace_bytes,
+                                 stream);
     case BK_PAPER_REFINED:
         if (prm->bins < 0 || prm->bins > 100000 || prm->t_upper < 0.0) return BK_EINVAL;
         return f32 ? launch_matern<BK_PAPER_REFINED, float>(locs, prm, g, ntiles, L, Lq, out, stream)
@@ -779,11 +686,8 @@ extern "C" int bk_besselk_deriv(const double* nu, const double* x, double* k, do
     resolve_thresholds(BK_PLAIN_F64, p.L_window, p.L_quad, &L, &Lq);
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7fffffffLL) return BK_EINVAL;
-    const RuleTable* R = rule_table_dev();
-    if (!R) return BK_EHIP;
-    hipLaunchKernelGGL(k_besselk_deriv, dim3((unsigned)blocks), dim3(256), 0, stream, nu, x, k, dk_dx, dk_dnu, n,
-                       p.result, L, Lq, R, p.stats);
-    return launch_status();
+    return launch(k_besselk_deriv, dim3((unsigned)blocks), dim3(256), stream, nu, x, k, dk_dx, dk_dnu, n, p.result,
+                  L, Lq, p.stats);
 }
 
 template <typename OutT>
@@ -796,14 +700,11 @@ static int launch_matern_grad(const bk_locs* locs, const bk_params* prm, const T
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
     const int64_t max_wg = 1LL << 23;
     const int64_t tiles_per_launch = max_wg / wg_per_tile > 0 ? max_wg / wg_per_tile : 1;
-    const RuleTable* R = rule_table_dev();
-    if (!R) return BK_EHIP;
     for (int64_t t0 = 0; t0 < ntiles; t0 += tiles_per_launch) {
         const int64_t nt = ntiles - t0 < tiles_per_launch ? ntiles - t0 : tiles_per_launch;
-        hipLaunchKernelGGL((k_matern_grad<OutT>), dim3((unsigned)(nt * wg_per_tile)), dim3(256), 0, stream, locs->x,
-                           locs->y, g, t0, prm->sigma2, 1.0 / prm->beta, nu, pref, psi, L, Lq, R, (OutT*)c, (OutT*)db,
-                           (OutT*)dn);
-        const int st = launch_status();
+        const int st = launch(k_matern_grad<OutT>, dim3((unsigned)(nt * wg_per_tile)), dim3(256), stream, locs->x,
+                              locs->y, g, t0, prm->sigma2, 1.0 / prm->beta, nu, pref, psi, L, Lq, (OutT*)c,
+                              (OutT*)db, (OutT*)dn);
         if (st != BK_OK) return st;
     }
     return BK_OK;

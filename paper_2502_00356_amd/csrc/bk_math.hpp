@@ -47,6 +47,40 @@ struct RuleTable {
     double tab[kTabLen];
 };
 
+// Chebyshev coefficients of Temme's Gamma1 and Gamma2 (see temme_k below).
+constexpr int kTemmeCheb = 14;
+
+struct TemmeCoef {
+    double g1[kTemmeCheb];
+    double g2[kTemmeCheb];
+};
+
+// kRuleTab and kTemmeTab: the two tables above as device constants (values made
+// by gen_tables.py at 40 digits and rounded to double), so no call sets anything
+// up on the GPU.
+#include "bk_tables.inc"
+
+// The tables as the kernels read them: through a pointer the optimiser cannot see
+// through (an empty asm statement), so that their values are fetched by scalar
+// loads from the constant segment instead of being folded into the code as
+// 64-bit literals, which costs registers (measured: spills in the Matern kernels).
+typedef __attribute__((address_space(4))) const RuleTable ConstSegRuleTable;
+typedef __attribute__((address_space(4))) const TemmeCoef ConstSegTemmeCoef;
+
+__device__ __forceinline__ const RuleTable& rule_tab()
+{
+    ConstSegRuleTable* p = (ConstSegRuleTable*)&kRuleTab;
+    __asm__ volatile("" : "+s"(p));
+    return *(const RuleTable*)p;
+}
+
+__device__ __forceinline__ const TemmeCoef& temme_tab()
+{
+    ConstSegTemmeCoef* p = (ConstSegTemmeCoef*)&kTemmeTab;
+    __asm__ volatile("" : "+s"(p));
+    return *(const TemmeCoef*)p;
+}
+
 // Per-entry quadrature plan.
 struct Plan {
     double tref;   // reference point: node mc, the node nearest the peak
@@ -129,9 +163,9 @@ __device__ __forceinline__ double log1p_tab(double p, const double* T)
 
 // The tables into LDS; every thread of the block must call it (it ends with a
 // barrier).
-__device__ __forceinline__ void stage_tab(double* s, const RuleTable* R)
+__device__ __forceinline__ void stage_tab(double* s)
 {
-    for (int j = threadIdx.x; j < kTabLen; j += blockDim.x) s[j] = R->tab[j];
+    for (int j = threadIdx.x; j < kTabLen; j += blockDim.x) s[j] = rule_tab().tab[j];
     __syncthreads();
 }
 
@@ -688,15 +722,9 @@ __device__ inline FixedOut paper_fixed(double nu, double x, int bins, double T, 
 //   Gamma2 = (1/Gamma(1-mu) + 1/Gamma(1+mu)) / 2,
 // then K_{eta+1} = (2 eta / x) K_eta + K_{eta-1} up to nu. Gamma1 and Gamma2 are
 // even entire functions of mu; they are evaluated from Chebyshev coefficients in
-// 8 mu^2 - 1, computed once on the host in long double. The series stops when a
+// 8 mu^2 - 1 (kTemmeTab). The series stops when a
 // term falls below 2^-53 of the sum (the paper caps it at 15000 terms).
 // ---------------------------------------------------------------------------
-constexpr int kTemmeCheb = 14;
-
-struct TemmeCoef {
-    double g1[kTemmeCheb];
-    double g2[kTemmeCheb];
-};
 
 __device__ __forceinline__ double cheb_eval(const double* c, double u)
 {

@@ -22,6 +22,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include "../../include/besselk.h"
+#include "bk_internal.hpp"
 
 namespace bk {
 
@@ -128,7 +129,7 @@ static HandleSlot* handle_slot(int dev)
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct MleLayout {
-    size_t S, dB, dN, a, part, res, info, total;
+    size_t S, dB, dN, a, part, res, info, mws, total;
 };
 
 static MleLayout mle_layout(int64_t n, int with_grad)
@@ -144,6 +145,7 @@ static MleLayout mle_layout(int64_t n, int with_grad)
     L.part = o; o += align256(sizeof(double) * 4 * (size_t)np);
     L.res = o; o += 256;
     L.info = o; o += 256;
+    L.mws = o; o += matern_learned_workspace_bytes(n, (int32_t)n, 0);   // for a learned-form Sigma
     L.total = o;
     return L;
 }
@@ -180,6 +182,8 @@ extern "C" int bk_matern_loglik(const bk_locs* locs, const double* z, const bk_p
     // Sigma (and its derivatives) as one full column-major n x n tile, FP64
     bk_params p = *prm;
     p.out_dtype = BK_OUT_F64;
+    p.workspace = ws + L.mws;
+    p.workspace_bytes = L.total - L.mws;
     int st = with_grad ? bk_matern_grad_tiles(locs, &p, (int32_t)n, 0, S, dB, dN, stream)
                        : bk_matern_tiles(locs, &p, (int32_t)n, 0, S, stream);
     if (st != BK_OK) return st;
@@ -202,16 +206,17 @@ extern "C" int bk_matern_loglik(const bk_locs* locs, const double* z, const bk_p
     if (rocsolver_dpotrs(h, rocblas_fill_lower, ni, 1, S, ni, a, ni) != rocblas_status_success) return BK_EHIP;
 
     const int nb = (int)((n + kRedBlock - 1) / kRedBlock < 1024 ? (n + kRedBlock - 1) / kRedBlock : 1024);
-    hipLaunchKernelGGL(k_logdiag, dim3(nb), dim3(kRedBlock), 0, stream, S, n, part);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedBlock), 0, stream, part, (int64_t)nb, 1, res + 0);
-    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kRedBlock), 0, stream, z, a, n, part);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedBlock), 0, stream, part, (int64_t)nb, 1, res + 1);
-    if (hipGetLastError() != hipSuccess) return BK_EHIP;
+    st = launch(k_logdiag, dim3(nb), dim3(kRedBlock), stream, (const double*)S, n, part);
+    if (st == BK_OK) st = launch(k_finish, dim3(1), dim3(kRedBlock), stream, (const double*)part, (int64_t)nb, 1, res + 0);
+    if (st == BK_OK) st = launch(k_dot, dim3(nb), dim3(kRedBlock), stream, z, (const double*)a, n, part);
+    if (st == BK_OK) st = launch(k_finish, dim3(1), dim3(kRedBlock), stream, (const double*)part, (int64_t)nb, 1, res + 1);
+    if (st != BK_OK) return st;
     if (with_grad) {
         if (rocsolver_dpotri(h, rocblas_fill_lower, ni, S, ni, info + 1) != rocblas_status_success) return BK_EHIP;
-        hipLaunchKernelGGL(k_grad_terms, dim3((unsigned)n), dim3(kRedBlock), 0, stream, S, dB, dN, a, n, part);
-        hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedBlock), 0, stream, part, n, 4, res + 2);
-        if (hipGetLastError() != hipSuccess) return BK_EHIP;
+        st = launch(k_grad_terms, dim3((unsigned)n), dim3(kRedBlock), stream, (const double*)S, (const double*)dB,
+                    (const double*)dN, (const double*)a, n, part);
+        if (st == BK_OK) st = launch(k_finish, dim3(1), dim3(kRedBlock), stream, (const double*)part, n, 4, res + 2);
+        if (st != BK_OK) return st;
     }
     double hres[6] = {0, 0, 0, 0, 0, 0};
     rocblas_int hinfo[2] = {0, 0};

@@ -58,10 +58,12 @@ constexpr float kTailTol = 3e-7f;
 constexpr int kTableSize = 1024;       // Matern: MLP tabulated over log10 x at fixed nu
 // Standalone K_nu: prediction cells over the training box, log10 x by nu.
 constexpr int kCellsLx = 512, kCellsNu = 64, kCells = kCellsLx * kCellsNu;
-// Matern learned launches: at most 2^21 workgroups (2^23 waves) each, so the
-// model's fallback list (one entry per wave with a rejected entry) never overflows.
-constexpr int64_t kMaternWgPerLaunch = 1LL << 21;
-constexpr int64_t kMaternWavesPerLaunch = kMaternWgPerLaunch * 4;
+// Learned Matern workspace: the window table and the interval plans of the call's
+// nu (kMaternTabBytes), then the wave bitmap (one bit per wave of the call).
+constexpr size_t kMaternTableOff = 0;                                   // kTableSize float4
+constexpr size_t kMaternPlanAOff = kMaternTableOff + 16 * kTableSize;     // (kTableSize - 1) float4
+constexpr size_t kMaternPlanBOff = kMaternPlanAOff + 16 * kTableSize;     // 3 (kTableSize - 1) double4
+constexpr size_t kMaternTabBytes = kMaternPlanBOff + 96 * kTableSize;    // 128 KiB
 
 // Device-side constants of a model for inference.
 struct MlpDev {
@@ -86,14 +88,10 @@ struct bk_model {
     float* params = nullptr;      // device FP32 master parameters [kNParam]
     half4_t* pack = nullptr;      // device FP16 operand pack (a1, a2, a3)
     float* bias = nullptr;        // device b2 (64) and b3 (3)
-    float* table = nullptr;       // device Matern window table [kTableSize][4]
-    float* mplan_a = nullptr;     // device Matern cell plans (float4 part) [kTableSize - 1]
-    double* mplan_b = nullptr;    // device Matern cell plans (three double4 parts) [kTableSize - 1][3]
     float* cells = nullptr;       // device prediction cells [kCellsLx][kCellsNu][4]
     float* plan_a = nullptr;      // device per-cell quadrature plans (float4 part)
     double* plan_b = nullptr;     // device per-cell quadrature plans (double4 part)
     double plan_Lq = -1.0;        // node target the plans were built for (< 0: none)
-    unsigned int* mlist = nullptr; // device Matern fallback list: count at [0], wave ids from [64]
     double norm[8] = {-0.5, 3.5, 5.005, 4.995, 8.0, 32.0, 0.0, 0.0};
     double box[4] = {-4.0, 3.0, 0.01, 10.0};
     double margins[4] = {0.05, 0.05, 0.05, 1.0};
@@ -586,7 +584,7 @@ template <bool kPlan>
 __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, const double* __restrict__ nu,
                                                                    const double* __restrict__ x,
                                                                    double* __restrict__ out, int64_t n, int result,
-                                                                   double Lq, const RuleTable* __restrict__ Rp,
+                                                                   double Lq, 
                                                                    unsigned int* __restrict__ qcount,
                                                                    unsigned int* __restrict__ queue,
                                                                    unsigned long long* __restrict__ stats)
@@ -604,7 +602,7 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
     double v = 0.0, z = 1.0;
     if (live) { v = fabs(nu[i]); z = x[i]; }
     if (tid < kSortBins) hist[tid] = 0u;
-    if (tid < 64) s_exp2[tid] = Rp->tab[tid];         // 2^(j/64); read after the sort's barriers
+    if (tid < 64) s_exp2[tid] = rule_tab().tab[tid];         // 2^(j/64); read after the sort's barriers
     const float lx = __log2f((float)(z > 0.0 ? z : 1.0)) * 0.30102999566f;   // log10 x in FP32
     // per-lane statistics as scalars (a dynamically indexed array would live in scratch)
     unsigned int c_range = 0, c_tail = 0, c_raised = 0, c_nonfin = 0, c_nodes = 0, c_ent = 0;
@@ -721,18 +719,18 @@ __global__ __launch_bounds__(256) void k_besselk_fallback(const double* __restri
                                                           double* __restrict__ out, int result,
                                                           const unsigned int* __restrict__ qcount,
                                                           const unsigned int* __restrict__ queue, double L, double Lq,
-                                                          const RuleTable* __restrict__ Rp,
+                                                          
                                                           unsigned long long* __restrict__ stats)
 {
     __shared__ double s_tab[kTabLen];
     const unsigned int cnt = *qcount;
     if (blockIdx.x * 256u >= cnt) return;      // the whole block has no entry (uniform)
-    stage_tab(s_tab, Rp);
+    stage_tab(s_tab);
     unsigned long long nodes = 0, ents = 0;
     for (unsigned int j = blockIdx.x * 256 + threadIdx.x; j < cnt; j += gridDim.x * 256) {
         const unsigned int i = queue[j];
         const double v = fabs(nu[i]), z = x[i];
-        Solved s = plain_solve(v, z, L, Lq, *Rp, s_tab);
+        Solved s = plain_solve(v, z, L, Lq, rule_tab(), s_tab);
         const double S = sum_mixed(v, z, s.p, s.A, s_tab);
         out[i] = assemble_k(z, s.delta, s.p.h * S, result);
         nodes += (unsigned long long)(s.p.N + 1);
@@ -778,7 +776,7 @@ __global__ __launch_bounds__(256) void k_matern_table(MlpDev M, float nu, float*
 // relative to node 0: B0 = nu m_pk h log2 e, B1 = (cosh t_pk - cosh t_lo) log2 e).
 __global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, double Lq, double pref,
                                                       const float* __restrict__ table,
-                                                      const RuleTable* __restrict__ Rp, float4_t* __restrict__ pa,
+                                                       float4_t* __restrict__ pa,
                                                       double4_t* __restrict__ pb)
 {
     const int k = blockIdx.x * 256 + threadIdx.x;
@@ -807,7 +805,7 @@ __global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, doubl
         P.c0 = cosh(tlo);
         P.c1 = cosh(tlo + P.h);
         P.kappa = 2.0 * cosh(P.h);
-        plan_for_nu(P, nu, Rp->tab);
+        plan_for_nu(P, nu, rule_tab().tab);
     }
     const double zk = exp10((double)M.lx_lo + (double)k * dlx);
     double B0 = 0.0, B1 = 0.0;
@@ -872,17 +870,30 @@ __device__ inline void tile_of_l(int64_t p, const TileGeomL& g, int64_t& I, int6
     I = J + (p - (J * T - J * (J - 1) / 2));
 }
 
-// Learned Matern. An entry the learned form rejects is written as NaN and its
-// wave is appended to the model's fallback list; k_matern_fallback then recomputes
-// the NaN entries of the listed waves with the mixed form. Keeping the fallback out
-// of this kernel keeps its registers (and so its occupancy) those of the learned pass.
-template <typename OutT>
+// Sum of a per-lane count over a wave (every lane active), added once to a global
+// counter by lane 0.
+__device__ inline void wave_count_l(unsigned long long* dst, unsigned int v)
+{
+    unsigned long long a = v;
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if ((threadIdx.x & 63) == 0 && a) atomicAdd(dst, a);
+}
+
+// Learned Matern. Wave w of the call (global workgroup index times 4 plus the wave
+// in the group) covers 64 rows of a tile column block and 8 of its columns. An
+// entry the learned form rejects is written as NaN and bit w of the call's wave
+// bitmap is set; k_matern_fallback then recomputes the NaN entries of the marked
+// waves with the mixed form. Keeping the fallback out of this kernel keeps its
+// registers (and so its occupancy) those of the learned pass. kStats: the
+// statistics variant (lanes past a ragged tile's last row stay in the wave, idle,
+// so that the wave can sum its counts).
+template <typename OutT, bool kStats>
 __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float4_t* __restrict__ plan_a,
                                                         const double4_t* __restrict__ plan_b,
                                                         const double* __restrict__ lx_, const double* __restrict__ ly_,
                                                         TileGeomL g, int64_t tile_base, double sigma2,
-                                                        double inv_beta, double nu, double pref,
-                                                        unsigned int* __restrict__ mlist, OutT* __restrict__ out)
+                                                        double inv_beta, double nu, unsigned int* __restrict__ bitmap,
+                                                        OutT* __restrict__ out, unsigned long long* __restrict__ stats)
 {
     constexpr int kColsPerWave = 8, kColsPerGroup = 32;
     // block -> (tile, row block, column block) in 32-bit arithmetic (a 64-bit
@@ -899,13 +910,16 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t il = (int64_t)rb * 64 + lane;
     const int64_t jl0 = (int64_t)cb * kColsPerGroup + (int64_t)wave * kColsPerWave;
-    if (il >= mI || jl0 >= nJ) return;
+    const bool row_ok = il < mI;
+    if (jl0 >= nJ || (!kStats && !row_ok)) return;
     const int64_t base = tile_offset_l(g.n, g.ts, g.T, g.lower, I, J);
-    const double xi = lx_[I * g.ts + il], yi = ly_[I * g.ts + il];
-    const int cend = (int)min((int64_t)kColsPerWave, nJ - jl0);
+    const int64_t ilr = row_ok ? il : 0;
+    const double xi = lx_[I * g.ts + ilr], yi = ly_[I * g.ts + ilr];
+    const int cend = (kStats && !row_ok) ? 0 : (int)min((int64_t)kColsPerWave, nJ - jl0);
     const float tscale = (float)(kTableSize - 1) / (M.lx_hi - M.lx_lo);
     const bool nu_ok = (float)nu >= M.nu_lo && (float)nu <= M.nu_hi;
     bool rejected = false;
+    unsigned int c_ent = 0, c_nodes = 0, c_range = 0, c_tail = 0, c_nonfin = 0, c_raised = 0;
     for (int c = 0; c < cend; ++c) {
         const int64_t jl = jl0 + c;
         const double dx = lx_[J * g.ts + jl] - xi, dy = ly_[J * g.ts + jl] - yi;
@@ -927,12 +941,14 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
             const double z = rr * inv_beta;
             const float lz = __log2f((float)z) * 0.30102999566f;
             bool ok = nu_ok && lz >= M.lx_lo && lz <= M.lx_hi;
+            if (kStats && !ok) c_range += 1;
             double hs = 0.0, lexp = 0.0;
             if (ok) {
                 float fpos = (lz - M.lx_lo) * tscale;
                 int k0 = min(max((int)fpos, 0), kTableSize - 2);
                 const float4_t a = plan_a[k0];
                 const int N = __float_as_int(a[2]);
+                if (kStats) c_raised += (unsigned int)(__float_as_int(a[3]) & 1);
                 if (N >= 0) {
                     const double4_t b0 = plan_b[3 * k0], b1 = plan_b[3 * k0 + 1], b2 = plan_b[3 * k0 + 2];
                     LearnedPlan P;
@@ -949,12 +965,19 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
                     const double eb = fma(-z, b2[3], b2[2]);
                     LearnedOut lo = learned_walk<true>(z, P, eb);
                     ok = lo.reason == 0;
+                    if (kStats) {
+                        c_ent += 1;
+                        c_nodes += (unsigned int)(N + 1);
+                        c_tail += lo.reason == BK_STAT_FB_TAIL ? 1u : 0u;
+                        c_nonfin += lo.reason == BK_STAT_FB_NONFINITE ? 1u : 0u;
+                    }
                     hs = lo.hs;
                     // pref + nu log z + Delta - z = K + nu log(z / z_k) - z cosh t_lo, and
                     // the walk's bias eb ln 2
                     lexp = fma(nu, log1p_small(fma(z, b2[1], -1.0)), fma(-z, P.c0, fma(eb, kLn2, b2[0])));
                 } else {
                     ok = false;
+                    if (kStats) c_nonfin += 1;
                 }
             }
             if (ok) {
@@ -968,55 +991,90 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
     }
     // lane 0 is active whenever any lane of the wave is (rows grow with the lane)
     if (__ballot(rejected) != 0ull && lane == 0) {
-        const unsigned int slot = atomicAdd(mlist, 1u);
-        mlist[64 + slot] = (unsigned int)(blockIdx.x * 4 + wave);
+        const int64_t w = ((tile_base * (int64_t)wg_per_tile + (int64_t)blockIdx.x) << 2) + wave;
+        atomicOr(bitmap + (w >> 5), 1u << (unsigned)(w & 31));
+    }
+    if (kStats) {
+        wave_count_l(stats + BK_STAT_ENTRIES, c_ent);
+        wave_count_l(stats + BK_STAT_NODES, c_nodes);
+        wave_count_l(stats + BK_STAT_FB_RANGE, c_range);
+        wave_count_l(stats + BK_STAT_FB_TAIL, c_tail);
+        wave_count_l(stats + BK_STAT_FB_NONFINITE, c_nonfin);
+        wave_count_l(stats + BK_STAT_NODE_RAISED, c_raised);
     }
 }
 
-// Fallback of the learned Matern kernel: each wave takes listed waves (grid-stride),
-// re-derives their rows and columns, and recomputes the NaN entries with the mixed
-// form (FP64 solve, FP32 node terms).
+// Fallback of the learned Matern kernel. Each wave scans 64 words of the wave
+// bitmap at a time (grid-stride), and for every marked wave re-derives its rows and
+// columns and recomputes the NaN entries with the mixed form (FP64 solve, FP32
+// node terms). The marked waves are few, so the scan is the bulk of the work.
 template <typename OutT>
 __global__ __launch_bounds__(256) void k_matern_fallback(const double* __restrict__ lx_, const double* __restrict__ ly_,
-                                                         TileGeomL g, int64_t tile_base, double sigma2,
-                                                         double inv_beta, double nu, double pref, double L, double Lq,
-                                                         const RuleTable* __restrict__ Rp,
-                                                         const unsigned int* __restrict__ mlist, OutT* __restrict__ out)
+                                                         TileGeomL g, double sigma2, double inv_beta, double nu,
+                                                         double pref, double L, double Lq,
+                                                         const unsigned int* __restrict__ bitmap, int64_t nwords,
+                                                         OutT* __restrict__ out, unsigned long long* __restrict__ stats)
 {
     constexpr int kColsPerWave = 8, kColsPerGroup = 32;
     __shared__ double s_tab[kTabLen];
-    stage_tab(s_tab, Rp);
-    const unsigned int cnt = mlist[0];
+    stage_tab(s_tab);
     const int lane = threadIdx.x & 63;
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
-    for (unsigned int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < cnt; w += gridDim.x * 4) {
-        const unsigned int id = mlist[64 + w];
-        const int64_t blk = id >> 2;
-        const int wave = (int)(id & 3u);
-        const int64_t p = tile_base + blk / wg_per_tile;
-        const int64_t local = blk % wg_per_tile;
-        const int rb = (int)(local % g.rb_per_tile), cb = (int)(local / g.rb_per_tile);
-        int64_t I, J;
-        tile_of_l(p, g, I, J);
-        const int64_t mI = min((int64_t)g.ts, g.n - I * g.ts);
-        const int64_t nJ = min((int64_t)g.ts, g.n - J * g.ts);
-        const int64_t il = (int64_t)rb * 64 + lane;
-        const int64_t jl0 = (int64_t)cb * kColsPerGroup + (int64_t)wave * kColsPerWave;
-        if (il >= mI || jl0 >= nJ) continue;
-        const int64_t base = tile_offset_l(g.n, g.ts, g.T, g.lower, I, J);
-        const double xi = lx_[I * g.ts + il], yi = ly_[I * g.ts + il];
-        const int cend = (int)min((int64_t)kColsPerWave, nJ - jl0);
-        for (int c = 0; c < cend; ++c) {
-            const int64_t o = base + il + (jl0 + c) * mI;
-            if (!isnan((double)out[o])) continue;
-            const int64_t jl = jl0 + c;
-            const double dx = lx_[J * g.ts + jl] - xi, dy = ly_[J * g.ts + jl] - yi;
-            const double z = sqrt(dx * dx + dy * dy) * inv_beta;
-            const Solved s = plain_solve(nu, z, L, Lq, *Rp, s_tab);
-            const double hs = s.p.h * sum_mixed(nu, z, s.p, s.A, s_tab);
-            out[o] = (OutT)(sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * hs);
+    unsigned int ents = 0, nodes = 0;
+    const int64_t stride = (int64_t)gridDim.x * 4 * 64;
+    for (int64_t w0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; w0 < nwords; w0 += stride) {
+        const unsigned int word = (w0 + lane < nwords) ? bitmap[w0 + lane] : 0u;
+        unsigned long long live = __ballot(word != 0u);
+        while (live) {                                   // wave-uniform loops
+            const int l = __builtin_ctzll(live);
+            live &= live - 1;
+            unsigned int bits = (unsigned int)__shfl((int)word, l, 64);
+            while (bits) {
+                const int b = __builtin_ctz(bits);
+                bits &= bits - 1;
+                const int64_t id = (w0 + l) * 32 + b;    // the marked wave
+                const int64_t blk = id >> 2;
+                const int wave = (int)(id & 3);
+                const int64_t p = blk / wg_per_tile;
+                const int64_t local = blk - p * wg_per_tile;
+                const int rb = (int)(local % g.rb_per_tile), cb = (int)(local / g.rb_per_tile);
+                int64_t I, J;
+                tile_of_l(p, g, I, J);
+                const int64_t mI = min((int64_t)g.ts, g.n - I * g.ts);
+                const int64_t nJ = min((int64_t)g.ts, g.n - J * g.ts);
+                const int64_t il = (int64_t)rb * 64 + lane;
+                const int64_t jl0 = (int64_t)cb * kColsPerGroup + (int64_t)wave * kColsPerWave;
+                if (il >= mI || jl0 >= nJ) continue;
+                const int64_t base = tile_offset_l(g.n, g.ts, g.T, g.lower, I, J);
+                const double xi = lx_[I * g.ts + il], yi = ly_[I * g.ts + il];
+                const int cend = (int)min((int64_t)kColsPerWave, nJ - jl0);
+                for (int c = 0; c < cend; ++c) {
+                    const int64_t o = base + il + (jl0 + c) * mI;
+                    if (!isnan((double)out[o])) continue;
+                    const int64_t jl = jl0 + c;
+                    const double dx = lx_[J * g.ts + jl] - xi, dy = ly_[J * g.ts + jl] - yi;
+                    const double z = sqrt(dx * dx + dy * dy) * inv_beta;
+                    const Solved s = plain_solve(nu, z, L, Lq, rule_tab(), s_tab);
+                    const double hs = s.p.h * sum_mixed(nu, z, s.p, s.A, s_tab);
+                    out[o] = (OutT)(sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * hs);
+                    ents += 1;
+                    nodes += (unsigned int)(s.p.N + 1);
+                }
+            }
         }
     }
+    if (stats) {
+        wave_count_l(stats + BK_STAT_ENTRIES, ents);
+        wave_count_l(stats + BK_STAT_NODES, nodes);
+        wave_count_l(stats + BK_STAT_FB_NODES, nodes);
+    }
+}
+
+// Clears n 32-bit words (a fill kernel rather than a memset node, so that a
+// captured graph replays it correctly).
+__global__ __launch_bounds__(256) void k_fill_u32(unsigned int* __restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1219,21 +1277,35 @@ static void pack_weights(const float* P, std::vector<_Float16>& pack, std::vecto
     for (int o = 0; o < 3; ++o) bias[64 + o] = P[kOffB3 + o];
 }
 
+static void model_free(bk_model* m)
+{
+    void* bufs[] = {m->params, m->pack, m->bias, m->cells, m->plan_a, m->plan_b};
+    for (void* q : bufs)
+        if (q) (void)hipFree(q);
+    m->params = nullptr;
+    m->pack = nullptr;
+    m->bias = nullptr;
+    m->cells = nullptr;
+    m->plan_a = nullptr;
+    m->plan_b = nullptr;
+}
+
+// Device buffers of a model; on any failure everything is released again, so a
+// model is either fully allocated or holds nothing.
 static int model_alloc(bk_model* m)
 {
     if (m->params) return BK_OK;
     if (hipGetDevice(&m->device) != hipSuccess) return BK_EHIP;
-    if (hipMalloc((void**)&m->params, sizeof(float) * kNParam) != hipSuccess) return BK_ENOMEM;
-    if (hipMalloc((void**)&m->pack, sizeof(_Float16) * 24 * 64 * 4) != hipSuccess) return BK_ENOMEM;
-    if (hipMalloc((void**)&m->bias, sizeof(float) * 68) != hipSuccess) return BK_ENOMEM;
-    if (hipMalloc((void**)&m->table, sizeof(float) * 4 * kTableSize) != hipSuccess) return BK_ENOMEM;
-    if (hipMalloc((void**)&m->mplan_a, sizeof(float) * 4 * kTableSize) != hipSuccess) return BK_ENOMEM;
-    if (hipMalloc((void**)&m->mplan_b, sizeof(double) * 12 * kTableSize) != hipSuccess) return BK_ENOMEM;
-    if (hipMalloc((void**)&m->cells, sizeof(float) * 4 * kCells) != hipSuccess) return BK_ENOMEM;
-    if (hipMalloc((void**)&m->plan_a, sizeof(float) * 4 * kCells) != hipSuccess) return BK_ENOMEM;
-    if (hipMalloc((void**)&m->plan_b, sizeof(double) * 4 * kCells) != hipSuccess) return BK_ENOMEM;
-    if (hipMalloc((void**)&m->mlist, sizeof(unsigned int) * (64 + (size_t)kMaternWavesPerLaunch)) != hipSuccess)
+    const bool ok = hipMalloc((void**)&m->params, sizeof(float) * kNParam) == hipSuccess &&
+                    hipMalloc((void**)&m->pack, sizeof(_Float16) * 24 * 64 * 4) == hipSuccess &&
+                    hipMalloc((void**)&m->bias, sizeof(float) * 68) == hipSuccess &&
+                    hipMalloc((void**)&m->cells, sizeof(float) * 4 * kCells) == hipSuccess &&
+                    hipMalloc((void**)&m->plan_a, sizeof(float) * 4 * kCells) == hipSuccess &&
+                    hipMalloc((void**)&m->plan_b, sizeof(double) * 4 * kCells) == hipSuccess;
+    if (!ok) {
+        model_free(m);
         return BK_ENOMEM;
+    }
     return BK_OK;
 }
 
@@ -1244,13 +1316,13 @@ static int model_cells(bk_model* m)
 {
     if (!m->params) return BK_OK;
     m->plan_Lq = -1.0;
-    hipLaunchKernelGGL(k_cell_table, dim3((kCells + 255) / 256), dim3(256), 0, nullptr, make_dev(m),
-                       reinterpret_cast<float4_t*>(m->cells));
-    hipLaunchKernelGGL(k_cell_plans, dim3((kCells + 255) / 256), dim3(256), 0, nullptr, make_dev(m),
-                       kDefaultLqMixed, reinterpret_cast<float4_t*>(m->plan_a),
-                       reinterpret_cast<double4_t*>(m->plan_b));
-    if (hipGetLastError() != hipSuccess) return BK_EHIP;
-    const int st = hip_ok(hipStreamSynchronize(nullptr));
+    int st = launch(k_cell_table, dim3((kCells + 255) / 256), dim3(256), nullptr, make_dev(m),
+                    reinterpret_cast<float4_t*>(m->cells));
+    if (st == BK_OK)
+        st = launch(k_cell_plans, dim3((kCells + 255) / 256), dim3(256), nullptr, make_dev(m), kDefaultLqMixed,
+                    reinterpret_cast<float4_t*>(m->plan_a), reinterpret_cast<double4_t*>(m->plan_b));
+    if (st != BK_OK) return st;
+    st = hip_ok(hipStreamSynchronize(nullptr));
     if (st == BK_OK) m->plan_Lq = kDefaultLqMixed;
     return st;
 }
@@ -1277,9 +1349,9 @@ static int launch_grad(const float* params, const float* u, const float* tgt, co
                        hipStream_t s)
 {
     const unsigned blocks = (unsigned)((B + 255) / 256);
-    hipLaunchKernelGGL(k_fwd_bwd, dim3(blocks), dim3(256), 0, s, params, u, tgt, tau, B, n, pa, pb, start, scr, loss);
-    hipLaunchKernelGGL(k_wgrad, dim3(kNParam), dim3(256), 0, s, scr, B, grad);
-    return hipGetLastError() == hipSuccess ? BK_OK : BK_EHIP;
+    const int st = launch(k_fwd_bwd, dim3(blocks), dim3(256), s, params, u, tgt, tau, B, n, pa, pb, start, scr, loss);
+    if (st != BK_OK) return st;
+    return launch(k_wgrad, dim3(kNParam), dim3(256), s, scr, B, grad);
 }
 
 }  // namespace bk
@@ -1301,38 +1373,47 @@ int bk_besselk_learned(const double* nu, const double* x, double* out, int64_t n
     unsigned int* qcount = (unsigned int*)prm->workspace;
     unsigned int* queue = (unsigned int*)((char*)prm->workspace + 256);
     const MlpDev M = make_dev(m);
-    const RuleTable* R = rule_table_dev();
-    if (!R) return BK_EHIP;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, qcount);
+    int st = launch(k_zero_u32, dim3(1), dim3(64), stream, qcount);
+    if (st != BK_OK) return st;
     const unsigned blocks = (unsigned)((n + kLearnedBlock - 1) / kLearnedBlock);
     if (mark_kernel_event(prm, 0, stream) != hipSuccess) return BK_EHIP;
-    if (m->plan_Lq == Lq)
-        hipLaunchKernelGGL(k_besselk_learned<true>, dim3(blocks), dim3(kLearnedBlock), 0, stream, M, nu, x, out, n,
-                           prm->result, Lq, R, qcount, queue, prm->stats);
-    else
-        hipLaunchKernelGGL(k_besselk_learned<false>, dim3(blocks), dim3(kLearnedBlock), 0, stream, M, nu, x, out, n,
-                           prm->result, Lq, R, qcount, queue, prm->stats);
-    if (hipGetLastError() != hipSuccess || mark_kernel_event(prm, 1, stream) != hipSuccess) return BK_EHIP;
-    hipLaunchKernelGGL(k_besselk_fallback, dim3(1024), dim3(256), 0, stream, nu, x, out, prm->result, qcount, queue, L,
-                       Lq, R, prm->stats);
-    return hipGetLastError() == hipSuccess ? BK_OK : BK_EHIP;
+    st = (m->plan_Lq == Lq)
+        ? launch(k_besselk_learned<true>, dim3(blocks), dim3(kLearnedBlock), stream, M, nu, x, out, n, prm->result,
+                 Lq, qcount, queue, prm->stats)
+        : launch(k_besselk_learned<false>, dim3(blocks), dim3(kLearnedBlock), stream, M, nu, x, out, n, prm->result,
+                 Lq, qcount, queue, prm->stats);
+    if (st != BK_OK) return st;
+    if (mark_kernel_event(prm, 1, stream) != hipSuccess) return BK_EHIP;
+    return launch(k_besselk_fallback, dim3(1024), dim3(256), stream, nu, x, out, prm->result, qcount, queue, L, Lq,
+                  prm->stats);
+}
+
+size_t matern_learned_workspace_bytes(int64_t n, int32_t tile_size, int32_t lower_only)
+{
+    if (n <= 0 || tile_size <= 0) return 0;
+    const int64_t T = (n + tile_size - 1) / tile_size;
+    const int64_t ntiles = lower_only ? T * (T + 1) / 2 : T * T;
+    const int64_t wg_per_tile = (int64_t)((tile_size + 63) / 64) * ((tile_size + 31) / 32);
+    const int64_t words = (ntiles * wg_per_tile * 4 + 31) / 32;
+    return kMaternTabBytes + (((size_t)words * 4 + 255) & ~(size_t)255);
 }
 
 int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_size, int32_t lower_only, void* out,
-                      double L, double Lq, hipStream_t stream)
+                      double L, double Lq, void* workspace, size_t workspace_bytes, hipStream_t stream)
 {
     const bk_model* m = prm->model;
     if (!m || !m->params || !m->trained) return BK_ENOMODEL;
+    const size_t need = matern_learned_workspace_bytes(locs->n, tile_size, lower_only);
+    if (!workspace || workspace_bytes < need) return BK_ENOMEM;
+    char* ws = (char*)workspace;
+    float* table = (float*)(ws + kMaternTableOff);
+    float4_t* plan_a = (float4_t*)(ws + kMaternPlanAOff);
+    double4_t* plan_b = (double4_t*)(ws + kMaternPlanBOff);
+    unsigned int* bitmap = (unsigned int*)(ws + kMaternTabBytes);
+    const int64_t nwords = (int64_t)((need - kMaternTabBytes) / 4);
     const MlpDev M = make_dev(m);
-    const RuleTable* R = rule_table_dev();
-    if (!R) return BK_EHIP;
     const double nu = prm->nu;
     const double pref = (1.0 - nu) * kLn2 - lgamma(nu);
-    hipLaunchKernelGGL(k_matern_table, dim3((kTableSize + 255) / 256), dim3(256), 0, stream, M, (float)prm->nu,
-                       m->table);
-    hipLaunchKernelGGL(k_matern_plans, dim3((kTableSize + 254) / 256), dim3(256), 0, stream, M, prm->nu, Lq, pref,
-                       m->table, R, reinterpret_cast<float4_t*>(m->mplan_a),
-                       reinterpret_cast<double4_t*>(m->mplan_b));
     TileGeomL g;
     g.n = locs->n;
     g.ts = tile_size;
@@ -1343,31 +1424,42 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
     const int64_t T = g.T;
     const int64_t ntiles = g.lower ? T * (T + 1) / 2 : T * T;
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
-    const int64_t tiles_per_launch = kMaternWgPerLaunch / wg_per_tile > 0 ? kMaternWgPerLaunch / wg_per_tile : 1;
-    if (wg_per_tile > kMaternWgPerLaunch) return BK_EINVAL;   // a tile side beyond 2^14 rows / 2^12 column blocks
+    const int64_t max_wg = 1LL << 23;                      // keeps a launch below 2^31 work-items
+    const int64_t tiles_per_launch = max_wg / wg_per_tile > 0 ? max_wg / wg_per_tile : 1;
     const double ib = 1.0 / prm->beta;
+    int st = launch(k_matern_table, dim3((kTableSize + 255) / 256), dim3(256), stream, M, (float)nu, table);
+    if (st == BK_OK)
+        st = launch(k_matern_plans, dim3((kTableSize + 254) / 256), dim3(256), stream, M, nu, Lq, pref,
+                    (const float*)table, plan_a, plan_b);
+    if (st == BK_OK)
+        st = launch(k_fill_u32, dim3((unsigned)std::min<int64_t>((nwords + 255) / 256, 4096)), dim3(256), stream,
+                    bitmap, nwords);
+    if (st != BK_OK) return st;
+    if (mark_kernel_event(prm, 0, stream) != hipSuccess) return BK_EHIP;
+    const bool f32 = prm->out_dtype == BK_OUT_F32;
     for (int64_t t0 = 0; t0 < ntiles; t0 += tiles_per_launch) {
         const int64_t nt = ntiles - t0 < tiles_per_launch ? ntiles - t0 : tiles_per_launch;
         const dim3 grid((unsigned)(nt * wg_per_tile));
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, m->mlist);
-        if (prm->out_dtype == BK_OUT_F32) {
-            hipLaunchKernelGGL(k_matern_learned<float>, grid, dim3(256), 0, stream, M,
-                               reinterpret_cast<const float4_t*>(m->mplan_a),
-                               reinterpret_cast<const double4_t*>(m->mplan_b), locs->x, locs->y, g,
-                               t0, prm->sigma2, ib, nu, pref, m->mlist, (float*)out);
-            hipLaunchKernelGGL(k_matern_fallback<float>, dim3(1024), dim3(256), 0, stream, locs->x, locs->y, g, t0,
-                               prm->sigma2, ib, nu, pref, L, Lq, R, m->mlist, (float*)out);
-        } else {
-            hipLaunchKernelGGL(k_matern_learned<double>, grid, dim3(256), 0, stream, M,
-                               reinterpret_cast<const float4_t*>(m->mplan_a),
-                               reinterpret_cast<const double4_t*>(m->mplan_b), locs->x, locs->y, g,
-                               t0, prm->sigma2, ib, nu, pref, m->mlist, (double*)out);
-            hipLaunchKernelGGL(k_matern_fallback<double>, dim3(1024), dim3(256), 0, stream, locs->x, locs->y, g, t0,
-                               prm->sigma2, ib, nu, pref, L, Lq, R, m->mlist, (double*)out);
-        }
-        if (hipGetLastError() != hipSuccess) return BK_EHIP;
+        const float4_t* pa = plan_a;
+        const double4_t* pb = plan_b;
+        if (f32)
+            st = prm->stats ? launch(k_matern_learned<float, true>, grid, dim3(256), stream, M, pa, pb, locs->x,
+                                     locs->y, g, t0, prm->sigma2, ib, nu, bitmap, (float*)out, prm->stats)
+                            : launch(k_matern_learned<float, false>, grid, dim3(256), stream, M, pa, pb, locs->x,
+                                     locs->y, g, t0, prm->sigma2, ib, nu, bitmap, (float*)out, prm->stats);
+        else
+            st = prm->stats ? launch(k_matern_learned<double, true>, grid, dim3(256), stream, M, pa, pb, locs->x,
+                                     locs->y, g, t0, prm->sigma2, ib, nu, bitmap, (double*)out, prm->stats)
+                            : launch(k_matern_learned<double, false>, grid, dim3(256), stream, M, pa, pb, locs->x,
+                                     locs->y, g, t0, prm->sigma2, ib, nu, bitmap, (double*)out, prm->stats);
+        if (st != BK_OK) return st;
     }
-    return BK_OK;
+    if (mark_kernel_event(prm, 1, stream) != hipSuccess) return BK_EHIP;
+    const dim3 fgrid((unsigned)std::min<int64_t>((nwords + 255) / 256, 1024));
+    return f32 ? launch(k_matern_fallback<float>, fgrid, dim3(256), stream, locs->x, locs->y, g, prm->sigma2, ib, nu,
+                        pref, L, Lq, (const unsigned int*)bitmap, nwords, (float*)out, prm->stats)
+               : launch(k_matern_fallback<double>, fgrid, dim3(256), stream, locs->x, locs->y, g, prm->sigma2, ib,
+                        nu, pref, L, Lq, (const unsigned int*)bitmap, nwords, (double*)out, prm->stats);
 }
 
 }  // namespace bk
@@ -1380,6 +1472,11 @@ extern "C" size_t bk_workspace_bytes(int64_t n)
     return 256 + (size_t)(n > 0 ? n : 0) * sizeof(unsigned int);
 }
 
+extern "C" size_t bk_matern_workspace_bytes(int64_t n, int32_t tile_size, int32_t lower_only)
+{
+    return matern_learned_workspace_bytes(n, tile_size, lower_only);
+}
+
 extern "C" int bk_model_create(bk_model** m)
 {
     if (!m) return BK_EINVAL;
@@ -1390,16 +1487,7 @@ extern "C" int bk_model_create(bk_model** m)
 extern "C" void bk_model_destroy(bk_model* m)
 {
     if (!m) return;
-    if (m->params) (void)hipFree(m->params);
-    if (m->pack) (void)hipFree(m->pack);
-    if (m->bias) (void)hipFree(m->bias);
-    if (m->table) (void)hipFree(m->table);
-    if (m->mplan_a) (void)hipFree(m->mplan_a);
-    if (m->mplan_b) (void)hipFree(m->mplan_b);
-    if (m->cells) (void)hipFree(m->cells);
-    if (m->plan_a) (void)hipFree(m->plan_a);
-    if (m->plan_b) (void)hipFree(m->plan_b);
-    if (m->mlist) (void)hipFree(m->mlist);
+    model_free(m);
     delete m;
 }
 
@@ -1522,8 +1610,7 @@ extern "C" int bk_mlp_infer(const bk_model* m, const float* u, float* y, int64_t
     if (n == 0) return BK_OK;
     if (!u || !y) return BK_EINVAL;
     if (!m->params) return BK_ENOMODEL;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, make_dev(m), u, y, n);
-    return hipGetLastError() == hipSuccess ? BK_OK : BK_EHIP;
+    return launch(k_mlp_infer, dim3((unsigned)((n + 255) / 256)), dim3(256), s, make_dev(m), u, y, n);
 }
 
 extern "C" size_t bk_mlp_grad_scratch_bytes(int64_t B)
@@ -1536,7 +1623,8 @@ extern "C" int bk_mlp_grad(const float* params, const float* u, const float* tgt
 {
     if (!params || !u || !tgt || !tau || !grad || !loss || !scratch || B <= 0 || B > (1 << 20)) return BK_EINVAL;
     if (scratch_bytes < bk_mlp_grad_scratch_bytes(B)) return BK_ENOMEM;
-    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, s, loss, (int64_t)1);
+    const int st = launch(k_zero_f32, dim3(1), dim3(256), s, loss, (int64_t)1);
+    if (st != BK_OK) return st;
     return launch_grad(params, u, tgt, tau, B, 0, 1, 0, 0, grad, loss, (float*)scratch, s);
 }
 
@@ -1548,9 +1636,8 @@ extern "C" int bk_adam_step(float* p, const float* g, float* m, float* v, int64_
         return BK_EINVAL;
     if (n == 0) return BK_OK;
     const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n, lr, beta1, beta2,
-                       eps, c1, c2);
-    return hipGetLastError() == hipSuccess ? BK_OK : BK_EHIP;
+    return launch(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), s, p, g, m, v, n, lr, beta1, beta2, eps, c1,
+                  c2);
 }
 
 static uint64_t gcd_u64(uint64_t a, uint64_t b)
@@ -1596,8 +1683,8 @@ extern "C" int bk_model_train(bk_model* m, const double* nu, const double* x, in
     const float cx = (float)m->norm[0], sx = (float)m->norm[1], cnu = (float)m->norm[2], snu = (float)m->norm[3];
     const float stn = (float)m->norm[4], snn = (float)m->norm[5];
     if (st == BK_OK)
-        hipLaunchKernelGGL(k_make_targets, dim3(nb), dim3(256), 0, s, nu, x, tlo, thi, nodes, n, cx, sx, cnu, snu, stn,
-                           snn, U, T);
+        st = launch(k_make_targets, dim3(nb), dim3(256), s, (const double*)nu, (const double*)x, (const double*)tlo,
+                    (const double*)thi, (const int32_t*)nodes, n, cx, sx, cnu, snu, stn, snn, U, T);
     // training box = range of the data
     {
         std::vector<double> hx(n), hn(n);
@@ -1648,7 +1735,7 @@ extern "C" int bk_model_train(bk_model* m, const double* nu, const double* x, in
         uint64_t pa = prng() % (uint64_t)n;
         while (pa == 0 || gcd_u64(pa, (uint64_t)n) != 1) pa = prng() % (uint64_t)n;
         const uint64_t pb = prng() % (uint64_t)n;
-        hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, s, loss, (int64_t)1);
+        st = launch(k_zero_f32, dim3(1), dim3(256), s, loss, (int64_t)1);
         for (int64_t b0 = 0; b0 < n && st == BK_OK; b0 += B) {
             const int64_t bs = std::min(B, n - b0);
             ++step;
@@ -1675,10 +1762,10 @@ extern "C" int bk_model_train(bk_model* m, const double* nu, const double* x, in
         if (st == BK_OK) st = model_upload(m, P.data());
     }
     if (st == BK_OK) {
-        hipLaunchKernelGGL(k_residuals, dim3(nb), dim3(256), 0, s, make_dev(m), U, T, n, res);
+        st = launch(k_residuals, dim3(nb), dim3(256), s, make_dev(m), (const float*)U, (const float*)T, n, res);
         std::vector<float> hr(3 * n);
-        if (hipMemcpyAsync(hr.data(), res, 12 * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
+        if (st == BK_OK && (hipMemcpyAsync(hr.data(), res, 12 * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                            hipStreamSynchronize(s) != hipSuccess))
             st = BK_EHIP;
         if (st == BK_OK) {
             // Window margins: the 99.8% quantile of the inference-path residuals

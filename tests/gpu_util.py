@@ -17,6 +17,20 @@ def rel_err(got, ref):
     return e
 
 
+def k_result_err_ok(got, kref, tol):
+    """Element-wise check of a K output (BK_RESULT_K) against the oracle's K: relative
+    error <= tol where K is a normal double; where it underflows (x beyond ~708) both
+    sides round once into the subnormal range, so |got - ref| <= tol ref + 2^-1074
+    (one subnormal unit), which also holds for K = 0 past x ~ 745."""
+    got = np.asarray(got, np.float64)
+    kref = np.asarray(kref, np.float64)
+    ok = np.empty(kref.shape, bool)
+    nrm = kref >= DBL_MIN
+    ok[nrm] = rel_err(got[nrm], kref[nrm]) <= tol
+    ok[~nrm] = np.abs(got[~nrm] - kref[~nrm]) <= tol * kref[~nrm] + 2.0 ** -1074
+    return ok
+
+
 def re_metric(logk_got, logk_ref):
     """RE = log10(1 + |log K_ref - log K| / 2^-52), the accuracy metric of Sec. IV-C."""
     return np.log10(1.0 + np.abs(np.asarray(logk_got) - np.asarray(logk_ref)) / 2.0 ** -52)

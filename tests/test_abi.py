@@ -190,3 +190,50 @@ def test_struct_layouts_match_the_header(tmp_path):
         want.append(ctypes.sizeof(cls))
         want.extend(getattr(cls, f).offset for f, _ in cls._fields_)
     assert got == want
+
+
+def test_binding_rejects_bad_caller_buffers():
+    """Every caller buffer is checked for dtype, contiguity, size and device before
+    its pointer reaches the library (these checks run without a GPU: the device test
+    comes last, so each case below raises on the property it breaks)."""
+    import torch
+    from paper_2502_00356_amd import api
+    f64 = torch.zeros(8, dtype=torch.float64)
+    with pytest.raises(ValueError, match="device"):          # host tensors
+        api.besselk(f64, f64, out=f64.clone())
+    with pytest.raises(ValueError, match="float64"):         # an FP32 buffer for FP64 output
+        api.besselk_deriv(f64, f64, want=("k",), out={"k": torch.zeros(8, dtype=torch.float32)})
+    with pytest.raises(ValueError, match="needed"):          # too short for the outputs
+        api.besselk_deriv(f64, f64, want=("dx",), out={"dx": torch.zeros(4, dtype=torch.float64)})
+    with pytest.raises(ValueError, match="needed"):          # statistics array shorter than STATS_LEN
+        api.besselk(f64, f64, out=f64.clone(), stats=torch.zeros(4, dtype=torch.int64))
+    with pytest.raises(ValueError, match="int64"):
+        api.besselk(f64, f64, out=f64.clone(), stats=torch.zeros(8, dtype=torch.int32))
+    with pytest.raises(ValueError, match="contiguous"):
+        api.besselk(f64, f64, out=torch.zeros(16, dtype=torch.float64)[::2])
+    with pytest.raises(ValueError, match="needed"):          # learned workspace too small
+        api.besselk(f64, f64, out=f64.clone(), mode="learned", workspace=torch.zeros(16, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="float32"):         # Matern output of the wrong element type
+        api.matern_tiles(f64, f64, 1.0, 0.1, 1.0, 8, 1, out_dtype=api.OUT_F32, out=torch.zeros(64, dtype=torch.float64))
+    with pytest.raises(ValueError, match="needed"):
+        api.matern_tiles(f64, f64, 1.0, 0.1, 1.0, 8, 1, out=torch.zeros(10, dtype=torch.float64))
+    with pytest.raises(ValueError, match="needed"):
+        api.matern_tiles(f64, f64, 1.0, 0.1, 1.0, 4, 1, mode="learned", out=torch.zeros(64, dtype=torch.float64),
+                         workspace=torch.zeros(64, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="needed"):
+        api.matern_grad_tiles(f64, f64, 1.0, 0.1, 1.0, 8, 1, want=("c",), out={"c": torch.zeros(10, dtype=torch.float64)})
+    with pytest.raises(ValueError, match="needed"):
+        api.adam_step(torch.zeros(8), torch.zeros(4), torch.zeros(8), torch.zeros(8), 1, 1e-3)
+
+
+def test_matern_workspace_size():
+    """Learned Matern workspace: 128 KiB of tables plus one bit per wave of 512
+    entries, in 256-byte units."""
+    from paper_2502_00356_amd import api
+    assert api.matern_workspace_bytes(0, 64, 1) == 0
+    assert api.matern_workspace_bytes(10, 0, 1) == 0
+    # n = 1024 full matrix in one 1024-tile: 16 x 32 workgroups of 4 waves = 2048 bits = 256 bytes
+    assert api.matern_workspace_bytes(1024, 1024, 0) == 131072 + 256
+    # 316^2 grid, lower 1024-tiles: 98 tile rows, 4851 tiles of 16 x 32 workgroups
+    waves = 4851 * 16 * 32 * 4
+    assert api.matern_workspace_bytes(99856, 1024, 1) == 131072 + ((waves + 31) // 32 * 4 + 255) // 256 * 256

@@ -4,7 +4,7 @@ subsets), plus properties that hold at any size."""
 import numpy as np
 import pytest
 
-from gpu_util import DBL_MIN, TOL_MIXED, TOL_PLAIN, rel_err, to_dev
+from gpu_util import DBL_MIN, TOL_MIXED, TOL_PLAIN, k_result_err_ok, rel_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -126,9 +126,17 @@ def test_grid_full_size_per_region(api, orc, model):
     dnu, dx = to_dev(nu), to_dev(x)
     rng = np.random.default_rng(23)
     s = np.unique(np.concatenate([rng.choice(nu.size, 1 << 16, replace=False), hidx[:4096]]))
-    _, _, ks = orc.besselk(nu[s], x[s])
+    kref, _, ks = orc.besselk(nu[s], x[s])
     sel = torch.from_numpy(s).cuda()
+    assert (x[s] > 708).sum() > 500 and (kref == 0).sum() > 100     # the sample reaches the underflow zone
     for mode, tol in (("plain", TOL_PLAIN), ("mixed", TOL_MIXED), ("learned", TOL_MIXED)):
+        # K itself (the output the benchmark times), element by element, including
+        # the subnormal zone
+        outk = api.besselk(dnu, dx, mode=mode, model=model, result=api.RESULT_K)
+        torch.cuda.synchronize()
+        okk = k_result_err_ok(outk[sel].cpu().numpy(), kref, tol)
+        assert okk.all(), (mode, int((~okk).sum()))
+        del outk
         out = api.besselk(dnu, dx, mode=mode, model=model, result=api.RESULT_SCALED)
         torch.cuda.synchronize()
         got = out[sel].cpu().numpy()
@@ -160,9 +168,13 @@ def test_learned_eval_set_and_probe(api, orc, model):
         fb, nu.size, st[api.STAT_FB_RANGE], st[api.STAT_FB_TAIL], st[api.STAT_FB_NONFINITE],
         st[api.STAT_NODE_RAISED]))
     s = np.random.default_rng(29).choice(nu.size, 1 << 16, replace=False)
-    _, _, ks = orc.besselk(nu[s], x[s])
+    kref, _, ks = orc.besselk(nu[s], x[s])
     assert rel_err(out.cpu().numpy()[s], ks).max() <= TOL_MIXED
     assert fb < 1e-3 * nu.size
+    outk = api.besselk(to_dev(nu), to_dev(x), mode="learned", model=model, result=api.RESULT_K)
+    torch.cuda.synchronize()
+    assert k_result_err_ok(outk.cpu().numpy()[s], kref, TOL_MIXED).all()
+    del outk
     pn, px = w.out_of_range_pairs(1 << 16, seed=6)
     stats.zero_()
     out = api.besselk(to_dev(pn), to_dev(px), mode="learned", model=model, result=api.RESULT_SCALED, stats=stats)

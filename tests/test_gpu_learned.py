@@ -380,3 +380,92 @@ def test_learned_kernel_events(api, trained):
     np.testing.assert_array_equal(got.cpu().numpy(), ref.cpu().numpy())
     t_k, t_all = ev[0].elapsed_time(ev[1]), outer[0].elapsed_time(outer[1])
     assert 0.0 < t_k <= t_all, (t_k, t_all)
+
+
+def test_two_streams_share_one_model(api, orc, trained):
+    """The learned forms only read the model: Matern tiles at two orders and K_nu on
+    two streams at once, each with its own workspace, give the oracle's values and
+    the same bits as one call at a time."""
+    import torch
+    from paper_2502_00356_amd import workloads as w
+    xy = w.uniform_locations(700, seed=61)
+    lx, ly = to_dev(xy[:, 0]), to_dev(xy[:, 1])
+    nu_s, x_s, _ = w.grid_pairs(1 << 16, seed=62)
+    dnu, dx = to_dev(nu_s), to_dev(x_s)
+    cases = ((0.8, 0.05), (3.7, 0.02))
+    seq = [api.matern_tiles(lx, ly, 1.0, b, v, 256, 1, mode="learned", model=trained) for v, b in cases]
+    kseq = api.besselk(dnu, dx, mode="learned", model=trained)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [torch.full_like(s, -1.0) for s in seq]
+    kout = torch.empty_like(kseq)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-1.0)
+        kout.fill_(-1.0)
+        torch.cuda.synchronize()
+        for k, ((v, b), st) in enumerate(zip(cases, streams)):
+            with torch.cuda.stream(st):
+                api.matern_tiles(lx, ly, 1.0, b, v, 256, 1, mode="learned", model=trained, out=outs[k])
+                if k == 1:
+                    api.besselk(dnu, dx, mode="learned", model=trained, out=kout)
+        torch.cuda.synchronize()
+        for k in range(2):
+            assert torch.equal(outs[k], seq[k]), (rep, k)
+        assert torch.equal(kout, kseq), rep
+    for (v, b), o in zip(cases, outs):
+        A = api.unpack_tiles(o, 700, 256, 1).numpy()
+        R = orc.matern_full(xy, 1.0, b, v)
+        m = R > 1e-300
+        assert rel_err(A[m], R[m]).max() <= TOL_MIXED, v
+
+
+def test_learned_matern_counting_variant(api, orc, trained):
+    """A call with statistics runs the counting variant of the learned Matern
+    kernels: the same bits as without, and counts that add up (one quadrature per
+    stored entry at nonzero distance, in range of the model)."""
+    import torch
+    from paper_2502_00356_amd import workloads as w
+    n, ts = 333, 128                       # ragged last tile row
+    xy = w.uniform_locations(n, seed=63)
+    lx, ly = to_dev(xy[:, 0]), to_dev(xy[:, 1])
+    ref = api.matern_tiles(lx, ly, 1.0, 0.03, 2.3, ts, 1, mode="learned", model=trained)
+    stats = torch.zeros(api.STATS_LEN, dtype=torch.int64, device="cuda")
+    got = api.matern_tiles(lx, ly, 1.0, 0.03, 2.3, ts, 1, mode="learned", model=trained, stats=stats)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    st = stats.cpu().numpy()
+    stored = api.matern_out_elems(n, ts, 1)
+    zero_dist = n                          # the diagonal (the points are distinct)
+    fb = int(st[api.STAT_FB_RANGE] + st[api.STAT_FB_TAIL] + st[api.STAT_FB_NONFINITE])
+    # every nonzero-distance entry is either out of the box or walked (and some walks
+    # are rejected); rejected entries are walked again by the fallback
+    assert int(st[api.STAT_ENTRIES]) - fb + int(st[api.STAT_FB_RANGE]) == stored - zero_dist
+    assert int(st[api.STAT_NODES]) >= 5 * int(st[api.STAT_ENTRIES])
+    assert 0 <= int(st[api.STAT_FB_NODES]) <= int(st[api.STAT_NODES])
+    A = api.unpack_tiles(got, n, ts, 1).numpy()
+    R = orc.matern_full(xy, 1.0, 0.03, 2.3)
+    m = R > 1e-300
+    assert rel_err(A[m], R[m]).max() <= TOL_MIXED
+
+
+def test_learned_matern_kernel_events(api, trained):
+    """The optional event pair brackets the learned Matern main launches (table,
+    plans, bitmap reset and fallback fall outside)."""
+    import torch
+    from paper_2502_00356_amd import workloads as w
+    xy = w.uniform_locations(2000, seed=64)
+    lx, ly = to_dev(xy[:, 0]), to_dev(xy[:, 1])
+    ref = api.matern_tiles(lx, ly, 1.0, 0.05, 1.5, 512, 1, mode="learned", model=trained)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    outer = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    for e in ev + outer:
+        e.record()
+    torch.cuda.synchronize()
+    outer[0].record()
+    got = api.matern_tiles(lx, ly, 1.0, 0.05, 1.5, 512, 1, mode="learned", model=trained, kernel_events=ev)
+    outer[1].record()
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    t_k, t_all = ev[0].elapsed_time(ev[1]), outer[0].elapsed_time(outer[1])
+    assert 0.0 < t_k <= t_all, (t_k, t_all)

@@ -105,3 +105,42 @@ def test_invalid_parameters(api):
             api.matern_tiles(a, a, kw["sigma2"], kw["beta"], kw["nu"], 2, 1)
     with pytest.raises(api.BkError):
         api.matern_tiles(a, a, 1.0, 0.1, 1.0, 0, 1)
+
+
+@pytest.mark.parametrize("mode", ["plain", "mixed"])
+def test_counting_variant(api, orc, mode):
+    """A call with statistics runs the counting variant of the Matern kernel: the
+    same bits, one quadrature per stored entry at nonzero distance, N + 1 >= 5 nodes
+    each (ragged last tile row and a duplicated point)."""
+    import torch
+    from paper_2502_00356_amd import workloads as w
+    n, ts = 301, 128
+    xy = w.uniform_locations(n, seed=71)
+    xy[7] = xy[150]                        # an exact duplicate: r == 0 off the diagonal
+    lx, ly = to_dev(xy[:, 0]), to_dev(xy[:, 1])
+    ref = api.matern_tiles(lx, ly, 1.0, 0.07, 1.9, ts, 1, mode=mode)
+    stats = torch.zeros(api.STATS_LEN, dtype=torch.int64, device="cuda")
+    got = api.matern_tiles(lx, ly, 1.0, 0.07, 1.9, ts, 1, mode=mode, stats=stats)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    st = stats.cpu().numpy()
+    # the duplicate pair (7, 150) is stored in tile (1, 0) only; (150, 7) and (7, 150)
+    # both sit in stored tiles when they share a diagonal tile, which they do not here
+    assert int(st[api.STAT_ENTRIES]) == api.matern_out_elems(n, ts, 1) - n - 1
+    assert int(st[api.STAT_NODES]) >= 5 * int(st[api.STAT_ENTRIES])
+
+
+def test_kernel_events_bracket_matern(api):
+    import torch
+    from paper_2502_00356_amd import workloads as w
+    xy = w.uniform_locations(1500, seed=72)
+    lx, ly = to_dev(xy[:, 0]), to_dev(xy[:, 1])
+    ref = api.matern_tiles(lx, ly, 1.0, 0.05, 1.2, 500, 1, mode="mixed")
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    for e in ev:
+        e.record()
+    torch.cuda.synchronize()
+    got = api.matern_tiles(lx, ly, 1.0, 0.05, 1.2, 500, 1, mode="mixed", kernel_events=ev)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    assert ev[0].elapsed_time(ev[1]) > 0.0

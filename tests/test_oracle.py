@@ -257,6 +257,25 @@ def test_mlp_forward_hand_case(orc):
     assert np.array_equal(y, ref)
 
 
+def test_mlp_loss_hand_values(orc):
+    """Expectile loss on two hand-worked samples, one with every residual e = t - y
+    positive (weights tau) and one with every residual negative (weights 1 - tau):
+      sample 0: e = (1, 2, 3):    0.1*1 + 0.9*4 + 0.9*9 = 11.8
+      sample 1: e = (-1, -1, -1): 0.9*1 + 0.1*1 + 0.1*1 = 1.1
+    mean over the batch (summed over outputs): 6.45. Swapping tau and 1 - tau gives
+    2.05, dropping the square 2.85, and dividing by outputs as well 2.15, so each of
+    those slips fails."""
+    y = np.array([[0.0, 0.0, 0.0], [1.0, 1.0, 1.0]])
+    t = np.array([[1.0, 2.0, 3.0], [0.0, 0.0, 0.0]])
+    tau = np.array([0.1, 0.9, 0.9])
+    assert orc.mlp_loss(y, t, tau) == pytest.approx(6.45, rel=1e-15)
+    # a single output: tau = 0.9 weights an under-prediction (e > 0) nine times an
+    # over-prediction of the same size
+    one = np.array([0.9])
+    assert orc.mlp_loss(np.array([[0.0]]), np.array([[2.0]]), one) == pytest.approx(3.6, rel=1e-15)
+    assert orc.mlp_loss(np.array([[2.0]]), np.array([[0.0]]), one) == pytest.approx(0.4, rel=1e-15)
+
+
 def test_mlp_backward_finite_differences(orc):
     """Analytic gradients against central differences of the loss."""
     p = _params(1)
