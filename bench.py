@@ -84,8 +84,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="matern-large",
                     choices=["matern-large", "grid", "matern-medium", "deriv-grid", "matern-grad-medium", "loglik",
-                             "paper-grid"],
+                             "paper-grid", "small-x", "matern-order"],
                     help="matern-large: the headline (316 x 316 grid, nu = 3.7, FP32 learned vs FP64 plain)")
+    ap.add_argument("--forms", default="learned,mixed,plain",
+                    help="matern-large: forms to time (comma-separated; the headline needs learned)")
     ap.add_argument("--cpu-tiles", type=int, default=4,
                     help="matern-large: whole tiles of the last tile row in the CPU baseline sample (0-4)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -193,6 +195,12 @@ def main():
     if a.workload == "matern-large":
         matern_headline(a, torch, api, workloads)
         return
+    if a.workload == "small-x":
+        small_x_bench(a, torch, api, workloads)
+        return
+    if a.workload == "matern-order":
+        matern_order_bench(a, torch, api, workloads)
+        return
     if a.workload != "grid":
         matern_bench(a, torch, api, workloads)
         return
@@ -258,10 +266,12 @@ def matern_headline(a, torch, api, workloads):
     elems = api.matern_out_elems(n, ts, 1)
     model = load_model(a, api)
     ws = torch.empty(api.matern_workspace_bytes(n, ts, 1), dtype=torch.uint8, device=dev)
-    outs = {torch.float32: torch.empty(elems, dtype=torch.float32, device=dev),
-            torch.float64: torch.empty(elems, dtype=torch.float64, device=dev)}
-    forms = (("learned", api.OUT_F32, "matern_learned"), ("mixed", api.OUT_F32, "matern_mixed"),
-             ("plain", api.OUT_F64, "matern_plain"))
+    outs = {torch.float32: torch.empty(elems, dtype=torch.float32, device=dev)}
+    if "plain" in want:
+        outs[torch.float64] = torch.empty(elems, dtype=torch.float64, device=dev)
+    want = set(a.forms.split(","))
+    forms = tuple(f for f in (("learned", api.OUT_F32, "matern_learned"), ("mixed", api.OUT_F32, "matern_mixed"),
+                              ("plain", api.OUT_F64, "matern_plain")) if f[0] in want or f[0] == "learned")
     stream = torch.cuda.current_stream()
     res = {}
     for f, odt, slot_key in forms:
@@ -349,8 +359,8 @@ def matern_headline(a, torch, api, workloads):
                    "n": n, "tile": ts, "entries": elems, "form": "learned",
                    "also": "bench.py --workload grid: the 2^24-pair standalone K_nu grid"},
         "forms": {f: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in d.items()} for f, d in res.items()},
-        "speedup_vs_plain_f64": res["plain"]["ms_per_step"] / head["ms_per_step"],
-        "speedup_vs_mixed": res["mixed"]["ms_per_step"] / head["ms_per_step"],
+        "speedup_vs_plain_f64": res["plain"]["ms_per_step"] / head["ms_per_step"] if "plain" in res else None,
+        "speedup_vs_mixed": res["mixed"]["ms_per_step"] / head["ms_per_step"] if "mixed" in res else None,
         "max_rel_err_sample": acc,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s (full-rate VALU lane-op slots)", "frac": achieved / VALU_PEAK_TOPS,
@@ -501,7 +511,9 @@ def matern_bench(a, torch, api, workloads):
         if tdt not in bufs:
             bufs[tdt] = torch.empty(elems, dtype=tdt, device=dev)
         out = bufs[tdt]
-        kw = dict(mode=f, out_dtype=dt, out=out, model=model)
+        ws = (torch.empty(api.matern_workspace_bytes(n, ts, 1), dtype=torch.uint8, device=dev)
+              if f == "learned" else None)
+        kw = dict(mode=f, out_dtype=dt, out=out, model=model, workspace=ws)
         for _ in range(max(1, a.warmup)):
             api.matern_tiles(lx, ly, 1.0, beta, nu, ts, 1, **kw)
         torch.cuda.synchronize()
@@ -613,6 +625,68 @@ def paper_bench(a, torch, api, workloads):
                          "x > 140": float(re[xs > 140].max())}
     line = {"metric": "K_nu evals/s, the paper's refined algorithm", "workload": a.workload, "n": a.n,
             "dtype": "f64", "results": res}
+    print(json.dumps(line), flush=True)
+
+
+def small_x_bench(a, torch, api, workloads):
+    """Small arguments, x in [1e-4, 0.1) (the paper's Temme region, Sec. IV-A):
+    2^24 pairs, nu ~ U[0.01, 10], x log-uniform (seed 8). The paper's refined
+    algorithm (Temme's series and the forward recurrence here) against the plain
+    FP64 windowed quadrature: time per evaluation and accuracy on a 2^16 sample."""
+    dev = torch.device("cuda:0")
+    nu_h, x_h = workloads.pairs_loguniform(a.n, 8, 0.01, 10.0, -4.0, -1.0)
+    nu = torch.from_numpy(nu_h).to(dev)
+    x = torch.from_numpy(x_h).to(dev)
+    out = torch.empty_like(x)
+    steps = max(1, a.steps)
+    res = {}
+    for name, mode in (("temme_series", "paper"), ("windowed_quadrature_f64", "plain")):
+        ms = _event_ms(torch, lambda: api.besselk(nu, x, out=out, mode=mode, result=api.RESULT_SCALED), steps,
+                       a.warmup)
+        res[name] = {"ms": round(ms, 4), "evals_per_s": a.n / (ms * 1e-3)}
+    if not a.no_cpu:
+        import oracle
+        idx = np.random.default_rng(97).permutation(a.n)[:1 << 16]
+        _, _, ks = oracle.besselk(nu_h[idx], x_h[idx])
+        sel = torch.from_numpy(idx).to(dev)
+        for name, mode in (("temme_series", "paper"), ("windowed_quadrature_f64", "plain")):
+            o = api.besselk(nu[sel].contiguous(), x[sel].contiguous(), mode=mode, result=api.RESULT_SCALED)
+            torch.cuda.synchronize()
+            e = np.abs(o.cpu().numpy() - ks) / ks
+            res[name]["max_rel_err"] = float(e.max())
+            res[name]["max_RE"] = float(np.log10(1.0 + e.max() / 2.0 ** -52))
+    line = {"metric": "K_nu evals/s at x in [1e-4, 0.1)", "workload": a.workload, "n": a.n, "dtype": "f64",
+            "results": res, "quadrature_over_temme": res["temme_series"]["ms"] / res["windowed_quadrature_f64"]["ms"]}
+    print(json.dumps(line), flush=True)
+
+
+def matern_order_bench(a, torch, api, workloads):
+    """Morton order against the generator's order (Sec. IV-D sorts locations along a
+    Morton curve): n = 40,000 uniform points (seed 3), beta = 0.05, nu in {0.8, 2.3},
+    lower 960-tiles, FP64 output, the three forms, both orders."""
+    dev = torch.device("cuda:0")
+    c = workloads.MATERN_MEDIUM
+    model = api.Model(a.model) if os.path.exists(a.model) else None
+    elems = api.matern_out_elems(c["n"], c["tile"], 1)
+    out = torch.empty(elems, dtype=torch.float64, device=dev)
+    ws = torch.empty(api.matern_workspace_bytes(c["n"], c["tile"], 1), dtype=torch.uint8, device=dev)
+    res = {}
+    for order in ("morton", "unsorted"):
+        xy = workloads.uniform_locations(c["n"], c["seed"], morton=(order == "morton"))
+        lx = torch.from_numpy(np.ascontiguousarray(xy[:, 0])).to(dev)
+        ly = torch.from_numpy(np.ascontiguousarray(xy[:, 1])).to(dev)
+        for nu in c["nus"]:
+            for f in ("plain", "mixed", "learned"):
+                if f == "learned" and model is None:
+                    continue
+                ms = _event_ms(torch, lambda: api.matern_tiles(lx, ly, 1.0, c["beta"], nu, c["tile"], 1, mode=f,
+                                                               out=out, model=model, workspace=ws),
+                               max(1, min(a.steps, 3)), a.warmup)
+                res["%s/nu=%g/%s" % (order, nu, f)] = round(ms, 3)
+    ratio = {k.replace("unsorted/", ""): res[k] / res[k.replace("unsorted", "morton")] for k in res if
+             k.startswith("unsorted")}
+    line = {"metric": "Matern ms per build, Morton vs unsorted locations", "workload": a.workload, "n": c["n"],
+            "tile": c["tile"], "beta": c["beta"], "ms": res, "unsorted_over_morton": ratio}
     print(json.dumps(line), flush=True)
 
 

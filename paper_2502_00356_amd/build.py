@@ -44,22 +44,23 @@ def issue_cost(op):
 
 
 def _loops(lines):
-    """(start, end) line spans of the loops of one function: a label and a later
-    branch back to it."""
+    """(start, end) line spans of the loops of one function: a label and the last
+    later branch back to it (a loop whose body has several paths has several back
+    edges; the span covers them all)."""
     import re
     labels = {}
     for i, l in enumerate(lines):
         m = re.match(r"^(\.LBB\d+_\d+):", l)
         if m:
             labels[m.group(1)] = i
-    spans = []
+    last = {}
     for i, l in enumerate(lines):
         m = re.search(r"s_cbranch_\w+\s+(\.LBB\d+_\d+)|s_branch\s+(\.LBB\d+_\d+)", l)
         if m:
             lab = m.group(1) or m.group(2)
             if lab in labels and labels[lab] < i:
-                spans.append((labels[lab], i))
-    return spans
+                last[lab] = i
+    return [(labels[lab], i) for lab, i in last.items()]
 
 
 def node_slots(asm_path):
@@ -67,7 +68,9 @@ def node_slots(asm_path):
     (issue_cost above), read from the gfx950 assembly of this build: the node loop
     is the innermost loop that evaluates the node exponential (v_exp_f32 for the
     FP32-term forms; the inlined FP64 exp, one v_ldexp_f64 without divisions or
-    logarithms, for the plain form)."""
+    logarithms, for the plain form), and its cost is divided by the exponentials
+    one trip evaluates (the plain form's paired walk evaluates two nodes a trip
+    when both sides of the reference node are live)."""
     text = open(asm_path).read().split("\n")
     funcs = {}
     cur = None

@@ -116,7 +116,11 @@ __global__ __launch_bounds__(kSolveBlock) __attribute__((amdgpu_waves_per_eu(6, 
 {
     __shared__ unsigned int hist[64];
     __shared__ double s_tab[kTabLen];
-    __shared__ double s_d[8][kSolveBlock];
+    // staged per entry between phases: v, z, t_ref, h, Delta, then for the plain
+    // form dlo, e^t_ref, e^-t_ref, expm1(t_ref) (paired walk), for the mixed form
+    // t0 and x cosh(t_ref) / 2
+    constexpr int kRows = MODE == BK_PLAIN_F64 ? 9 : 7;
+    __shared__ double s_d[kRows][kSolveBlock];
     __shared__ int s_i[3][kSolveBlock];
     const int tid = threadIdx.x;
     if (tid < kTabLen) s_tab[tid] = rule_tab().tab[tid];   // read after the sorts' barriers
@@ -150,11 +154,17 @@ __global__ __launch_bounds__(kSolveBlock) __attribute__((amdgpu_waves_per_eu(6, 
     s_d[0][slot] = v2;
     s_d[1][slot] = z2;
     s_d[2][slot] = sv.p.tref;
-    s_d[3][slot] = sv.p.t0;
-    s_d[4][slot] = sv.p.h;
-    s_d[5][slot] = sv.delta;
-    s_d[6][slot] = sv.A;
-    s_d[7][slot] = sv.B;
+    s_d[3][slot] = sv.p.h;
+    s_d[4][slot] = sv.delta;
+    if constexpr (MODE == BK_PLAIN_F64) {
+        s_d[5][slot] = sv.dlo;
+        s_d[6][slot] = sv.E;
+        s_d[7][slot] = sv.Ei;
+        s_d[8][slot] = sv.Sr;
+    } else {
+        s_d[5][slot] = sv.p.t0;
+        s_d[6][slot] = sv.A;
+    }
     s_i[0][slot] = li;
     s_i[1][slot] = sv.p.N;
     s_i[2][slot] = sv.p.mc;
@@ -165,13 +175,19 @@ __global__ __launch_bounds__(kSolveBlock) __attribute__((amdgpu_waves_per_eu(6, 
         const double v3 = s_d[0][tid], z3 = s_d[1][tid];
         Plan p;
         p.tref = s_d[2][tid];
-        p.t0 = s_d[3][tid];
-        p.h = s_d[4][tid];
+        p.h = s_d[3][tid];
         p.N = s_i[1][tid];
         p.mc = s_i[2][tid];
-        const double A = s_d[6][tid], B = s_d[7][tid];
-        const double S = (MODE == BK_PLAIN_F64) ? sum_f64(v3, p, A, B, s_tab) : sum_mixed(v3, z3, p, A, s_tab);
-        out[(int64_t)blockIdx.x * kSolveBlock + l3] = assemble(z3, s_d[5][tid], p.h * S, result);
+        double hs;
+        if constexpr (MODE == BK_PLAIN_F64) {
+            p.t0 = 0.0;                       // not used by the paired walk
+            hs = p.h * sum_f64(v3, z3, p, s_d[6][tid], s_d[7][tid], s_d[8][tid], s_tab);
+            hs = fma(hs, s_d[5][tid], hs);    // the low part of Delta
+        } else {
+            p.t0 = s_d[5][tid];
+            hs = p.h * sum_mixed(v3, z3, p, s_d[6][tid], s_tab);
+        }
+        out[(int64_t)blockIdx.x * kSolveBlock + l3] = assemble(z3, s_d[4][tid], hs, result);
         nodes = (unsigned long long)(p.N + 1);
         ents = 1;
     }
@@ -273,14 +289,16 @@ __global__ __launch_bounds__(256, 3) void k_besselk_deriv(const double* __restri
         } else {
             const RuleTable& R = rule_tab();
             const Solved s0 = plain_solve(v, z, L, Lq, R, s_tab);
-            const double hs0 = s0.p.h * sum_f64(v, s0.p, s0.A, s0.B, s_tab);
+            double hs0 = s0.p.h * sum_f64(v, z, s0.p, s0.E, s0.Ei, s0.Sr, s_tab);
+            hs0 = fma(hs0, s0.dlo, hs0);
             rk = assemble(z, s0.delta, hs0, result);
             nodes += (unsigned long long)(s0.p.N + 1);
             rx = 0.0;
             if (dkdx) {
                 const double v1 = fabs(v - 1.0);
                 const Solved s1 = plain_solve(v1, z, L, Lq, R, s_tab);
-                const double hs1 = s1.p.h * sum_f64(v1, s1.p, s1.A, s1.B, s_tab);
+                double hs1 = s1.p.h * sum_f64(v1, z, s1.p, s1.E, s1.Ei, s1.Sr, s_tab);
+                hs1 = fma(hs1, s1.dlo, hs1);
                 nodes += (unsigned long long)(s1.p.N + 1);
                 rx = -unscale(z, exp(s1.delta) * hs1 + (v / z) * (exp(s0.delta) * hs0), result);
             }
@@ -395,8 +413,14 @@ __global__ __launch_bounds__(256, 4) void k_matern(const double* __restrict__ lx
                 }
             } else {
                 Solved s = plain_solve(nu, z, L, Lq, rule_tab(), s_tab);
-                double S = (MODE == BK_PLAIN_F64) ? sum_f64(nu, s.p, s.A, s.B, s_tab) : sum_mixed(nu, z, s.p, s.A, s_tab);
-                val = sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * (s.p.h * S);
+                double hs;
+                if constexpr (MODE == BK_PLAIN_F64) {
+                    hs = s.p.h * sum_f64(nu, z, s.p, s.E, s.Ei, s.Sr, s_tab);
+                    hs = fma(hs, s.dlo, hs);
+                } else {
+                    hs = s.p.h * sum_mixed(nu, z, s.p, s.A, s_tab);
+                }
+                val = sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * hs;
                 c_nodes += (unsigned int)(s.p.N + 1);
                 c_ent += 1;
             }
@@ -455,11 +479,13 @@ __global__ __launch_bounds__(256) void k_matern_grad(const double* __restrict__ 
             const double z = r * inv_beta, lz = log(z);
             const Solved s0 = plain_solve(nu, z, L, Lq, R, s_tab);
             // the same expression as k_matern, so that C is bit-identical with or without the derivatives
-            vc = sigma2 * exp(pref + nu * lz + (s0.delta - z)) * (s0.p.h * sum_f64(nu, s0.p, s0.A, s0.B, s_tab));
+            double hs0 = s0.p.h * sum_f64(nu, z, s0.p, s0.E, s0.Ei, s0.Sr, s_tab);
+            hs0 = fma(hs0, s0.dlo, hs0);
+            vc = sigma2 * exp(pref + nu * lz + (s0.delta - z)) * hs0;
             if (ob) {
                 const Solved s1 = plain_solve(nu1, z, L, Lq, R, s_tab);
-                vb = sigma2 * inv_beta * exp(pref + (nu + 1.0) * lz + (s1.delta - z)) *
-                     (s1.p.h * sum_f64(nu1, s1.p, s1.A, s1.B, s_tab));
+                const double hs1 = s1.p.h * sum_f64(nu1, z, s1.p, s1.E, s1.Ei, s1.Sr, s_tab);
+                vb = sigma2 * inv_beta * exp(pref + (nu + 1.0) * lz + (s1.delta - z)) * fma(hs1, s1.dlo, hs1);
             }
             if (on) {
                 const Solved sd = dnu_solve(nu, z, s0.p.t0, L, Lq, R, s_tab);

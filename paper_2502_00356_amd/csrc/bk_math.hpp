@@ -326,14 +326,43 @@ __device__ __forceinline__ int node_count(double width, double h)
 // A = x cosh(t_ref)/2, B = x sinh(t_ref)/2 of the cancellation-free xterm.
 struct Solved {
     Plan p;
-    double delta;
-    double A, B;
+    double delta, dlo;   // Delta as an unevaluated sum delta + dlo (|dlo| below an ulp of delta)
+    double A, B;         // x cosh(t_ref) / 2, x sinh(t_ref) / 2 (single walk, FP32-term walk)
+    double E, Ei, Sr;    // e^t_ref, e^-t_ref, expm1(t_ref) (paired walk of the plain sum)
     double gstar;   // g(t*) (used by the window export)
     double t1;
 };
 
+// Rounding error of s = a + b (Knuth's two-sum): a + b = s + two_sum_err(a, b, s) exactly.
+__device__ __forceinline__ double two_sum_err(double a, double b, double s)
+{
+    const double bb = s - a;
+    return (a - (s - bb)) + (b - bb);
+}
+
+// ln 2 - kLn2 (the part of ln 2 below the double kLn2).
+constexpr double kLn2Lo = 2.319046813846299558e-17;
+
+// Delta = nu t_ref - ln 2 - q as hi + lo: the product split exactly by a fused
+// multiply-add, the two sums' rounding errors carried by two_sum_err. Contraction
+// is off here: fusing nu t_ref into the first sum (or q's product into it) would
+// round something other than what the error terms describe.
+__device__ __forceinline__ void delta_dd(double nu, double tref, double q, double& hi, double& lo)
+{
+#pragma clang fp contract(off)
+    const double pr = nu * tref, pe = fma(nu, tref, -pr);
+    const double s1 = pr - q, e1 = two_sum_err(pr, -q, s1);
+    const double s2 = s1 - kLn2, e2 = two_sum_err(s1, -kLn2, s2);
+    hi = s2;
+    lo = ((pe + e1) + e2) - kLn2Lo;
+}
+
 // Node grid on [t0, t1] with step at most h0, reference node nearest tpk, and
-// the prefactor constants for the node walk.
+// the prefactor constants for the node walk. Delta = nu t_ref - ln 2 -
+// 2 x sinh^2(t_ref/2) reaches ~120 for large orders at small x, where rounding it
+// to one double would cost ~1e-14 of K; it is kept as delta + dlo, with nu t_ref
+// split exactly (fused multiply-add) and the sums' rounding errors carried, so
+// that what is left is the ~3 ulps of the sinh^2 term.
 __device__ inline Solved plan_window(double nu, double x, double t0, double t1, double tpk, double h0)
 {
     Solved s;
@@ -354,9 +383,12 @@ __device__ inline Solved plan_window(double nu, double x, double t0, double t1, 
     s.p.N = N;
     s.p.mc = mc;
     s.p.h = h;
-    s.delta = nu * tref - kLn2 - 2.0 * x * sh2 * sh2;
+    delta_dd(nu, tref, 2.0 * x * sh2 * sh2, s.delta, s.dlo);
     s.A = 0.5 * x * ch;
     s.B = 0.5 * x * sh;
+    s.Sr = em * (em + 2.0);                            // expm1(t_ref), no cancellation
+    s.E = s.Sr + 1.0;
+    s.Ei = recip(s.E);
     s.gstar = 0.0;
     s.t1 = t1;
     return s;
@@ -424,19 +456,53 @@ __device__ __forceinline__ void walk_step(Walk& w, int m)
     w.V = (m + 1 <= w.mc) ? vin : vout;
 }
 
-// FP64 trapezoid sum S = sum_m c_m exp(d_m) (1 + P_m), c_0 = c_N = 1/2; T is
-// exp_tab's table.
-__device__ inline double sum_f64(double nu, const Plan& p, double A, double B, const double* T)
+// FP64 trapezoid sum of the plain form, S = sum_m c_m exp(d_m) (1 + P_m),
+// c_0 = c_N = 1/2, as a paired walk outward from the reference node: iteration j
+// takes node mc + j (right, j <= N - mc) and node mc - j (left, 1 <= j <= mc),
+// both at |w| = j h / 2. With x (cosh t - cosh t_ref) = 2 x sinh(w) sinh(s),
+// s = (t + t_ref) / 2 >= |w| (product-to-sum, no cancellation):
+//   right: d = nu j h - (x/2) 2 sinh|w| 2 sinh(t_ref + |w|),
+//   left:  d = -nu j h + (x/2) 2 sinh|w| 2 sinh(t_ref - |w|).
+// 2 sinh|w| = V (1 + e^-|w|) with V = expm1(|w|) from V' = V q + expm1(h/2),
+// which only ever runs outward from V = 0 (its relative error grows by about an
+// ulp per step; an inward run loses relative accuracy as V shrinks, and that loss
+// reached ~5e-14 of K left of interior peaks); 2 sinh(t_ref + |w|) the same way
+// from expm1(t_ref); 2 sinh(t_ref - |w|) = e^t_ref e^-|w| - e^-t_ref e^|w|, whose
+// terms differ by a factor e^(2 (t_ref - |w|)) >= e^t_ref. The two sides share V,
+// e^-|w| and nu j h; a side no lane of the wave needs is skipped. T is exp_tab's
+// table; E, Ei, Sr = e^t_ref, e^-t_ref, expm1(t_ref) from the solve.
+__device__ inline double sum_f64(double nu, double x, const Plan& p, double E, double Ei, double Sr, const double* T)
 {
-    Walk w = walk_begin(nu, p);
-    double S = 0.0, ends = 0.0;
-    for (int m = 0; m <= p.N; ++m) {
-        double term = exp_tab(walk_exponent(w, m, nu, A, B), T) * (1.0 + w.P);
-        S += term;
-        if (m == 0 || m == p.N) ends += term;
-        walk_step(w, m);
+    const int nr = p.N - p.mc, nl = p.mc, jmax = nr > nl ? nr : nl;
+    const double h = p.h, xh = 0.5 * x;
+    const double qm1 = expm1(0.5 * h), q = qm1 + 1.0, qi = recip(q);
+    const double rho = exp_tab(-2.0 * nu * h, T), rhoi = recip(rho);
+    double V = 0.0, Bq = 1.0;                 // expm1(|w|), e^-|w|
+    double SR = Sr, ER = Ei;                  // expm1(t_ref + |w|), e^-(t_ref + |w|)
+    double PR = exp_tab(-2.0 * nu * p.tref, T), PL = PR;   // e^(-2 nu t) at nodes mc + j, mc - j
+    double S = 0.0, jd = 0.0;
+    for (int j = 0; j <= jmax; ++j) {
+        const double nuu = nu * (jd * h);     // j h formed per node: no drift
+        const double xs = xh * fma(V, Bq, V);
+        if (j <= nr) {
+            const double ss = fma(SR, ER, SR);
+            const double t = exp_tab(fma(-xs, ss, nuu), T) * (1.0 + PR);
+            S = fma((j == nr || (j == 0 && nl == 0)) ? 0.5 : 1.0, t, S);   // ends: node N; node 0 if mc = 0
+        }
+        if (j >= 1 && j <= nl) {
+            const double ss = fma(E, Bq, -Ei * (V + 1.0));
+            const double t = exp_tab(fma(xs, ss, -nuu), T) * (1.0 + PL);
+            S = fma(j == nl ? 0.5 : 1.0, t, S);                          // node 0
+        }
+        V = fma(V, q, qm1);
+        Bq *= qi;
+        SR = fma(SR, q, qm1);
+        ER *= qi;
+        PR *= rho;
+        PL *= rhoi;
+        jd += 1.0;
     }
-    return S - 0.5 * ends;
+    return S;
 }
 
 // Node walk of the FP32-term forms (mixed and learned). Their terms need the
