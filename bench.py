@@ -266,10 +266,10 @@ def matern_headline(a, torch, api, workloads):
     elems = api.matern_out_elems(n, ts, 1)
     model = load_model(a, api)
     ws = torch.empty(api.matern_workspace_bytes(n, ts, 1), dtype=torch.uint8, device=dev)
+    want = set(a.forms.split(","))
     outs = {torch.float32: torch.empty(elems, dtype=torch.float32, device=dev)}
     if "plain" in want:
         outs[torch.float64] = torch.empty(elems, dtype=torch.float64, device=dev)
-    want = set(a.forms.split(","))
     forms = tuple(f for f in (("learned", api.OUT_F32, "matern_learned"), ("mixed", api.OUT_F32, "matern_mixed"),
                               ("plain", api.OUT_F64, "matern_plain")) if f[0] in want or f[0] == "learned")
     stream = torch.cuda.current_stream()

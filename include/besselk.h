@@ -292,6 +292,23 @@ int bk_model_train(bk_model* model, const double* nu, const double* x, int64_t n
  * N = ceil(N_pred * (1 + eta) + n_add) (host values). */
 int bk_model_set_margins(bk_model* model, double d_lo, double d_hi, double eta, double n_add);
 
+/* The four margins (d_lo, d_hi, eta, n_add) into m4 (host). */
+int bk_model_get_margins(const bk_model* model, double* m4);
+
+/* What fills the learned form's prediction tables (the standalone cells, their
+ * plans, and the Matern window table of each call).
+ *  BK_TABLE_NETWORK : the network's predictions (default).
+ *  BK_TABLE_SOLVER  : the plain window solver of Sec. IV-B (bk_window at the
+ *                     model's training thresholds) at the same points: the same
+ *                     kernels without the network, for measuring what the
+ *                     network contributes. The margins still apply; set them to
+ *                     zero for the solver's windows as they are. */
+typedef enum { BK_TABLE_NETWORK = 0, BK_TABLE_SOLVER = 1 } bk_table_source;
+
+/* Select the table source (bk_table_source) and rebuild the prediction cells
+ * (synchronous). BK_ENOMODEL if the model has no parameters yet. */
+int bk_model_set_table_source(bk_model* model, int32_t source);
+
 /* Copy the flat FP32 parameter vector to host (BK_MLP_NPARAM floats) or set it
  * (setting it, the normalisation or the box rebuilds the prediction cells below
  * and synchronises the device). */

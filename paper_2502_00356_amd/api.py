@@ -25,6 +25,7 @@ OUT_F64, OUT_F32 = 0, 1
 STAT_ENTRIES, STAT_NODES, STAT_FB_RANGE, STAT_FB_TAIL, STAT_NODE_RAISED, STAT_FB_NONFINITE, STAT_FB_NODES = range(7)
 STATS_LEN = 8
 MLP_NPARAM = 4547
+TABLE_NETWORK, TABLE_SOLVER = 0, 1
 MODES = {"plain": PLAIN_F64, "mixed": MIXED_F32C, "learned": LEARNED, "paper": PAPER_REFINED}
 
 _vp = ctypes.c_void_p
@@ -81,6 +82,8 @@ _m_save = _sig("bk_model_save", ctypes.c_int, [_vp, ctypes.c_char_p])
 _m_train = _sig("bk_model_train", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(TrainCfg),
                                                  ctypes.POINTER(ctypes.c_float), _vp])
 _m_margins = _sig("bk_model_set_margins", ctypes.c_int, [_vp, _dbl, _dbl, _dbl, _dbl])
+_m_get_margins = _sig("bk_model_get_margins", ctypes.c_int, [_vp, ctypes.POINTER(_dbl)])
+_m_table_source = _sig("bk_model_set_table_source", ctypes.c_int, [_vp, _i32])
 _m_getp = _sig("bk_model_get_params", ctypes.c_int, [_vp, _vp])
 _m_setp = _sig("bk_model_set_params", ctypes.c_int, [_vp, _vp])
 _m_getn = _sig("bk_model_get_norm", ctypes.c_int, [_vp, _vp])
@@ -375,6 +378,15 @@ class Model:
 
     def set_margins(self, d_lo, d_hi, eta, n_add):
         _check(_m_margins(self.handle, float(d_lo), float(d_hi), float(eta), float(n_add)))
+
+    def get_margins(self):
+        m4 = (_dbl * 4)()
+        _check(_m_get_margins(self.handle, m4))
+        return tuple(m4)
+
+    def set_table_source(self, source):
+        """TABLE_NETWORK or TABLE_SOLVER (bk_model_set_table_source); rebuilds the cells."""
+        _check(_m_table_source(self.handle, int(source)))
 
     def get_params(self):
         t = torch.empty(MLP_NPARAM, dtype=torch.float32)

@@ -96,6 +96,7 @@ struct bk_model {
     double box[4] = {-4.0, 3.0, 0.01, 10.0};
     double margins[4] = {0.05, 0.05, 0.05, 1.0};
     double train_L[2] = {15.0, 14.5};
+    int table_source = BK_TABLE_NETWORK;   // what fills the cells and the Matern table
     bool trained = false;
     int device = 0;
 };
@@ -271,6 +272,44 @@ __global__ __launch_bounds__(256) void k_cell_table(MlpDev M, float4_t* __restri
         w[2] = fmaxf(w[2], y2);
     }
     if (c < kCells) cells[c] = w;
+}
+
+// The plain solver's window (Sec. IV-B: peak, window ends at g* - L, strip-bound
+// node count for exp(-Lq)) at (nu, 10^lx), in the network's normalised output
+// units (t_lo / st, t_hi / st, N / sn). N / sn is exact in FP32 (sn is a power of
+// two), so the decode gives back N.
+__device__ inline void solver_prediction(const MlpDev& M, float lx, float nu, double L, double Lq, float& y0,
+                                         float& y1, float& y2)
+{
+    const Solved s = plain_solve((double)nu, exp10((double)lx), L, Lq, rule_tab(), rule_tab().tab);
+    y0 = (float)(s.p.t0 / (double)M.st);
+    y1 = (float)(s.t1 / (double)M.st);
+    y2 = (float)((double)s.p.N / (double)M.sn);
+}
+
+// Prediction cells filled by the plain solver instead of the network, at the same
+// four corners (the union of the solver's windows there): the learned form without
+// the network, for measuring what the network itself contributes.
+__global__ __launch_bounds__(256) void k_cell_table_solver(MlpDev M, double L, double Lq,
+                                                           float4_t* __restrict__ cells)
+{
+#pragma clang fp contract(off)
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= kCells) return;
+    const int i = c / kCellsNu, j = c % kCellsNu;
+    const float dl = (M.lx_hi - M.lx_lo) / (float)kCellsLx;
+    const float dn = (M.nu_hi - M.nu_lo) / (float)kCellsNu;
+    float4_t w = {__builtin_inff(), -__builtin_inff(), -__builtin_inff(), 0.0f};
+    for (int k = 0; k < 4; ++k) {
+        const float lx = M.lx_lo + (float)(i + (k & 1)) * dl;
+        const float nu = M.nu_lo + (float)(j + (k >> 1)) * dn;
+        float y0, y1, y2;
+        solver_prediction(M, lx, nu, L, Lq, y0, y1, y2);
+        w[0] = fminf(w[0], y0);
+        w[1] = fmaxf(w[1], y1);
+        w[2] = fmaxf(w[2], y2);
+    }
+    cells[c] = w;
 }
 
 // The cell of an entry inside the training box (the last cell of each axis also
@@ -761,6 +800,21 @@ __global__ __launch_bounds__(256) void k_matern_table(MlpDev M, float nu, float*
         table[4 * i + 2] = y2;
         table[4 * i + 3] = 0.0f;
     }
+}
+
+// The Matern window table filled by the plain solver at the same points.
+__global__ __launch_bounds__(256) void k_matern_table_solver(MlpDev M, float nu, double L, double Lq,
+                                                             float* __restrict__ table)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= kTableSize) return;
+    const float lx = M.lx_lo + (M.lx_hi - M.lx_lo) * (float)i / (float)(kTableSize - 1);
+    float y0, y1, y2;
+    solver_prediction(M, lx, nu, L, Lq, y0, y1, y2);
+    table[4 * i] = y0;
+    table[4 * i + 1] = y1;
+    table[4 * i + 2] = y2;
+    table[4 * i + 3] = 0.0f;
 }
 
 // Quadrature plans of the Matern table's cells (between rows k and k + 1) at the
@@ -1316,8 +1370,11 @@ static int model_cells(bk_model* m)
 {
     if (!m->params) return BK_OK;
     m->plan_Lq = -1.0;
-    int st = launch(k_cell_table, dim3((kCells + 255) / 256), dim3(256), nullptr, make_dev(m),
-                    reinterpret_cast<float4_t*>(m->cells));
+    int st = m->table_source == BK_TABLE_SOLVER
+                 ? launch(k_cell_table_solver, dim3((kCells + 255) / 256), dim3(256), nullptr, make_dev(m),
+                          m->train_L[0], m->train_L[1], reinterpret_cast<float4_t*>(m->cells))
+                 : launch(k_cell_table, dim3((kCells + 255) / 256), dim3(256), nullptr, make_dev(m),
+                          reinterpret_cast<float4_t*>(m->cells));
     if (st == BK_OK)
         st = launch(k_cell_plans, dim3((kCells + 255) / 256), dim3(256), nullptr, make_dev(m), kDefaultLqMixed,
                     reinterpret_cast<float4_t*>(m->plan_a), reinterpret_cast<double4_t*>(m->plan_b));
@@ -1427,7 +1484,10 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
     const int64_t max_wg = 1LL << 23;                      // keeps a launch below 2^31 work-items
     const int64_t tiles_per_launch = max_wg / wg_per_tile > 0 ? max_wg / wg_per_tile : 1;
     const double ib = 1.0 / prm->beta;
-    int st = launch(k_matern_table, dim3((kTableSize + 255) / 256), dim3(256), stream, M, (float)nu, table);
+    int st = m->table_source == BK_TABLE_SOLVER
+                 ? launch(k_matern_table_solver, dim3((kTableSize + 255) / 256), dim3(256), stream, M, (float)nu,
+                          m->train_L[0], m->train_L[1], table)
+                 : launch(k_matern_table, dim3((kTableSize + 255) / 256), dim3(256), stream, M, (float)nu, table);
     if (st == BK_OK)
         st = launch(k_matern_plans, dim3((kTableSize + 254) / 256), dim3(256), stream, M, nu, Lq, pref,
                     (const float*)table, plan_a, plan_b);
@@ -1546,6 +1606,21 @@ extern "C" int bk_model_set_margins(bk_model* m, double d_lo, double d_hi, doubl
     m->margins[1] = d_hi;
     m->margins[2] = eta;
     m->margins[3] = n_add;
+    return model_cells(m);
+}
+
+extern "C" int bk_model_get_margins(const bk_model* m, double* m4)
+{
+    if (!m || !m4) return BK_EINVAL;
+    for (int i = 0; i < 4; ++i) m4[i] = m->margins[i];
+    return BK_OK;
+}
+
+extern "C" int bk_model_set_table_source(bk_model* m, int32_t source)
+{
+    if (!m || (source != BK_TABLE_NETWORK && source != BK_TABLE_SOLVER)) return BK_EINVAL;
+    if (!m->params) return BK_ENOMODEL;
+    m->table_source = source;
     return model_cells(m);
 }
 

@@ -42,3 +42,14 @@ def to_dev(a, dtype=None):
     if dtype is not None:
         t = t.to(dtype)
     return t.cuda()
+
+
+def packed_index(api, n, ts, lower, i, j):
+    """Offsets in the packed tile output of global entries (i, j) (with lower_only,
+    tile row i // ts must be at least tile column j // ts)."""
+    i = np.asarray(i, np.int64)
+    j = np.asarray(j, np.int64)
+    I, J = i // ts, j // ts
+    off = np.array([api.matern_tile_offset(n, ts, lower, int(a), int(b)) for a, b in zip(I, J)], dtype=np.int64)
+    mI = np.minimum(ts, n - I * ts)
+    return off + (i - I * ts) + (j - J * ts) * mI
