@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="matern-large",
                     choices=["matern-large", "grid", "matern-medium", "deriv-grid", "matern-grad-medium", "loglik",
-                             "paper-grid", "small-x", "matern-order"],
+                             "paper-grid", "small-x", "matern-order", "valu-rates"],
                     help="matern-large: the headline (316 x 316 grid, nu = 3.7, FP32 learned vs FP64 plain)")
     ap.add_argument("--forms", default="learned,mixed,plain",
                     help="matern-large: forms to time (comma-separated; the headline needs learned)")
@@ -201,6 +201,9 @@ def main():
     if a.workload == "matern-order":
         matern_order_bench(a, torch, api, workloads)
         return
+    if a.workload == "valu-rates":
+        valu_rates_bench(torch)
+        return
     if a.workload != "grid":
         matern_bench(a, torch, api, workloads)
         return
@@ -310,6 +313,7 @@ def matern_headline(a, torch, api, workloads):
                       write_gbps=elems * out.element_size() / (ms * 1e-3) / 1e9,
                       out_dtype="f32" if odt == api.OUT_F32 else "f64",
                       mean_nodes=nodes_main / max(1, quad_main), node_total_main=nodes_main,
+                      lane_efficiency=nodes_main / max(1, int(st[api.STAT_LANE_SLOTS])),
                       fallbacks=fb, fallback_nodes=int(st[api.STAT_FB_NODES]),
                       node_slots=NODE_SLOTS.get(slot_key),
                       node_work_frac=(NODE_SLOTS[slot_key] * nodes_main / (kms * 1e-3) / 1e12 / VALU_PEAK_TOPS
@@ -399,7 +403,10 @@ def grid_bench(a, torch, api, workloads):
                         mean_nodes=float(st[api.STAT_NODES]) / max(1, int(st[api.STAT_ENTRIES])),
                         node_total=int(st[api.STAT_NODES]),
                         fallbacks=int(st[api.STAT_FB_RANGE] + st[api.STAT_FB_TAIL] + st[api.STAT_FB_NONFINITE]),
-                        nodes_raised=int(st[api.STAT_NODE_RAISED]))
+                        nodes_raised=int(st[api.STAT_NODE_RAISED]),
+                        # share of the node walk's lane slots (64 x a wave's largest N + 1) doing work
+                        lane_efficiency=float(st[api.STAT_NODES] - st[api.STAT_FB_NODES])
+                        / max(1, int(st[api.STAT_LANE_SLOTS])))
     head = forms[form]
 
     # accuracy of the timed forms on a bounded sample against the oracle, and the
@@ -525,12 +532,51 @@ def matern_bench(a, torch, api, workloads):
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / steps
+        st = torch.zeros(api.STATS_LEN, dtype=torch.int64, device=dev)      # counting pass, untimed
+        api.matern_tiles(lx, ly, 1.0, beta, nu, ts, 1, stats=st, **kw)
+        torch.cuda.synchronize()
+        st = st.cpu().numpy()
+        fb = int(st[api.STAT_FB_RANGE] + st[api.STAT_FB_TAIL] + st[api.STAT_FB_NONFINITE])
+        main_nodes = int(st[api.STAT_NODES] - st[api.STAT_FB_NODES])
+        main_ents = int(st[api.STAT_ENTRIES]) - (fb - int(st[api.STAT_FB_RANGE]))
         res["nu=%g/%s" % (nu, f)] = {"ms": round(ms, 3), "entries_per_s": elems / (ms * 1e-3),
                                      "write_gbps": elems * out.element_size() / (ms * 1e-3) / 1e9,
-                                     "out_dtype": str(tdt).replace("torch.", "")}
+                                     "out_dtype": str(tdt).replace("torch.", ""),
+                                     "mean_nodes": main_nodes / max(1, main_ents), "fallbacks": fb,
+                                     "lane_efficiency": main_nodes / max(1, int(st[api.STAT_LANE_SLOTS]))}
     line = {"metric": "Matern entries/s", "workload": a.workload, "n": n, "tile": ts, "entries": elems,
             "beta": beta, "results": res}
     print(json.dumps(line), flush=True)
+
+
+RATE_OPS = ("v_fma_f64", "v_add_f64", "v_mul_f64", "v_fma_f32", "v_add_f32", "v_mul_f32", "v_exp_f32", "v_log_f32",
+            "v_rcp_f32", "v_rcp_f64", "v_sqrt_f32", "v_cvt_f32_f64+v_cvt_f64_f32", "v_max_f32", "v_ldexp_f64",
+            "v_rsq_f64", "v_add_u32")
+
+
+def valu_rates_bench(torch):
+    """Issue rate of single VALU instructions (paper_2502_00356_amd/csrc/valu_rates.hip):
+    eight independent chains per lane, 2^15 workgroups of 256 lanes (2^17 waves), one
+    timed launch per instruction. Reports wave64 instructions per CU-clock (256 CUs at
+    2.4 GHz): 1.0 is one instruction per clock per CU across its four SIMDs."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2502_00356_amd", "libvalurates.so"))
+    f = lib.valu_rate_ms
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]
+    blocks, iters = 1 << 15, 256
+    sink = torch.empty(blocks * 256, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    rates = {}
+    for op, name in enumerate(RATE_OPS):
+        ms = ctypes.c_float(0.0)
+        st = f(op, iters, blocks, ctypes.c_void_p(sink.data_ptr()), ctypes.byref(ms))
+        if st != 0:
+            sys.exit("valu_rate_ms(%d) failed with %d" % (op, st))
+        insts = blocks * 4 * iters * 8 * (2 if op == 11 else 1)      # wave64 instructions
+        rates[name] = round(insts / (ms.value * 1e-3) / (256 * 2.4e9), 3)
+    print(json.dumps({"metric": "VALU wave64 instructions per CU-clock (256 CUs, 2.4 GHz)", "waves": blocks * 4,
+                      "chains_per_lane": 8, "iters": iters, "rates": rates}), flush=True)
 
 
 def _event_ms(torch, fn, steps, warmup):

@@ -82,6 +82,11 @@ enum {
     BK_STAT_FB_NODES = 6,     /* learned: nodes of the entries the fallback launch
                                  recomputed (already counted in BK_STAT_NODES,
                                  as are those entries in BK_STAT_ENTRIES)     */
+    BK_STAT_LANE_SLOTS = 7,   /* main kernel (plain, mixed, learned forms): sum over
+                                 its waves, per group of entries a wave walks side
+                                 by side, of 64 x the largest N + 1 among them: the
+                                 lane-node slots the node walk occupies. Nodes of the
+                                 main kernel / LANE_SLOTS is the share that did work */
     BK_STATS_LEN = 8
 };
 

@@ -22,7 +22,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 PLAIN_F64, MIXED_F32C, LEARNED, PAPER_REFINED = 0, 1, 2, 3
 RESULT_K, RESULT_SCALED, RESULT_LOG = 0, 1, 2
 OUT_F64, OUT_F32 = 0, 1
-STAT_ENTRIES, STAT_NODES, STAT_FB_RANGE, STAT_FB_TAIL, STAT_NODE_RAISED, STAT_FB_NONFINITE, STAT_FB_NODES = range(7)
+STAT_ENTRIES, STAT_NODES, STAT_FB_RANGE, STAT_FB_TAIL, STAT_NODE_RAISED, STAT_FB_NONFINITE, STAT_FB_NODES, \
+    STAT_LANE_SLOTS = range(8)
 STATS_LEN = 8
 MLP_NPARAM = 4547
 TABLE_NETWORK, TABLE_SOLVER = 0, 1

@@ -11,6 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbesselk.so")
+RATES_LIB = os.path.join(HERE, "libvalurates.so")
 SOURCES = ["bk_kernels.hip", "bk_mlp.hip", "bk_mle.hip"]
 # rocSOLVER (Cholesky, triangular solves, inverse) and the rocBLAS handle it runs on
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
@@ -145,6 +146,15 @@ def build(verbose=False, jobs=None):
     os.replace(LIB + ".tmp", LIB)
     for o in objs:
         os.remove(o)
+    # instruction-rate probe behind issue_cost (bench.py --workload valu-rates); its own
+    # library, not part of the K_nu path
+    cmd = [hipcc] + flags + ["-shared", "-o", RATES_LIB + ".tmp", os.path.join(CSRC, "valu_rates.hip")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    p = subprocess.run(cmd, stderr=subprocess.PIPE, stdout=subprocess.PIPE)
+    if p.returncode != 0:
+        raise RuntimeError("HIP build of valu_rates.hip failed:\n" + p.stderr.decode())
+    os.replace(RATES_LIB + ".tmp", RATES_LIB)
     # node-loop issue slots of this build, for the benchmark's roofline accounting
     try:
         import json

@@ -64,5 +64,9 @@ int bk_besselk_learned(const double* nu, const double* x, double* out, int64_t n
 size_t matern_learned_workspace_bytes(int64_t n, int32_t tile_size, int32_t lower_only);
 int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_size, int32_t lower_only,
                       void* out, double L, double Lq, void* workspace, size_t workspace_bytes, hipStream_t stream);
+// bk_matern_tiles with the learned form's workspace given explicitly (the caller's,
+// or the no-allocation entry point's static scratch).
+int matern_tiles_dispatch(const bk_locs* locs, const bk_params* prm, int32_t tile_size, int32_t lower_only,
+                          void* out, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 }  // namespace bk

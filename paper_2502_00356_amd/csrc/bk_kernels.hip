@@ -54,6 +54,13 @@ __device__ inline void wave_count(unsigned long long* dst, unsigned int v)
     if ((threadIdx.x & 63) == 0 && a) atomicAdd(dst, a);
 }
 
+// Largest per-lane value over a wave (every lane active).
+__device__ inline unsigned int wave_max_u32(unsigned int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned int)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
 // Special values shared by every form; returns true if handled.
 __device__ __forceinline__ bool special_value(double v, double z, int result, double& r)
 {
@@ -194,6 +201,8 @@ __global__ __launch_bounds__(kSolveBlock) __attribute__((amdgpu_waves_per_eu(6, 
     if (stats) {
         block_count_w(stats + BK_STAT_NODES, nodes, kSolveBlock / 64);
         block_count_w(stats + BK_STAT_ENTRIES, ents, kSolveBlock / 64);
+        const unsigned int wmax = wave_max_u32((unsigned int)nodes);
+        block_count_w(stats + BK_STAT_LANE_SLOTS, (threadIdx.x & 63) == 0 ? 64ull * wmax : 0ull, kSolveBlock / 64);
     }
 }
 
@@ -392,6 +401,7 @@ __global__ __launch_bounds__(256, 4) void k_matern(const double* __restrict__ lx
     const double xi = lx[I * g.ts + ilr], yi = ly[I * g.ts + ilr];
     const int cend = (kStats && !row_ok) ? 0 : (int)min((int64_t)kColsPerWave, nJ - jl0);
     unsigned int c_ent = 0, c_nodes = 0;
+    unsigned int col_nodes[kColsPerWave] = {};      // statistics: nodes per column walked
     for (int c = 0; c < cend; ++c) {
         const int64_t jl = jl0 + c;
         const double xj = lx[J * g.ts + jl], yj = ly[J * g.ts + jl];
@@ -410,6 +420,7 @@ __global__ __launch_bounds__(256, 4) void k_matern(const double* __restrict__ lx
                     val = sigma2 * exp(pref + nu * log(z) + f.lscale) * f.hs;
                     c_nodes += (unsigned int)(bins + 1);
                     c_ent += 1;
+                    if (kStats) col_nodes[c] = (unsigned int)(bins + 1);
                 }
             } else {
                 Solved s = plain_solve(nu, z, L, Lq, rule_tab(), s_tab);
@@ -423,6 +434,7 @@ __global__ __launch_bounds__(256, 4) void k_matern(const double* __restrict__ lx
                 val = sigma2 * exp(pref + nu * log(z) + (s.delta - z)) * hs;
                 c_nodes += (unsigned int)(s.p.N + 1);
                 c_ent += 1;
+                if (kStats) col_nodes[c] = (unsigned int)(s.p.N + 1);
             }
         }
         out[base + il + jl * mI] = (OutT)val;
@@ -430,6 +442,10 @@ __global__ __launch_bounds__(256, 4) void k_matern(const double* __restrict__ lx
     if (kStats) {
         wave_count(stats + BK_STAT_ENTRIES, c_ent);
         wave_count(stats + BK_STAT_NODES, c_nodes);
+        unsigned int slots = 0;
+#pragma unroll
+        for (int c = 0; c < kColsPerWave; ++c) slots += 64u * wave_max_u32(col_nodes[c]);
+        wave_count(stats + BK_STAT_LANE_SLOTS, (threadIdx.x & 63) == 0 ? slots : 0u);
     }
 }
 
@@ -633,8 +649,10 @@ static int launch_matern(const bk_locs* locs, const bk_params* prm, const TileGe
     return mark_kernel_event(prm, 1, stream) == hipSuccess ? BK_OK : BK_EHIP;
 }
 
-extern "C" int bk_matern_tiles(const bk_locs* locs, const bk_params* prm, int32_t tile_size,
-                               int32_t lower_only, void* out, hipStream_t stream)
+namespace bk {
+
+int matern_tiles_dispatch(const bk_locs* locs, const bk_params* prm, int32_t tile_size, int32_t lower_only,
+                          void* out, void* workspace, size_t workspace_bytes, hipStream_t stream)
 {
     if (!locs || !prm || tile_size <= 0 || locs->n < 0) return BK_EINVAL;
     if (!(prm->beta > 0.0) || !(prm->nu > 0.0) || !(prm->sigma2 >= 0.0) || isinf(prm->nu) || isinf(prm->beta))
@@ -663,8 +681,7 @@ extern "C" int bk_matern_tiles(const bk_locs* locs, const bk_params* prm, int32_
         return f32 ? launch_matern<BK_MIXED_F32C, float>(locs, prm, g, ntiles, L, Lq, out, stream)
                    : launch_matern<BK_MIXED_F32C, double>(locs, prm, g, ntiles, L, Lq, out, stream);
     case BK_LEARNED:
-        return bk_matern_learned(locs, prm, tile_size, lower_only, out, L, Lq, prm->workspace, prm->workspace_bytes,
-                                 stream);
+        return bk_matern_learned(locs, prm, tile_size, lower_only, out, L, Lq, workspace, workspace_bytes, stream);
     case BK_PAPER_REFINED:
         if (prm->bins < 0 || prm->bins > 100000 || prm->t_upper < 0.0) return BK_EINVAL;
         return f32 ? launch_matern<BK_PAPER_REFINED, float>(locs, prm, g, ntiles, L, Lq, out, stream)
@@ -672,6 +689,16 @@ extern "C" int bk_matern_tiles(const bk_locs* locs, const bk_params* prm, int32_
     default:
         return BK_EINVAL;
     }
+}
+
+}  // namespace bk
+
+extern "C" int bk_matern_tiles(const bk_locs* locs, const bk_params* prm, int32_t tile_size,
+                               int32_t lower_only, void* out, hipStream_t stream)
+{
+    if (!prm) return BK_EINVAL;
+    return matern_tiles_dispatch(locs, prm, tile_size, lower_only, out, prm->workspace, prm->workspace_bytes,
+                                 stream);
 }
 
 // Digamma psi(v), v > 0, on the host in long double: shift up with

@@ -542,6 +542,15 @@ __device__ __forceinline__ WalkF walkf_begin_exp(double nu, double x, double t0,
 
 __device__ __forceinline__ double walkf_exponent2(const WalkF& w) { return fma(w.a2, w.c, w.e); }
 
+// The same step without the FP64 factor Q (kept elsewhere).
+__device__ __forceinline__ void walkf_step_noq(WalkF& w)
+{
+    const double c2n = fma(w.kappa, w.cn, -w.c);
+    w.c = w.cn;
+    w.cn = c2n;
+    w.e += w.b2;
+}
+
 __device__ __forceinline__ void walkf_step(WalkF& w)
 {
     const double c2n = fma(w.kappa, w.cn, -w.c);

@@ -17,9 +17,10 @@
 // raised if needed to what the strip bound asks for the predicted window (one
 // half-width, in FP32), so the step is always admissible. An entry is accepted
 // only if (a) it lies inside the model's training box and (b) the integral beyond
-// each end of the window, bounded through the concavity of g from the two end
-// nodes, is below a tolerance; otherwise it is recomputed with the plain FP64
-// solver and FP32-compensated node terms.
+// each end of the window, bounded from the two end nodes (g is concave right of an
+// inflection point that lies left of the peak; the convex piece near t = 0 is
+// bounded separately), is below a tolerance; otherwise it is recomputed with the
+// plain FP64 solver and FP32-compensated node terms.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -372,8 +373,75 @@ __device__ inline LearnedPlan learned_plan(double tlo, double thi, int N, const 
 // largest node's exponent, from the cell), so every FP32 exponential sees an argument
 // of moderate size and the 2^k 2^f split is not needed; the prefactor carries 2^eb.
 // Else the split is made at every node.
-template <bool kBias>
-__device__ inline LearnedOut learned_walk(double x, const LearnedPlan& P, double eb = 0.0)
+// Node sum of the learned forms (terms relative to node 0, or to the plan's peak
+// node with kBias). kQf: the factor 1 + e^(-2 nu t) of a node is carried in FP32 as
+// P = e^(-2 nu t) (P' = rho P), the term formed as e + e P with one rounding. Each
+// step rounds P by 2^-24 relative and rho in FP32 is off by up to 2^-24, so P_m is
+// off by m 2^-23 relative, and the term by m 2^-23 P_m / (1 + P_m) <= 2^-23 m rho^m
+// <= 2^-23 / (e ln(1 / rho)); with 2 nu h >= 1/2 (rho <= e^-1/2) that is below 9e-8.
+// Otherwise (kQf false) the factor follows Q' = rho Q + (1 - rho) in FP64 and is
+// rounded to FP32 once per node.
+template <bool kBias, bool kQf>
+__device__ inline void learned_sum(WalkF& w, int N, float Pf, float rhof, float& e0, float& e1, float& eprev,
+                                   float& elast, double& Sd)
+{
+    // the exponent is not bounded above without the bias (t_lo is not the peak), so
+    // the FP32 exponential is split as 2^k 2^f with k, f formed in FP64; the FP32
+    // terms are summed in FP64, whose rounding is negligible next to theirs.
+    // With the bias, an argument d converts to FP32 with an absolute error of
+    // |d| 2^-24; the terms that carry the sum lie within a few units of eb, the
+    // others are smaller by 2^-|d|, so this adds a few 1e-8 to the sum.
+    auto node = [&]() {
+        const double d = walkf_exponent2(w);
+        float t;
+        if constexpr (kQf) {
+            const float ex = __builtin_amdgcn_exp2f((float)d);
+            t = fmaf(ex, Pf, ex);
+            Pf *= rhof;
+            walkf_step_noq(w);
+        } else {
+            if (kBias) {
+                t = __builtin_amdgcn_exp2f((float)d) * (float)w.Q;
+            } else {
+                const double kf = rint(d);
+                t = ldexpf(__builtin_amdgcn_exp2f((float)(d - kf)) * (float)w.Q, (int)kf);
+            }
+            walkf_step(w);
+        }
+        return t;
+    };
+    // Nodes go in groups of four: a group is added pairwise in FP32 (two roundings,
+    // <= 1.2e-7 of the group, all terms positive) and the groups sum in FP64.
+    e0 = node();
+    e1 = node();                               // N >= kNodeMin: at least five nodes
+    Sd = (double)(e0 + e1);
+    eprev = e0;
+    elast = e1;
+    int m = 2;
+    for (; m + 3 <= N; m += 4) {
+        const float ta = node(), tb = node(), tc = node(), td = node();
+        Sd += (double)((ta + tb) + (tc + td));
+        eprev = tc;
+        elast = td;
+    }
+    if (m + 1 <= N) {
+        const float ta = node(), tb = node();
+        Sd += (double)(ta + tb);
+        eprev = ta;
+        elast = tb;
+        m += 2;
+    }
+    if (m == N) {                               // one node left
+        const float t = node();
+        Sd += (double)t;
+        eprev = elast;
+        elast = t;
+    }
+}
+
+// kQfOk: the caller allows the FP32 node factor (taken where 2 nu h >= 1/2).
+template <bool kBias, bool kQfOk = false>
+__device__ inline LearnedOut learned_walk(double x, double nu, const LearnedPlan& P, double eb = 0.0)
 {
     LearnedOut o;
     o.reason = 0;
@@ -394,57 +462,80 @@ __device__ inline LearnedOut learned_walk(double x, const LearnedPlan& P, double
     w.rho = P.rho;
     w.omr = 1.0 - P.rho;
     w.Q = P.Q0;
-    // the exponent is not bounded above here (t_lo is not the peak), so the FP32
-    // exponential is split as 2^k 2^f with k, f formed in FP64; the FP32 terms are
-    // summed in FP64, whose rounding is negligible next to theirs
-    // With the bias, an argument d converts to FP32 with an absolute error of
-    // |d| 2^-24; the terms that carry the sum lie within a few units of eb, the
-    // others are smaller by 2^-|d|, so this adds a few 1e-8 to the sum.
-    auto node = [&]() {
-        const double d = walkf_exponent2(w);
-        float t;
-        if (kBias) {
-            t = __builtin_amdgcn_exp2f((float)d) * (float)w.Q;
-        } else {
-            const double kf = rint(d);
-            t = ldexpf(__builtin_amdgcn_exp2f((float)(d - kf)) * (float)w.Q, (int)kf);
-        }
-        walkf_step(w);
-        return t;
-    };
-    // Nodes go in pairs: a pair is added in FP32 (one rounding, <= 6e-8 of the pair)
-    // and the pair sums in FP64.
-    const float e0 = node(), e1 = node();      // N >= kNodeMin: at least five nodes
-    double Sd = (double)(e0 + e1);
-    float eprev = e0, elast = e1;
-    int m = 2;
-    for (; m + 1 <= N; m += 2) {
-        const float ta = node(), tb = node();
-        Sd += (double)(ta + tb);
-        eprev = ta;
-        elast = tb;
-    }
-    if (m == N) {                               // odd node count left one node
-        const float t = node();
-        Sd += (double)t;
-        eprev = elast;
-        elast = t;
-    }
+    float e0, e1, eprev, elast;
+    double Sd;
+    if (kQfOk && P.b2 >= 0.25 * kLog2e)        // b2 = nu h log2 e: 2 nu h >= 1/2
+        learned_sum<kBias, kQfOk>(w, N, (float)(P.Q0 - 1.0), (float)P.rho, e0, e1, eprev, elast, Sd);
+    else
+        learned_sum<kBias, false>(w, N, 0.0f, 0.0f, e0, e1, eprev, elast, Sd);
     Sd -= 0.5 * ((double)e0 + (double)elast);
     o.hs = h * Sd;
     if (!(Sd > 0.0) || !isfinite(Sd)) { o.reason = BK_STAT_FB_NONFINITE; return o; }
     const float S = (float)Sd;
-    // Tails beyond the ends. Right of the peak g is concave, so past the last node
-    // the integrand lies below the exponential with slope g'(t_N), and the tail
-    // integral is at most f(t_N) / |g'(t_N)|; the secant slope of the last two
-    // nodes is no steeper than g'(t_N), so using it keeps the bound. In units of
-    // the sum S (integral / h): e_N / |log(e_N / e_{N-1})|. The same bound on the
-    // left (g concave where nu t is not small) is e_0 / log(e_1 / e_0).
+    // Tails beyond the ends, in units of the sum S (integral / h). g = log cosh(nu t)
+    // - x cosh t has g'' = nu^2 sech^2(nu t) - x cosh t, decreasing in t: g is convex
+    // on [0, t_c) and concave on [t_c, inf) (t_c = 0 if nu^2 <= x), and g' > 0 on
+    // (0, t_c], so the peak t* lies right of t_c.
+    // Right: if e_N < e_{N-1}, the mean value theorem puts a point xi > t* in
+    // (t_{N-1}, t_N) where g'(xi) is the secant slope; g' decreases right of t_c, so
+    // |g'| >= |secant| on [t_N, inf) and the tail is at most e_N / |log(e_N / e_{N-1})|.
     const float lr = __builtin_amdgcn_logf(elast * __builtin_amdgcn_rcpf(eprev)) * 0.69314718f;
     if (!(elast < eprev) || elast > -lr * kTailTol * S) { o.reason = BK_STAT_FB_TAIL; return o; }
     if (tlo > 0.0) {
+        // Left (t_lo > 0, e_0 < e_1, so t_lo < t*). t_c is the fixed point of the
+        // decreasing map F(t) = acosh(nu / sqrt(x cosh t)) / nu (0 where the argument is
+        // <= 1), so F(0) >= t_c, and alternate iterates from there bound t_c from below
+        // and above: lo <= t_c <= up (each FP32 value moved outward by 2^-10 relative,
+        // far above its rounding). F(0) alone settles most windows (t_lo >= F(0));
+        // the others take two more pairs of iterates.
+        // D = g(t_lo) - g(0) >= Delta = nu t_lo - ln 2 - x (cosh t_lo - 1) (the
+        // log(1 + e^(-2 nu t_lo)) part is dropped), and ll = log(e_1 / e_0) = s h, s the
+        // secant slope of the first two nodes.
+        //  - t_lo >= up: as on the right, g'(t) >= s on [t_c, t_lo], so g lies below the
+        //    line through t_lo of slope s there; on [0, up] g is below the chord from
+        //    (0, g(0)) to (up, line(up)) (convex up to t_c, and the line bounds the rest),
+        //    so the tail is at most e_0 (1 / ll + (up / h) (e^a - e^b) / (a - b)),
+        //    a = -ll (t_lo - up) / h, b = -D.
+        //  - t_lo <= lo: g is convex on [0, t_lo], below its chord, and the tail is at
+        //    most e_0 (t_lo / h) (1 - e^-D) / D.
+        //  - otherwise the window is rejected.
         const float ll = __builtin_amdgcn_logf(e1 * __builtin_amdgcn_rcpf(e0)) * 0.69314718f;
-        if (!(e0 < e1) || e0 > ll * kTailTol * S) { o.reason = BK_STAT_FB_TAIL; return o; }
+        if (!(e0 < e1)) { o.reason = BK_STAT_FB_TAIL; return o; }
+        const float nuf = (float)nu, xf = (float)x, inu = __builtin_amdgcn_rcpf(nuf);
+        auto F = [&](float t, float ch) {           // ch = cosh t
+            const float y = nuf * __builtin_amdgcn_rsqf(xf * ch);
+            if (!(y > 1.0f)) return 0.0f;
+            return __builtin_amdgcn_logf(y + __builtin_amdgcn_sqrtf(fmaf(y, y, -1.0f))) * 0.69314718f * inu;
+        };
+        auto coshf_ = [](float t) {
+            const float e = __builtin_amdgcn_exp2f(t * 1.44269504f);
+            return 0.5f * (e + __builtin_amdgcn_rcpf(e));
+        };
+        const float tlof = (float)tlo, ih = (float)(1.0 / h);
+        float up = F(0.0f, 1.0f) * 1.0009765625f, lo = 0.0f;
+        if (!(tlof >= up)) {                        // t_lo near t_c: narrow the bounds
+            lo = F(up, coshf_(up)) * 0.9990234375f;
+            up = fminf(up, F(lo, coshf_(lo)) * 1.0009765625f);
+            lo = fmaxf(lo, F(up, coshf_(up)) * 0.9990234375f);
+            up = fminf(up, F(lo, coshf_(lo)) * 1.0009765625f);
+        }
+        const float D = fmaxf((float)(kBias ? fma(-eb, kLn2, o.delta) : o.delta), 0.0f);
+        float bound;
+        if (tlof >= up) {
+            const float a = -ll * (tlof - up) * ih, b = -D, dab = a - b;
+            const float ea = __builtin_amdgcn_exp2f(a * 1.44269504f), eb2 = __builtin_amdgcn_exp2f(b * 1.44269504f);
+            // mean of e^t between b and a (at most the larger end value)
+            const float chord = fabsf(dab) > 1e-3f ? (ea - eb2) * __builtin_amdgcn_rcpf(dab) : fmaxf(ea, eb2);
+            bound = e0 * (__builtin_amdgcn_rcpf(ll) + up * ih * chord);
+        } else if (tlof <= lo) {
+            const float r = D > 1e-3f ? (1.0f - __builtin_amdgcn_exp2f(-D * 1.44269504f)) * __builtin_amdgcn_rcpf(D)
+                                      : 1.0f;       // (1 - e^-D) / D <= 1
+            bound = e0 * tlof * ih * r;
+        } else {
+            o.reason = BK_STAT_FB_TAIL;
+            return o;
+        }
+        if (!(bound <= kTailTol * S)) { o.reason = BK_STAT_FB_TAIL; return o; }
     }
     return o;
 }
@@ -554,6 +645,22 @@ __device__ __forceinline__ double scaled_exp(double r, double c)
     const double y = r * kLog2e;
     const double k = rint(y);
     return ldexp((double)__builtin_amdgcn_exp2f((float)(y - k)) * c, (int)k);
+}
+
+// c e^r as scaled_exp, rounded to the output type. For FP32 output the product
+// 2^f c and the scaling by 2^k are taken in FP32 (two roundings, <= 1.2e-7, and a
+// correctly rounded subnormal result where C lies below the FP32 normal range).
+template <typename OutT>
+__device__ __forceinline__ OutT scaled_exp_out(double r, double c)
+{
+    if constexpr (sizeof(OutT) == sizeof(float)) {
+        if (!(c > 1e-30 && c < 1e30)) return (float)scaled_exp(r, c);   // c itself far from FP32's range
+        const double y = r * kLog2e;
+        const double k = rint(y);
+        return ldexpf(__builtin_amdgcn_exp2f((float)(y - k)) * (float)c, (int)k);
+    } else {
+        return scaled_exp(r, c);
+    }
 }
 
 // Final value for the FP32-term forms: c = h S times e^(Delta - z) (or e^Delta).
@@ -727,9 +834,9 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
         if constexpr (kPlan) {
             // log2 of the term at the cell's peak node t_pk relative to node 0, at this entry
             const double eb = (vs * ((double)(Np >> 16) * P.h) - zs * s_thi[tid]) * kLog2e;
-            lo = learned_walk<true>(zs, P, eb);
+            lo = learned_walk<true>(zs, vs, P, eb);
         } else {
-            lo = learned_walk<false>(zs, P);
+            lo = learned_walk<false>(zs, vs, P);
         }
         c_nodes = (unsigned int)(Ns + 1);
         c_ent = 1;
@@ -742,14 +849,18 @@ __global__ __launch_bounds__(kLearnedBlock, 5) void k_besselk_learned(MlpDev M, 
         }
     }
     if (stats) {
-        unsigned long long cnt[6];
+        unsigned long long cnt[8];
         cnt[BK_STAT_ENTRIES] = c_ent;
         cnt[BK_STAT_NODES] = c_nodes;
         cnt[BK_STAT_FB_RANGE] = c_range;
         cnt[BK_STAT_FB_TAIL] = c_tail;
         cnt[BK_STAT_NODE_RAISED] = c_raised;
         cnt[BK_STAT_FB_NONFINITE] = c_nonfin;
-        block_stats_w(stats, cnt, 6, kLearnedBlock / 64);
+        cnt[BK_STAT_FB_NODES] = 0;
+        unsigned int wmax = c_nodes;
+        for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, (unsigned int)__shfl_xor((int)wmax, o, 64));
+        cnt[BK_STAT_LANE_SLOTS] = (threadIdx.x & 63) == 0 ? 64ull * wmax : 0ull;
+        block_stats_w(stats, cnt, 8, kLearnedBlock / 64);
     }
 }
 
@@ -881,19 +992,15 @@ __global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, doubl
     pb[3 * k + 2] = b2;
 }
 
-// log(1 + u) for |u| <= 0.02 by its Taylor series through u^9 (truncation below
-// 2e-17 relative).
-__device__ __forceinline__ double log1p_small(double u)
+// log(1 + u) for |u| <= 0.02 in FP32, by its Taylor series through u^4: the
+// truncation is below u^5 / 5 < 7e-10 and the FP32 rounding of u and of the
+// series about 2^-24 |u| < 1.2e-9, absolute. The learned Matern kernel multiplies
+// it by nu, so an order nu moves C by about nu 2e-9 relative (2e-8 at nu = 10).
+__device__ __forceinline__ float log1p_small_f(float u)
 {
-    double p = 1.0 / 9.0;
-    p = fma(p, -u, 1.0 / 8.0);
-    p = fma(p, -u, 1.0 / 7.0);
-    p = fma(p, -u, 1.0 / 6.0);
-    p = fma(p, -u, 1.0 / 5.0);
-    p = fma(p, -u, 1.0 / 4.0);
-    p = fma(p, -u, 1.0 / 3.0);
-    p = fma(p, -u, 1.0 / 2.0);
-    p = fma(p, -u, 1.0);
+    float p = fmaf(u, -0.25f, 0.333333333f);
+    p = fmaf(p, u, -0.5f);
+    p = fmaf(p, u, 1.0f);
     return p * u;
 }
 
@@ -974,6 +1081,7 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
     const bool nu_ok = (float)nu >= M.nu_lo && (float)nu <= M.nu_hi;
     bool rejected = false;
     unsigned int c_ent = 0, c_nodes = 0, c_range = 0, c_tail = 0, c_nonfin = 0, c_raised = 0;
+    unsigned int col_nodes[kColsPerWave] = {};      // statistics: nodes per column walked
     for (int c = 0; c < cend; ++c) {
         const int64_t jl = jl0 + c;
         const double dx = lx_[J * g.ts + jl] - xi, dy = ly_[J * g.ts + jl] - yi;
@@ -990,7 +1098,7 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
         } else {
             rr = sqrt(r2);
         }
-        double val = sigma2;
+        OutT val = (OutT)sigma2;
         if (rr != 0.0) {
             const double z = rr * inv_beta;
             const float lz = __log2f((float)z) * 0.30102999566f;
@@ -1017,31 +1125,33 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
                     P.b2 = b1[2];
                     P.dnu = b1[3];
                     const double eb = fma(-z, b2[3], b2[2]);
-                    LearnedOut lo = learned_walk<true>(z, P, eb);
+                    LearnedOut lo = learned_walk<true, true>(z, nu, P, eb);
                     ok = lo.reason == 0;
                     if (kStats) {
                         c_ent += 1;
                         c_nodes += (unsigned int)(N + 1);
+                        col_nodes[c] = (unsigned int)(N + 1);
                         c_tail += lo.reason == BK_STAT_FB_TAIL ? 1u : 0u;
                         c_nonfin += lo.reason == BK_STAT_FB_NONFINITE ? 1u : 0u;
                     }
                     hs = lo.hs;
                     // pref + nu log z + Delta - z = K + nu log(z / z_k) - z cosh t_lo, and
                     // the walk's bias eb ln 2
-                    lexp = fma(nu, log1p_small(fma(z, b2[1], -1.0)), fma(-z, P.c0, fma(eb, kLn2, b2[0])));
+                    lexp = fma(nu, (double)log1p_small_f((float)fma(z, b2[1], -1.0)),
+                               fma(-z, P.c0, fma(eb, kLn2, b2[0])));
                 } else {
                     ok = false;
                     if (kStats) c_nonfin += 1;
                 }
             }
             if (ok) {
-                val = scaled_exp(lexp, sigma2 * hs);
+                val = scaled_exp_out<OutT>(lexp, sigma2 * hs);
             } else {
-                val = __builtin_nan("");
+                val = (OutT)__builtin_nan("");
                 rejected = true;
             }
         }
-        out[base + il + jl * mI] = (OutT)val;
+        out[base + il + jl * mI] = val;
     }
     // lane 0 is active whenever any lane of the wave is (rows grow with the lane)
     if (__ballot(rejected) != 0ull && lane == 0) {
@@ -1055,6 +1165,14 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
         wave_count_l(stats + BK_STAT_FB_TAIL, c_tail);
         wave_count_l(stats + BK_STAT_FB_NONFINITE, c_nonfin);
         wave_count_l(stats + BK_STAT_NODE_RAISED, c_raised);
+        unsigned int slots = 0;
+#pragma unroll
+        for (int c = 0; c < kColsPerWave; ++c) {
+            unsigned int v = col_nodes[c];
+            for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned int)__shfl_xor((int)v, o, 64));
+            slots += 64u * v;
+        }
+        wave_count_l(stats + BK_STAT_LANE_SLOTS, (threadIdx.x & 63) == 0 ? slots : 0u);
     }
 }
 

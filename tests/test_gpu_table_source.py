@@ -75,7 +75,7 @@ def test_solver_tables_meet_the_bar(api, orc):
     from paper_2502_00356_amd import workloads as w
     m = _model(api, api.TABLE_SOLVER, True)
     nu, x = w.eval_pairs(1 << 15, seed=5)
-    _, kref, ksref = orc.besselk(nu, x)
+    kref, _, ksref = orc.besselk(nu, x)
     got = api.besselk(to_dev(nu), to_dev(x), mode="learned", model=m)
     gs = api.besselk(to_dev(nu), to_dev(x), mode="learned", model=m, result=api.RESULT_SCALED)
     torch.cuda.synchronize()
@@ -100,7 +100,7 @@ def test_network_against_solver_tables_standalone(api, orc):
     nu, x = w.eval_pairs(1 << 22, seed=5)
     dnu, dx = to_dev(nu), to_dev(x)
     idx = np.random.default_rng(0).choice(nu.size, 1 << 13, replace=False)
-    kref = orc.besselk(nu[idx], x[idx])[1]
+    kref = orc.besselk(nu[idx], x[idx])[0]
     rows = []
     for name, src, zero in VARIANTS:
         m = _model(api, getattr(api, src), zero)
@@ -138,7 +138,7 @@ def test_network_against_solver_tables_matern(api, orc):
         torch.cuda.synchronize()
         st = stats.cpu().numpy()
         got = out.cpu().numpy()[pidx].astype(np.float64)
-        assert rel_err(got, ref).max() <= TOL_MIXED, name
+        assert rel_err(got, ref).max() <= TOL_MIXED + 2.0 ** -24, name      # FP32 output
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
         for a, b in ev:
             a.record()
