@@ -189,6 +189,25 @@ int bk_matern_tiles(const bk_locs* locs, const bk_params* params, int32_t tile_s
  * sizes are invalid. */
 size_t bk_matern_workspace_bytes(int64_t n, int32_t tile_size, int32_t lower_only);
 
+/* bk_matern_tiles for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation, output and arguments, but the learned form's workspace comes from a
+ * static device array inside the library, BK_NOALLOC_SCRATCH_BYTES per GPU, set up
+ * on the first call on each device and held until the process ends.
+ * params->workspace and params->workspace_bytes are ignored. The forms other than
+ * BK_LEARNED use no workspace and behave exactly as bk_matern_tiles.
+ * Limits and errors: BK_ENOMEM if bk_matern_workspace_bytes(n, tile_size,
+ * lower_only) exceeds BK_NOALLOC_SCRATCH_BYTES (about 1.6e10 stored entries with
+ * 1,024-tiles; the 316 x 316-point lower-tile build needs 1.4 MiB); BK_EINVAL if a
+ * non-NULL stream belongs to another device than the current one; otherwise the
+ * statuses of bk_matern_tiles.
+ * No call allocates or frees memory. Every call on one GPU uses that GPU's one
+ * array (each call clears what it needs), so calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller. */
+#define BK_NOALLOC_SCRATCH_BYTES (4u << 20)
+int bk_matern_tiles_noalloc(const bk_locs* locs, const bk_params* params, int32_t tile_size,
+                            int32_t lower_only, void* out, hipStream_t stream);
+
 /* Number of output elements bk_matern_tiles writes (host computation). */
 int64_t bk_matern_out_elems(int64_t n, int32_t tile_size, int32_t lower_only);
 

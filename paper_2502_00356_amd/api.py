@@ -67,6 +67,8 @@ _besselk_ex = _sig("bk_besselk_ex", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.P
 _ws_bytes = _sig("bk_workspace_bytes", ctypes.c_size_t, [_i64])
 _mws_bytes = _sig("bk_matern_workspace_bytes", ctypes.c_size_t, [_i64, _i32, _i32])
 _matern = _sig("bk_matern_tiles", ctypes.c_int, [ctypes.POINTER(Locs), ctypes.POINTER(Params), _i32, _i32, _vp, _vp])
+_matern_noalloc = _sig("bk_matern_tiles_noalloc", ctypes.c_int,
+                      [ctypes.POINTER(Locs), ctypes.POINTER(Params), _i32, _i32, _vp, _vp])
 _out_elems = _sig("bk_matern_out_elems", _i64, [_i64, _i32, _i32])
 _tile_off = _sig("bk_matern_tile_offset", _i64, [_i64, _i32, _i32, _i32, _i32])
 _window = _sig("bk_window", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _dbl, _dbl, _vp])
@@ -250,6 +252,29 @@ def matern_tiles(lx, ly, sigma2, beta, nu, tile_size, lower_only, mode="plain", 
         p.kernel_events[0] = kernel_events[0].cuda_event
         p.kernel_events[1] = kernel_events[1].cuda_event
     _check(_matern(ctypes.byref(locs), ctypes.byref(p), int(tile_size), int(lower_only), op, _stream(stream)))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 4 << 20
+
+
+def matern_tiles_noalloc(lx, ly, sigma2, beta, nu, tile_size, lower_only, out, mode="learned", out_dtype=OUT_F32,
+                         model=None, L_window=0.0, L_quad=0.0, stream=None, stats=None):
+    """bk_matern_tiles_noalloc: tiled Matern covariance into the caller's packed
+    output, the learned form's workspace taken from the library's static device
+    scratch (no allocation in the library or here)."""
+    n = lx.numel()
+    if ly.numel() != n:
+        raise ValueError("lx and ly differ in size")
+    elems = matern_out_elems(n, tile_size, lower_only)
+    dt = torch.float32 if int(out_dtype) == OUT_F32 else torch.float64
+    op = _dev(out, dt, max(elems, 0))
+    locs = Locs(x=_dev(lx, torch.float64), y=_dev(ly, torch.float64), n=n)
+    p = Params(mode=_mode(mode), out_dtype=int(out_dtype), sigma2=float(sigma2), beta=float(beta), nu=float(nu),
+               L_window=float(L_window), L_quad=float(L_quad),
+               model=(model.handle if model is not None else None), stats=_stats(stats))
+    _check(_matern_noalloc(ctypes.byref(locs), ctypes.byref(p), int(tile_size), int(lower_only), op,
+                           _stream(stream)))
     return out
 
 

@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <random>
 #include <vector>
 
@@ -1645,6 +1646,56 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
 // ---------------------------------------------------------------------------
 // C ABI: model, training and MLP primitives
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// No-allocation learned Matern: the workspace of bk_matern_tiles' learned form
+// (window table, interval plans, wave bitmap) lives in a static device array, one
+// copy per GPU, held until the process ends. Host code never passes the array's
+// name to a kernel: its address on each device comes from hipGetSymbolAddress,
+// taken once per device with that device current.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[BK_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of this device's scratch (set up on the first call on the device).
+int scratch_for_current_device(void** ptr)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return BK_EHIP;
+    if (dev < 0 || dev >= kMaxScratchDevices) return BK_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return BK_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return BK_OK;
+}
+}  // namespace
+
+extern "C" int bk_matern_tiles_noalloc(const bk_locs* locs, const bk_params* prm, int32_t tile_size,
+                                       int32_t lower_only, void* out, hipStream_t stream)
+{
+    if (!locs || !prm || tile_size <= 0 || locs->n < 0) return BK_EINVAL;
+    if (prm->mode != BK_LEARNED || locs->n == 0)     // the other forms use no workspace
+        return matern_tiles_dispatch(locs, prm, tile_size, lower_only, out, nullptr, 0, stream);
+    const size_t need = matern_learned_workspace_bytes(locs->n, tile_size, lower_only);
+    if (need == 0 || need > (size_t)BK_NOALLOC_SCRATCH_BYTES) return BK_ENOMEM;
+    if (stream) {                // the scratch address is per device: the stream must be the current device's
+        int dev = -1, sdev = -1;
+        if (hipGetDevice(&dev) != hipSuccess || hipStreamGetDevice(stream, &sdev) != hipSuccess) return BK_EHIP;
+        if (dev != sdev) return BK_EINVAL;
+    }
+    void* ws = nullptr;
+    const int st = scratch_for_current_device(&ws);
+    if (st != BK_OK) return st;
+    return matern_tiles_dispatch(locs, prm, tile_size, lower_only, out, ws, (size_t)BK_NOALLOC_SCRATCH_BYTES, stream);
+}
+
 extern "C" size_t bk_workspace_bytes(int64_t n)
 {
     return 256 + (size_t)(n > 0 ? n : 0) * sizeof(unsigned int);

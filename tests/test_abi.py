@@ -77,6 +77,32 @@ def test_argument_validation_is_host_side(lib):
     assert m(ctypes.byref(locs0), ctypes.byref(q), 4, 1, None, None) == 0
 
 
+def test_noalloc_entry_point_validates_on_host(lib):
+    """bk_matern_tiles_noalloc: the argument checks of bk_matern_tiles, and a call
+    whose learned-form workspace would not fit the static scratch returns BK_ENOMEM
+    before any device work (runs without a GPU)."""
+    from paper_2502_00356_amd import api
+    f = lib.bk_matern_tiles_noalloc
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.POINTER(api.Locs), ctypes.POINTER(api.Params), ctypes.c_int32, ctypes.c_int32,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    q = api.Params(mode=api.LEARNED, sigma2=1.0, beta=0.1, nu=1.0)
+    locs = api.Locs(x=ctypes.c_void_p(16), y=ctypes.c_void_p(16), n=10)
+    assert f(None, ctypes.byref(q), 4, 1, ctypes.c_void_p(16), None) == 1                  # null locs
+    assert f(ctypes.byref(locs), None, 4, 1, ctypes.c_void_p(16), None) == 1               # null params
+    assert f(ctypes.byref(locs), ctypes.byref(q), 0, 1, ctypes.c_void_p(16), None) == 1    # tile size 0
+    assert f(ctypes.byref(api.Locs(x=None, y=None, n=0)), ctypes.byref(q), 4, 1, None, None) == 0
+    n, ts = 2_000_000, 64
+    assert api.matern_workspace_bytes(n, ts, 1) > api.NOALLOC_SCRATCH_BYTES
+    big = api.Locs(x=ctypes.c_void_p(16), y=ctypes.c_void_p(16), n=n)
+    assert f(ctypes.byref(big), ctypes.byref(q), ts, 1, ctypes.c_void_p(16), None) == 3    # BK_ENOMEM
+    # the 316 x 316-point lower 1,024-tile build fits
+    assert api.matern_workspace_bytes(316 * 316, 1024, 1) <= api.NOALLOC_SCRATCH_BYTES
+    src = open(HEADER).read()
+    assert re.search(r"#define BK_NOALLOC_SCRATCH_BYTES \(4u << 20\)", src)
+    assert api.NOALLOC_SCRATCH_BYTES == 4 << 20
+
+
 def test_model_handle_host_calls(lib):
     """Model calls that need no device memory: create/destroy, the prediction-cell
     dimensions, and the argument checks of the cell copy (runs without a GPU)."""
