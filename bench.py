@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="matern-large",
                     choices=["matern-large", "grid", "matern-medium", "deriv-grid", "matern-grad-medium", "loglik",
-                             "paper-grid", "small-x", "matern-order", "valu-rates"],
+                             "paper-grid", "small-x", "matern-order", "valu-rates", "table-source"],
                     help="matern-large: the headline (316 x 316 grid, nu = 3.7, FP32 learned vs FP64 plain)")
     ap.add_argument("--forms", default="learned,mixed,plain",
                     help="matern-large: forms to time (comma-separated; the headline needs learned)")
@@ -203,6 +203,9 @@ def main():
         return
     if a.workload == "valu-rates":
         valu_rates_bench(torch)
+        return
+    if a.workload == "table-source":
+        table_source_bench(a, torch, api, workloads)
         return
     if a.workload != "grid":
         matern_bench(a, torch, api, workloads)
@@ -547,6 +550,66 @@ def matern_bench(a, torch, api, workloads):
     line = {"metric": "Matern entries/s", "workload": a.workload, "n": n, "tile": ts, "entries": elems,
             "beta": beta, "results": res}
     print(json.dumps(line), flush=True)
+
+
+def table_source_bench(a, torch, api, workloads):
+    """What the network adds over the same tables filled by the plain window solver
+    (bk_model_set_table_source): the learned kernels on the 2^24-pair evaluation set
+    (seed 5) and on the 316 x 316 Matern build (nu = 3.7, beta = 0.02, lower
+    1,024-tiles, FP32), with the cells / window table from the network (its
+    calibrated margins), from the solver with the same margins, and from the solver
+    with none. Per source: main-kernel time (HIP events around it), mean nodes per
+    entry walked, fallbacks."""
+    dev = torch.device("cuda:0")
+    nu_h, x_h = workloads.eval_pairs(a.n, seed=5)
+    nu = torch.from_numpy(nu_h).to(dev)
+    x = torch.from_numpy(x_h).to(dev)
+    out = torch.empty_like(x)
+    ws = torch.empty(api.workspace_bytes(a.n), dtype=torch.uint8, device=dev)
+    c = workloads.MATERN_LARGE
+    xy = workloads.jittered_grid_locations(c["side"], c["seed"])
+    n, ts = xy.shape[0], c["tile"]
+    lx = torch.from_numpy(np.ascontiguousarray(xy[:, 0])).to(dev)
+    ly = torch.from_numpy(np.ascontiguousarray(xy[:, 1])).to(dev)
+    elems = api.matern_out_elems(n, ts, 1)
+    mout = torch.empty(elems, dtype=torch.float32, device=dev)
+    mws = torch.empty(api.matern_workspace_bytes(n, ts, 1), dtype=torch.uint8, device=dev)
+    res = {}
+    for name, src, zero in (("network", api.TABLE_NETWORK, False), ("solver+margins", api.TABLE_SOLVER, False),
+                            ("solver", api.TABLE_SOLVER, True)):
+        m = api.Model(a.model)
+        if zero:
+            m.set_margins(0.0, 0.0, 0.0, 0.0)
+        m.set_table_source(src)
+        row = {}
+        for wl, call in (("grid_2^24", lambda ev=None, st=None: api.besselk(nu, x, out=out, mode="learned", model=m,
+                                                                           workspace=ws, kernel_events=ev, stats=st)),
+                         ("matern_316^2", lambda ev=None, st=None: api.matern_tiles(
+                             lx, ly, c["sigma2"], c["beta"], c["nu"], ts, 1, mode="learned", out_dtype=api.OUT_F32,
+                             out=mout, model=m, workspace=mws, kernel_events=ev, stats=st))):
+            for _ in range(max(1, a.warmup)):
+                call()
+            reps = max(3, min(a.steps, 10))
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            for e0, e1 in ev:
+                e0.record()
+                e1.record()
+            torch.cuda.synchronize()
+            for k in range(reps):
+                call(ev=ev[k])
+            torch.cuda.synchronize()
+            kms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+            st = torch.zeros(api.STATS_LEN, dtype=torch.int64, device=dev)
+            call(st=st)
+            torch.cuda.synchronize()
+            st = st.cpu().numpy()
+            fb = int(st[api.STAT_FB_RANGE] + st[api.STAT_FB_TAIL] + st[api.STAT_FB_NONFINITE])
+            walked = int(st[api.STAT_ENTRIES]) - (fb - int(st[api.STAT_FB_RANGE]))
+            row[wl] = {"kernel_ms": round(kms, 4), "mean_nodes": int(st[api.STAT_NODES] - st[api.STAT_FB_NODES])
+                       / max(1, walked), "fallbacks": fb}
+        res[name] = row
+    print(json.dumps({"metric": "learned kernels with network-filled vs solver-filled tables", "n_grid": a.n,
+                      "matern_entries": elems, "results": res}), flush=True)
 
 
 RATE_OPS = ("v_fma_f64", "v_add_f64", "v_mul_f64", "v_fma_f32", "v_add_f32", "v_mul_f32", "v_exp_f32", "v_log_f32",

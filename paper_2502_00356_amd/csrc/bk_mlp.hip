@@ -382,7 +382,7 @@ __device__ inline LearnedPlan learned_plan(double tlo, double thi, int N, const 
 // <= 2^-23 / (e ln(1 / rho)); with 2 nu h >= 1/2 (rho <= e^-1/2) that is below 9e-8.
 // Otherwise (kQf false) the factor follows Q' = rho Q + (1 - rho) in FP64 and is
 // rounded to FP32 once per node.
-template <bool kBias, bool kQf>
+template <bool kBias, bool kQf, bool kQuads>
 __device__ inline void learned_sum(WalkF& w, int N, float Pf, float rhof, float& e0, float& e1, float& eprev,
                                    float& elast, double& Sd)
 {
@@ -413,6 +413,22 @@ __device__ inline void learned_sum(WalkF& w, int N, float Pf, float rhof, float&
     };
     // Nodes go in groups of four: a group is added pairwise in FP32 (two roundings,
     // <= 1.2e-7 of the group, all terms positive) and the groups sum in FP64.
+    if constexpr (kQuads) {
+        // N + 1 is a multiple of four (N >= 7): whole groups only
+        const float ta = node(), tb = node(), tc = node(), td = node();
+        e0 = ta;
+        e1 = tb;
+        Sd = (double)((ta + tb) + (tc + td));
+        eprev = tc;
+        elast = td;
+        for (int m = 4; m < N; m += 4) {
+            const float ua = node(), ub = node(), uc = node(), ud = node();
+            Sd += (double)((ua + ub) + (uc + ud));
+            eprev = uc;
+            elast = ud;
+        }
+        return;
+    }
     e0 = node();
     e1 = node();                               // N >= kNodeMin: at least five nodes
     Sd = (double)(e0 + e1);
@@ -441,7 +457,8 @@ __device__ inline void learned_sum(WalkF& w, int N, float Pf, float rhof, float&
 }
 
 // kQfOk: the caller allows the FP32 node factor (taken where 2 nu h >= 1/2).
-template <bool kBias, bool kQfOk = false>
+// kQuads: the plan's N + 1 is a multiple of four.
+template <bool kBias, bool kQfOk = false, bool kQuads = false>
 __device__ inline LearnedOut learned_walk(double x, double nu, const LearnedPlan& P, double eb = 0.0)
 {
     LearnedOut o;
@@ -466,10 +483,10 @@ __device__ inline LearnedOut learned_walk(double x, double nu, const LearnedPlan
     float e0, e1, eprev, elast;
     double Sd;
     if (kQfOk && P.b2 >= 0.25 * kLog2e)        // b2 = nu h log2 e: 2 nu h >= 1/2
-        learned_sum<kBias, kQfOk>(w, N, (float)(P.Q0 - 1.0), (float)P.rho, e0, e1, eprev, elast, Sd);
+        learned_sum<kBias, kQfOk, kQuads>(w, N, (float)(P.Q0 - 1.0), (float)P.rho, e0, e1, eprev, elast, Sd);
     else
-        learned_sum<kBias, false>(w, N, 0.0f, 0.0f, e0, e1, eprev, elast, Sd);
-    Sd -= 0.5 * ((double)e0 + (double)elast);
+        learned_sum<kBias, false, kQuads>(w, N, 0.0f, 0.0f, e0, e1, eprev, elast, Sd);
+    Sd -= (double)(0.5f * (e0 + elast));       // one FP32 rounding of a term-sized value
     o.hs = h * Sd;
     if (!(Sd > 0.0) || !isfinite(Sd)) { o.reason = BK_STAT_FB_NONFINITE; return o; }
     const float S = (float)Sd;
@@ -480,8 +497,13 @@ __device__ inline LearnedOut learned_walk(double x, double nu, const LearnedPlan
     // Right: if e_N < e_{N-1}, the mean value theorem puts a point xi > t* in
     // (t_{N-1}, t_N) where g'(xi) is the secant slope; g' decreases right of t_c, so
     // |g'| >= |secant| on [t_N, inf) and the tail is at most e_N / |log(e_N / e_{N-1})|.
-    const float lr = __builtin_amdgcn_logf(elast * __builtin_amdgcn_rcpf(eprev)) * 0.69314718f;
-    if (!(elast < eprev) || elast > -lr * kTailTol * S) { o.reason = BK_STAT_FB_TAIL; return o; }
+    // First without the logarithm: |log r| >= 1 - r for r = e_N / e_{N-1} < 1, so
+    // e_N e_{N-1} <= tol S (e_{N-1} - e_N) already implies the bound.
+    if (!(elast < eprev)) { o.reason = BK_STAT_FB_TAIL; return o; }
+    if (!(elast * eprev <= kTailTol * S * (eprev - elast))) {
+        const float lr = __builtin_amdgcn_logf(elast * __builtin_amdgcn_rcpf(eprev)) * 0.69314718f;
+        if (elast > -lr * kTailTol * S) { o.reason = BK_STAT_FB_TAIL; return o; }
+    }
     if (tlo > 0.0) {
         // Left (t_lo > 0, e_0 < e_1, so t_lo < t*). t_c is the fixed point of the
         // decreasing map F(t) = acosh(nu / sqrt(x cosh t)) / nu (0 where the argument is
@@ -512,7 +534,7 @@ __device__ inline LearnedOut learned_walk(double x, double nu, const LearnedPlan
             const float e = __builtin_amdgcn_exp2f(t * 1.44269504f);
             return 0.5f * (e + __builtin_amdgcn_rcpf(e));
         };
-        const float tlof = (float)tlo, ih = (float)(1.0 / h);
+        const float tlof = (float)tlo, ih = __builtin_amdgcn_rcpf((float)h);
         float up = F(0.0f, 1.0f) * 1.0009765625f, lo = 0.0f;
         if (!(tlof >= up)) {                        // t_lo near t_c: narrow the bounds
             lo = F(up, coshf_(up)) * 0.9990234375f;
@@ -956,7 +978,10 @@ __global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, doubl
     bool raised;
     decode_window(M, fminf(t0[0], t1[0]), fmaxf(t0[1], t1[1]), fmaxf(t0[2], t1[2]), nu, exp10(lxm), Lq, tlo, thi,
                   N, raised);
-    const bool valid = thi > tlo && isfinite(thi) && N >= 0;
+    // N + 1 raised to a multiple of four (a finer step on the same window), so that
+    // the kernel's walk runs whole groups of four nodes with no remainder code
+    if (N >= 0) N = ((N + 4) & ~3) - 1;
+    const bool valid = thi > tlo && isfinite(thi) && N >= 0 && N <= kNodeMax;
     float4_t a;
     a[0] = (float)tlo;
     a[1] = (float)thi;
@@ -1112,7 +1137,7 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
                 const float4_t a = plan_a[k0];
                 const int N = __float_as_int(a[2]);
                 if (kStats) c_raised += (unsigned int)(__float_as_int(a[3]) & 1);
-                if (N >= 0) {
+                if (N >= 0) {                   // N + 1 is a multiple of four (k_matern_plans)
                     const double4_t b0 = plan_b[3 * k0], b1 = plan_b[3 * k0 + 1], b2 = plan_b[3 * k0 + 2];
                     LearnedPlan P;
                     P.tlo = (double)a[0];
@@ -1126,7 +1151,7 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
                     P.b2 = b1[2];
                     P.dnu = b1[3];
                     const double eb = fma(-z, b2[3], b2[2]);
-                    LearnedOut lo = learned_walk<true, true>(z, nu, P, eb);
+                    LearnedOut lo = learned_walk<true, true, true>(z, nu, P, eb);
                     ok = lo.reason == 0;
                     if (kStats) {
                         c_ent += 1;
