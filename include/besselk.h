@@ -40,7 +40,10 @@ typedef enum {
 /* Evaluation form.
  *  BK_PLAIN_F64  : per-entry peak and window solve in FP64 (the bracket/Newton
  *                  search of Sec. IV-B), node count from the trapezoid strip
- *                  bound, FP64 node terms and FP64 accumulation.
+ *                  bound, FP64 node terms and FP64 accumulation. bk_besselk and
+ *                  bk_besselk_ex take Temme's series with the forward recurrence
+ *                  instead (Sec. IV-A, the paper's branch for x < 0.1) where
+ *                  x < 0.1 and K_nu(x) lies far inside the double range.
  *  BK_MIXED_F32C : the same FP64 solve; node exponents formed in FP64 without
  *                  cancellation, exponentials in FP32, Kahan-compensated FP32 sum,
  *                  FP64 prefactor. Looser window (relative error ~1e-7 class).

@@ -670,19 +670,16 @@ __device__ __forceinline__ double scaled_exp(double r, double c)
     return ldexp((double)__builtin_amdgcn_exp2f((float)(y - k)) * c, (int)k);
 }
 
-// c e^r as scaled_exp, rounded to the output type. For FP32 output the product
-// 2^f c and the scaling by 2^k are taken in FP32 (two roundings, <= 1.2e-7, and a
-// correctly rounded subnormal result where C lies below the FP32 normal range).
+// c 2^k rounded to the output type (exact scaling; for FP32 output one rounding of
+// c to FP32 first where c lies well inside its range).
 template <typename OutT>
-__device__ __forceinline__ OutT scaled_exp_out(double r, double c)
+__device__ __forceinline__ OutT scale2_out(double c, int k)
 {
     if constexpr (sizeof(OutT) == sizeof(float)) {
-        if (!(c > 1e-30 && c < 1e30)) return (float)scaled_exp(r, c);   // c itself far from FP32's range
-        const double y = r * kLog2e;
-        const double k = rint(y);
-        return ldexpf(__builtin_amdgcn_exp2f((float)(y - k)) * (float)c, (int)k);
+        if (!(c > 1e-30 && c < 1e30)) return (float)ldexp(c, k);
+        return ldexpf((float)c, k);
     } else {
-        return scaled_exp(r, c);
+        return ldexp(c, k);
     }
 }
 
@@ -1098,11 +1095,12 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
     const int64_t il = (int64_t)rb * 64 + lane;
     const int64_t jl0 = (int64_t)cb * kColsPerGroup + (int64_t)wave * kColsPerWave;
     const bool row_ok = il < mI;
-    if (jl0 >= nJ || (!kStats && !row_ok)) return;
+    // the statistics variant keeps every wave to the end for its block-wide sums
+    if (!kStats && (jl0 >= nJ || !row_ok)) return;
     const int64_t base = tile_offset_l(g.n, g.ts, g.T, g.lower, I, J);
     const int64_t ilr = row_ok ? il : 0;
     const double xi = lx_[I * g.ts + ilr], yi = ly_[I * g.ts + ilr];
-    const int cend = (kStats && !row_ok) ? 0 : (int)min((int64_t)kColsPerWave, nJ - jl0);
+    const int cend = (kStats && (!row_ok || jl0 >= nJ)) ? 0 : (int)min((int64_t)kColsPerWave, nJ - jl0);
     const float tscale = (float)(kTableSize - 1) / (M.lx_hi - M.lx_lo);
     const bool nu_ok = (float)nu >= M.nu_lo && (float)nu <= M.nu_hi;
     bool rejected = false;
@@ -1130,7 +1128,7 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
             const float lz = __log2f((float)z) * 0.30102999566f;
             bool ok = nu_ok && lz >= M.lx_lo && lz <= M.lx_hi;
             if (kStats && !ok) c_range += 1;
-            double hs = 0.0, lexp = 0.0;
+            double hs = 0.0, kq = 0.0;
             if (ok) {
                 float fpos = (lz - M.lx_lo) * tscale;
                 int k0 = min(max((int)fpos, 0), kTableSize - 2);
@@ -1150,7 +1148,16 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
                     P.Q0 = b1[1];
                     P.b2 = b1[2];
                     P.dnu = b1[3];
-                    const double eb = fma(-z, b2[3], b2[2]);
+                    // the prefactor's exponent pref + nu log z + Delta - z, known before the
+                    // walk: = K + nu log(z / z_k) - z cosh t_lo plus the walk's bias eb0 ln 2
+                    const double eb0 = fma(-z, b2[3], b2[2]);
+                    const double lexp = fma(nu, (double)log1p_small_f((float)fma(z, b2[1], -1.0)),
+                                            fma(-z, P.c0, fma(eb0, kLn2, b2[0])));
+                    // lexp log2 e = kq + f (|f| <= 1/2): f joins the bias (every node term
+                    // scaled by 2^f), 2^kq is applied to the result exactly
+                    const double y = lexp * kLog2e;
+                    kq = rint(y);
+                    const double eb = eb0 - (y - kq);
                     LearnedOut lo = learned_walk<true, true, true>(z, nu, P, eb);
                     ok = lo.reason == 0;
                     if (kStats) {
@@ -1161,17 +1168,13 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
                         c_nonfin += lo.reason == BK_STAT_FB_NONFINITE ? 1u : 0u;
                     }
                     hs = lo.hs;
-                    // pref + nu log z + Delta - z = K + nu log(z / z_k) - z cosh t_lo, and
-                    // the walk's bias eb ln 2
-                    lexp = fma(nu, (double)log1p_small_f((float)fma(z, b2[1], -1.0)),
-                               fma(-z, P.c0, fma(eb, kLn2, b2[0])));
                 } else {
                     ok = false;
                     if (kStats) c_nonfin += 1;
                 }
             }
             if (ok) {
-                val = scaled_exp_out<OutT>(lexp, sigma2 * hs);
+                val = scale2_out<OutT>(sigma2 * hs, (int)kq);
             } else {
                 val = (OutT)__builtin_nan("");
                 rejected = true;
@@ -1185,12 +1188,8 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
         atomicOr(bitmap + (w >> 5), 1u << (unsigned)(w & 31));
     }
     if (kStats) {
-        wave_count_l(stats + BK_STAT_ENTRIES, c_ent);
-        wave_count_l(stats + BK_STAT_NODES, c_nodes);
-        wave_count_l(stats + BK_STAT_FB_RANGE, c_range);
-        wave_count_l(stats + BK_STAT_FB_TAIL, c_tail);
-        wave_count_l(stats + BK_STAT_FB_NONFINITE, c_nonfin);
-        wave_count_l(stats + BK_STAT_NODE_RAISED, c_raised);
+        // one atomic per counter per workgroup (per-wave atomics on the same eight
+        // addresses serialise in L2 over millions of waves)
         unsigned int slots = 0;
 #pragma unroll
         for (int c = 0; c < kColsPerWave; ++c) {
@@ -1198,7 +1197,16 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
             for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned int)__shfl_xor((int)v, o, 64));
             slots += 64u * v;
         }
-        wave_count_l(stats + BK_STAT_LANE_SLOTS, (threadIdx.x & 63) == 0 ? slots : 0u);
+        unsigned long long cnt[8];
+        cnt[BK_STAT_ENTRIES] = c_ent;
+        cnt[BK_STAT_NODES] = c_nodes;
+        cnt[BK_STAT_FB_RANGE] = c_range;
+        cnt[BK_STAT_FB_TAIL] = c_tail;
+        cnt[BK_STAT_NODE_RAISED] = c_raised;
+        cnt[BK_STAT_FB_NONFINITE] = c_nonfin;
+        cnt[BK_STAT_FB_NODES] = 0;
+        cnt[BK_STAT_LANE_SLOTS] = lane == 0 ? slots : 0u;
+        block_stats_w(stats, cnt, 8, 4);
     }
 }
 

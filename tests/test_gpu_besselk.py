@@ -141,8 +141,34 @@ def test_stats_counters(api):
     api.besselk(to_dev(nu), to_dev(x), mode="plain", stats=stats)
     torch.cuda.synchronize()
     s = stats.cpu().numpy()
-    assert s[api.STAT_ENTRIES] == 2000
-    assert 2000 * 5 <= s[api.STAT_NODES] <= 2000 * 200
+    # x < 0.1 takes Temme's series (not counted as quadrature); these orders and
+    # arguments are all far inside its range
+    quad = 2 * int((x >= 0.1).sum())
+    assert s[api.STAT_ENTRIES] == quad
+    assert quad * 5 <= s[api.STAT_NODES] <= quad * 200
+
+
+def test_small_x_temme_branch(api, orc):
+    """Plain FP64 at x < 0.1, where it takes Temme's series with the forward
+    recurrence (Sec. IV-A) unless K_nu(x) could leave the double range: K, e^x K and
+    log K against the oracle's integral, including integer and half-integer orders,
+    the x = 0.1 boundary, arguments down to 1e-8, and orders past the series' range
+    (nu = 40..60 at x = 1e-6, where the quadrature runs instead and K overflows)."""
+    rng = np.random.default_rng(21)
+    nu = np.concatenate([rng.uniform(0.0, 12.0, 3000), np.arange(0, 13) * 0.5, [0.3, 2.7, 7.5, 9.99]])
+    x = np.concatenate([10.0 ** rng.uniform(-8, -1, 3000), np.full(13, 0.05), [0.1, 0.0999999, 1e-8, 0.1]])
+    k, lk, ks = orc.besselk(nu, x)
+    got_k, got_s, got_l = (_gpu(api, nu, x, "plain", r) for r in (0, 1, 2))
+    fin = np.isfinite(k) & (k >= DBL_MIN)
+    assert rel_err(got_k[fin], k[fin]).max() <= TOL_PLAIN
+    assert rel_err(got_s, ks).max() <= TOL_PLAIN
+    assert np.all(np.abs(got_l - lk) <= TOL_PLAIN + 4 * np.finfo(float).eps * np.abs(lk))
+    big_nu = np.array([40.0, 50.0, 60.0])
+    big_x = np.full(3, 1e-6)
+    _, lk2, _ = orc.besselk(big_nu, big_x)
+    got_l2 = _gpu(api, big_nu, big_x, "plain", 2)
+    assert np.all(np.isfinite(got_l2))
+    assert np.all(np.abs(got_l2 - lk2) <= TOL_PLAIN + 4 * np.finfo(float).eps * np.abs(lk2))
 
 
 def test_invalid_arguments(api):
