@@ -458,7 +458,9 @@ __device__ inline void learned_sum(WalkF& w, int N, float Pf, float rhof, float&
 
 // kQfOk: the caller allows the FP32 node factor (taken where 2 nu h >= 1/2).
 // kQuads: the plan's N + 1 is a multiple of four.
-template <bool kBias, bool kQfOk = false, bool kQuads = false>
+// kDirect: eb is the walk's first exponent itself (log2 of node 0's term, the
+// caller's bias folded in), and o.delta is Delta without a bias.
+template <bool kBias, bool kQfOk = false, bool kQuads = false, bool kDirect = false>
 __device__ inline LearnedOut learned_walk(double x, double nu, const LearnedPlan& P, double eb = 0.0)
 {
     LearnedOut o;
@@ -468,15 +470,19 @@ __device__ inline LearnedOut learned_walk(double x, double nu, const LearnedPlan
     // reference t_ref = t_lo; sinh^2(t/2) = (cosh t - 1) / 2 loses ~1e-16 absolute,
     // i.e. at most ~2e-13 relative in the scale for x <= 1e3, far inside this form's budget
     o.delta = P.dnu - x * (P.c0 - 1.0);
-    if (kBias) o.delta = fma(eb, kLn2, o.delta);
+    if (kBias && !kDirect) o.delta = fma(eb, kLn2, o.delta);
     WalkF w;
     w.kappa = P.kappa;
     w.c = P.c0;
     w.cn = P.c1;
     w.a2 = -x * kLog2e;
     w.b2 = P.b2;
-    w.e = x * P.c0 * kLog2e;
-    if (kBias) w.e -= eb;
+    if (kDirect) {
+        w.e = eb;
+    } else {
+        w.e = x * P.c0 * kLog2e;
+        if (kBias) w.e -= eb;
+    }
     w.rho = P.rho;
     w.omr = 1.0 - P.rho;
     w.Q = P.Q0;
@@ -542,7 +548,7 @@ __device__ inline LearnedOut learned_walk(double x, double nu, const LearnedPlan
             lo = fmaxf(lo, F(up, coshf_(up)) * 0.9990234375f);
             up = fminf(up, F(lo, coshf_(lo)) * 1.0009765625f);
         }
-        const float D = fmaxf((float)(kBias ? fma(-eb, kLn2, o.delta) : o.delta), 0.0f);
+        const float D = fmaxf((float)(kBias && !kDirect ? fma(-eb, kLn2, o.delta) : o.delta), 0.0f);
         float bound;
         if (tlof >= up) {
             const float a = -ll * (tlof - up) * ih, b = -D, dab = a - b;
@@ -954,11 +960,12 @@ __global__ __launch_bounds__(256) void k_matern_table_solver(MlpDev M, float nu,
 // at the cell's larger x (the floor falls with x, so it holds over the cell), and
 // the whole walk set-up, nu included. Layout as the prediction cells' plans, with
 // the nu-dependent part (rho, Q0, b2, dnu) in a second double4 and, in a third, the
-// prefactor's pieces at the interval's lower end z_k: K = pref + nu log z_k +
-// nu t_lo - ln 2 and 1 / z_k, so that an entry needs only log1p(z / z_k - 1),
-// |z / z_k - 1| < 0.017, for log z; and the walk's bias 2^eb, eb = B0 - z B1 (log2
-// of the term at the node m_pk of the largest term at the interval's middle,
-// relative to node 0: B0 = nu m_pk h log2 e, B1 = (cosh t_pk - cosh t_lo) log2 e).
+// prefactor's pieces at the interval's lower end z_k, so that an entry needs only
+// log1p(z / z_k - 1), |z / z_k - 1| < 0.016, for log z. The walk is biased by 2^eb,
+// eb = B0 - z B1 (log2 of the term at the node m_pk of the largest term at the
+// interval's middle, relative to node 0: B0 = nu m_pk h log2 e, B1 = (cosh t_pk -
+// cosh t_lo) log2 e); the third double4 holds A2 = (pref + nu log z_k + nu t_lo -
+// ln 2) log2 e + B0, 1 / z_k, C2 = B1 + cosh(t_lo) log2 e and B0.
 __global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, double Lq, double pref,
                                                       const float* __restrict__ table,
                                                        float4_t* __restrict__ pa,
@@ -1008,8 +1015,10 @@ __global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, doubl
         B0 = nu * (double)mpk * P.h * kLog2e;
         B1 = (cosh(tlo + (double)mpk * P.h) - P.c0) * kLog2e;
     }
+    // third double4: A2, 1 / z_k, C2, B0 (the prefactor and node 0's exponent in log2
+    // units, see k_matern_learned)
     const double4_t b0 = {P.h, P.c0, P.c1, P.kappa}, b1 = {P.rho, P.Q0, P.b2, P.dnu};
-    const double4_t b2 = {pref + nu * log(zk) + P.dnu, 1.0 / zk, B0, B1};
+    const double4_t b2 = {(pref + nu * log(zk) + P.dnu) * kLog2e + B0, 1.0 / zk, B1 + P.c0 * kLog2e, B0};
     pb[3 * k] = b0;
     pb[3 * k + 1] = b1;
     pb[3 * k + 2] = b2;
@@ -1072,7 +1081,7 @@ __device__ inline void wave_count_l(unsigned long long* dst, unsigned int v)
 // statistics variant (lanes past a ragged tile's last row stay in the wave, idle,
 // so that the wave can sum its counts).
 template <typename OutT, bool kStats>
-__global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float4_t* __restrict__ plan_a,
+__global__ __launch_bounds__(256, 8) void k_matern_learned(MlpDev M, const float4_t* __restrict__ plan_a,
                                                         const double4_t* __restrict__ plan_b,
                                                         const double* __restrict__ lx_, const double* __restrict__ ly_,
                                                         TileGeomL g, int64_t tile_base, double sigma2,
@@ -1103,6 +1112,7 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
     const int cend = (kStats && (!row_ok || jl0 >= nJ)) ? 0 : (int)min((int64_t)kColsPerWave, nJ - jl0);
     const float tscale = (float)(kTableSize - 1) / (M.lx_hi - M.lx_lo);
     const bool nu_ok = (float)nu >= M.nu_lo && (float)nu <= M.nu_hi;
+    const double nul2e = nu * kLog2e;
     bool rejected = false;
     unsigned int c_ent = 0, c_nodes = 0, c_range = 0, c_tail = 0, c_nonfin = 0, c_raised = 0;
     unsigned int col_nodes[kColsPerWave] = {};      // statistics: nodes per column walked
@@ -1148,17 +1158,19 @@ __global__ __launch_bounds__(256, 4) void k_matern_learned(MlpDev M, const float
                     P.Q0 = b1[1];
                     P.b2 = b1[2];
                     P.dnu = b1[3];
-                    // the prefactor's exponent pref + nu log z + Delta - z, known before the
-                    // walk: = K + nu log(z / z_k) - z cosh t_lo plus the walk's bias eb0 ln 2
-                    const double eb0 = fma(-z, b2[3], b2[2]);
-                    const double lexp = fma(nu, (double)log1p_small_f((float)fma(z, b2[1], -1.0)),
-                                            fma(-z, P.c0, fma(eb0, kLn2, b2[0])));
-                    // lexp log2 e = kq + f (|f| <= 1/2): f joins the bias (every node term
-                    // scaled by 2^f), 2^kq is applied to the result exactly
-                    const double y = lexp * kLog2e;
+                    // In log2 units, with the walk's bias eb0 = B0 - z B1 (node t_pk's term
+                    // relative to node 0, k_matern_plans), the prefactor's exponent
+                    // (pref + nu log z + Delta - z) log2 e + eb0 is
+                    //   y = nu log2(z / z_k) + A2 - z C2,
+                    // A2 = (pref + nu log z_k + nu t_lo - ln 2) log2 e + B0, C2 = B1 + cosh(t_lo) log2 e,
+                    // and node 0's exponent is x cosh(t_lo) log2 e - eb0 = z C2 - B0. With
+                    // y = kq + f (|f| <= 1/2), f joins node 0's exponent (every node term
+                    // scaled by 2^f) and 2^kq is applied to the result exactly.
+                    const double y = fma(nul2e, (double)log1p_small_f((float)fma(z, b2[1], -1.0)),
+                                         fma(-z, b2[2], b2[0]));
                     kq = rint(y);
-                    const double eb = eb0 - (y - kq);
-                    LearnedOut lo = learned_walk<true, true, true>(z, nu, P, eb);
+                    const double e_init = fma(z, b2[2], (y - kq) - b2[3]);
+                    LearnedOut lo = learned_walk<true, true, true, true>(z, nu, P, e_init);
                     ok = lo.reason == 0;
                     if (kStats) {
                         c_ent += 1;
