@@ -329,7 +329,7 @@ def matern_headline(a, torch, api, workloads):
     cpu, acc = None, {}
     if not a.no_cpu:
         import oracle
-        i, j = cpu_sample_entries(n, ts, a.cpu_sample // 4, max(0, min(4, a.cpu_tiles)), seed=99)
+        i, j = cpu_sample_entries(n, ts, a.cpu_sample, max(0, min(4, a.cpu_tiles)), seed=99)
         t0 = time.perf_counter()
         ref = oracle.matern_entries(xy, xy, i, j, s2, beta, nu)
         dt = time.perf_counter() - t0
@@ -337,7 +337,7 @@ def matern_headline(a, torch, api, workloads):
         cpu = dict(value=i.size / dt, unit="entries/s", cores=cores, kind="oracle",
                    sample="%d stored entries drawn uniformly plus the %d whole tiles of the last tile row (diagonal, "
                           "its left neighbour, middle, farthest): %d entries; long-double adaptive Gauss-Kronrod, "
-                          "OpenMP over entries, %.1f s" % (a.cpu_sample // 4, max(0, min(4, a.cpu_tiles)), i.size, dt))
+                          "OpenMP over entries, %.1f s" % (a.cpu_sample, max(0, min(4, a.cpu_tiles)), i.size, dt))
         pidx = torch.from_numpy(packed_index(api, n, ts, i, j)).to(dev)
         m = ref > 1e-30
         for f, odt, _ in forms:

@@ -47,6 +47,7 @@ typedef enum {
  *  BK_MIXED_F32C : the same FP64 solve; node exponents formed in FP64 without
  *                  cancellation, exponentials in FP32, Kahan-compensated FP32 sum,
  *                  FP64 prefactor. Looser window (relative error ~1e-7 class).
+ *                  Like BK_PLAIN_F64, Temme's series (FP64) where x < 0.1.
  *  BK_LEARNED    : a 2-64-64-3 MLP on (log10 x, nu) predicts the window and node
  *                  count in place of the solve (the count is raised to the
  *                  strip-bound rule's if lower); the standalone form reads the

@@ -80,12 +80,13 @@ __device__ __forceinline__ double assemble(double z, double delta, double hs, in
     return ldexp(exp(64.0 * kLn2 - z) * exp(delta) * hs, -64);
 }
 
-// The plain form takes Temme's series with the forward recurrence (Sec. IV-A; the
+// The plain and mixed forms take Temme's series with the forward recurrence (Sec. IV-A; the
 // paper's branch for x < 0.1 in Alg. 2) where x < 0.1 and K_nu(x) stays far inside
 // the double range: log K_nu(x) <= log Gamma(nu) + nu log(2/x) for x < 0.1, bounded
 // here by nu (log(2/x) + log(nu + 1)) + log(1/nu + 1) < 600. On 2^24 pairs with
-// x in [1e-4, 0.1) it is 3.7 times faster than the windowed quadrature and as
-// accurate (max relative error 3.0e-15 against 6.4e-15).
+// x in [1e-4, 0.1) it is 3.7 times faster than the windowed FP64 quadrature and as
+// accurate (max relative error 3.0e-15 against 6.4e-15); it also takes 10% off the
+// FP32-term form on the 2^24 grid, at FP64 accuracy for those entries.
 __device__ __forceinline__ bool temme_applies(double v, double z)
 {
     if (!(z < kPaperTemmeX) || !(v > 0.0)) return false;
@@ -129,8 +130,7 @@ __device__ unsigned int block_sort_slot(int key, unsigned int* hist)
 // holds entries that take the same branches and loop counts:
 //  1. entry order: special values; key = peak regime (0: nu^2 <= x, t* = 0;
 //     1: interior peak, window from t = 0; 2: interior peak with a left root
-//     likely, estimated by nu asinh(nu/x) > L; plain form only, 4: x < 0.1,
-//     Temme's series);
+//     likely, estimated by nu asinh(nu/x) > L; 4: x < 0.1, Temme's series);
 //  2. regime order: Temme's series (and its store), or the FP64 peak / window
 //     solve and node count;
 //  3. node-count order: the node walk, the prefactor and the store to the
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kSolveBlock) __attribute__((amdgpu_waves_per_eu(6, 
     }
     int key = 0;
     if (work && v * v > z) key = ((float)v * asinhf((float)(v / z)) > (float)L) ? 2 : 1;
-    if (MODE == BK_PLAIN_F64 && work && temme_applies(v, z)) key = 4;
+    if (work && temme_applies(v, z)) key = 4;
     // phase 1 -> 2: sort by regime (Temme's series in waves of their own)
     unsigned int slot = block_sort_slot<kSolveBlock>(work ? key : 3, hist);
     s_d[0][slot] = v;

@@ -1315,107 +1315,193 @@ __global__ __launch_bounds__(256) void k_make_targets(const double* __restrict__
     tgt[3 * i + 2] = (float)nodes[i] / sn;
 }
 
-// Forward and backward of one sample per lane. Stores, feature-major ([feature][B]),
-// the tensors the weight gradients need: u, h1, h2, gh1, gh2, gy; accumulates the loss.
-// Sample b of the batch is row perm(b) = (pa * (start + b) + pb) mod n of the data.
-__global__ __launch_bounds__(256) void k_fwd_bwd(const float* __restrict__ P, const float* __restrict__ U,
-                                                 const float* __restrict__ T, const float* __restrict__ tau, int64_t B,
-                                                 int64_t n, uint64_t pa, uint64_t pb, int64_t start,
-                                                 float* __restrict__ scr, float* __restrict__ loss)
+// Training gradient of one tile of kTrainTile = 64 samples per 256-lane workgroup
+// (FP32 on the vector ALU: on gfx950 the FP32 matrix cores have the vector units'
+// peak, and these 64 x 64 x 64 products are too small to gain from them). The
+// tile's activations and back-propagated gradients live in LDS, one row per
+// sample; every 64 x 64 product is split over the 256 lanes, 16 outputs each
+// (lane t: sample or unit t / 4, units or columns 16 (t % 4) ... + 15), so each
+// lane runs a quarter of one sample's work instead of a whole sample:
+//   h1 = relu(W1 u + b1), z2 = W2 h1 + b2, h2 = relu(z2), y = W3 h2 + b3,
+//   gy = dL/dy, g2 = [z2 > 0] W3^T gy, g1 = [h1 > 0] W2^T g2,
+//   dW2 = sum_s g2 h1^T, dW1 = sum_s g1 u^T, dW3 = sum_s gy h2^T, biases likewise.
+// The tile's gradient (kNParam floats) goes to its row of `partial`; k_grad_reduce
+// sums the rows in a fixed order. Sample b of the batch is row perm(b) =
+// (pa * (start + b) + pb) mod n of the data (n = 0: row b); samples past B add
+// nothing (their gy is zero).
+constexpr int kTrainTile = 64;
+constexpr int kTrainThreads = 256;
+constexpr int kTrainLd = kH + 1;          // padded LDS rows
+
+__device__ __forceinline__ uint64_t train_row(int64_t start, int64_t b, int64_t n, uint64_t pa, uint64_t pb)
 {
-    __shared__ float sP[kNParam];
-    __shared__ float red[4];
-    for (int k = threadIdx.x; k < kNParam; k += 256) sP[k] = P[k];
-    __syncthreads();
-    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    float l = 0.0f;
-    if (b < B) {
-        uint64_t row = (uint64_t)(start + b);
-        if (n > 0) row = (pa * row + pb) % (uint64_t)n;      // pa, row < n < 2^31: no overflow
-        float* su = scr;                 // [2][B]
-        float* sh1 = su + 2 * B;         // [64][B]
-        float* sh2 = sh1 + 64 * B;       // [64][B]
-        float* sg1 = sh2 + 64 * B;       // [64][B]
-        float* sg2 = sg1 + 64 * B;       // [64][B]
-        float* sgy = sg2 + 64 * B;       // [3][B]
-        const float u0 = U[2 * row], u1 = U[2 * row + 1];
-        su[b] = u0;
-        su[B + b] = u1;
-        float h1[kH], z2[kH];
-#pragma unroll
-        for (int j = 0; j < kH; ++j) {
-            float z = fmaf(sP[kOffW1 + 2 * j], u0, fmaf(sP[kOffW1 + 2 * j + 1], u1, sP[kOffB1 + j]));
-            h1[j] = fmaxf(z, 0.0f);
-            sh1[j * B + b] = h1[j];
-        }
-        float y[3] = {sP[kOffB3], sP[kOffB3 + 1], sP[kOffB3 + 2]};
-        for (int i2 = 0; i2 < kH; ++i2) {
-            float z = sP[kOffB2 + i2];
-#pragma unroll
-            for (int j = 0; j < kH; ++j) z = fmaf(sP[kOffW2 + i2 * kH + j], h1[j], z);
-            z2[i2] = z;
-            const float h = fmaxf(z, 0.0f);
-            sh2[i2 * B + b] = h;
-#pragma unroll
-            for (int o = 0; o < 3; ++o) y[o] = fmaf(sP[kOffW3 + o * kH + i2], h, y[o]);
-        }
-        float gy[3];
-        const float invB = 1.0f / (float)B;
-#pragma unroll
-        for (int o = 0; o < 3; ++o) {
-            const float e = T[3 * row + o] - y[o];
-            const float w = e < 0.0f ? 1.0f - tau[o] : tau[o];
-            l += w * e * e;
-            gy[o] = -2.0f * w * e * invB;
-            sgy[o * B + b] = gy[o];
-        }
-        float g2[kH];
-#pragma unroll
-        for (int i2 = 0; i2 < kH; ++i2) {
-            float g = sP[kOffW3 + i2] * gy[0] + sP[kOffW3 + kH + i2] * gy[1] + sP[kOffW3 + 2 * kH + i2] * gy[2];
-            g2[i2] = z2[i2] > 0.0f ? g : 0.0f;
-            sg2[i2 * B + b] = g2[i2];
-        }
-        for (int j = 0; j < kH; ++j) {
-            float g = 0.0f;
-#pragma unroll
-            for (int i2 = 0; i2 < kH; ++i2) g = fmaf(sP[kOffW2 + i2 * kH + j], g2[i2], g);
-            sg1[j * B + b] = h1[j] > 0.0f ? g : 0.0f;
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
-    __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(loss, (red[0] + red[1] + red[2] + red[3]) / (float)B);
+    uint64_t row = (uint64_t)(start + b);
+    if (n > 0) row = (pa * row + pb) % (uint64_t)n;      // pa, row < n < 2^31: no overflow
+    return row;
 }
 
-// Weight gradients: one workgroup per parameter group row, reduction over the batch.
-// Parameter k is sum_b A[b] * Bv[b] for two feature rows (or sum_b A[b] for biases).
-__global__ __launch_bounds__(256) void k_wgrad(const float* __restrict__ scr, int64_t B, float* __restrict__ grad)
+__global__ __launch_bounds__(kTrainThreads) void k_train_tile(const float* __restrict__ P, const float* __restrict__ U,
+                                                              const float* __restrict__ T, const float* __restrict__ tau,
+                                                              int64_t B, int64_t n, uint64_t pa, uint64_t pb,
+                                                              int64_t start, float* __restrict__ partial,
+                                                              float* __restrict__ loss)
 {
-    __shared__ float red[4];
-    const int k = blockIdx.x;                 // parameter index
-    const float* su = scr;
-    const float* sh1 = su + 2 * B;
-    const float* sh2 = sh1 + 64 * B;
-    const float* sg1 = sh2 + 64 * B;
-    const float* sg2 = sg1 + 64 * B;
-    const float* sgy = sg2 + 64 * B;
-    const float* a;
-    const float* bv = nullptr;
-    if (k < kOffB1) { int j = k / 2, c = k % 2; a = sg1 + (int64_t)j * B; bv = su + (int64_t)c * B; }
-    else if (k < kOffW2) { a = sg1 + (int64_t)(k - kOffB1) * B; }
-    else if (k < kOffB2) { int i2 = (k - kOffW2) / kH, j = (k - kOffW2) % kH; a = sg2 + (int64_t)i2 * B; bv = sh1 + (int64_t)j * B; }
-    else if (k < kOffW3) { a = sg2 + (int64_t)(k - kOffB2) * B; }
-    else if (k < kOffB3) { int o = (k - kOffW3) / kH, i2 = (k - kOffW3) % kH; a = sgy + (int64_t)o * B; bv = sh2 + (int64_t)i2 * B; }
-    else { a = sgy + (int64_t)(k - kOffB3) * B; }
-    float s = 0.0f;
-    if (bv) { for (int64_t b = threadIdx.x; b < B; b += 256) s = fmaf(a[b], bv[b], s); }
-    else { for (int64_t b = threadIdx.x; b < B; b += 256) s += a[b]; }
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __shared__ float sP[kNParam];
+    __shared__ float sW2T[kH * kH];           // W2 transposed (rows of W2^T for g1)
+    __shared__ float sH1[kTrainTile * kTrainLd], sH2[kTrainTile * kTrainLd];
+    __shared__ float sG1[kTrainTile * kTrainLd], sG2[kTrainTile * kTrainLd];
+    __shared__ float sU[kTrainTile * 2], sGy[kTrainTile * 4];
+    const int t = threadIdx.x;
+    for (int k = t; k < kNParam; k += kTrainThreads) sP[k] = P[k];
+    for (int k = t; k < kH * kH; k += kTrainThreads) sW2T[(k % kH) * kH + k / kH] = P[kOffW2 + k];
+    const int64_t tile0 = (int64_t)blockIdx.x * kTrainTile;
+    const int r = t >> 2, q0 = 16 * (t & 3);  // lane's sample (or unit) r and its 16 columns
+    const bool live_r = tile0 + r < B;
+    float u0 = 0.0f, u1 = 0.0f;
+    if (live_r) {
+        const uint64_t row = train_row(start, tile0 + r, n, pa, pb);
+        u0 = U[2 * row];
+        u1 = U[2 * row + 1];
+    }
+    if ((t & 3) == 0) {
+        sU[2 * r] = u0;
+        sU[2 * r + 1] = u1;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) grad[k] = red[0] + red[1] + red[2] + red[3];
+    // h1 (sample r, units q0..q0+15)
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int j = q0 + k;
+        sH1[r * kTrainLd + j] = fmaxf(fmaf(sP[kOffW1 + 2 * j], u0, fmaf(sP[kOffW1 + 2 * j + 1], u1, sP[kOffB1 + j])), 0.0f);
+    }
+    __syncthreads();
+    {   // h2 = relu(W2 h1 + b2)
+        float h[kH];
+#pragma unroll
+        for (int j = 0; j < kH; ++j) h[j] = sH1[r * kTrainLd + j];
+        for (int k = 0; k < 16; ++k) {
+            const int i = q0 + k;
+            float z = sP[kOffB2 + i];
+#pragma unroll
+            for (int j = 0; j < kH; ++j) z = fmaf(sP[kOffW2 + i * kH + j], h[j], z);
+            sH2[r * kTrainLd + i] = fmaxf(z, 0.0f);   // h2 > 0 iff z2 > 0
+        }
+    }
+    __syncthreads();
+    // output, loss and gy: lanes 0..191, sample t / 3, output t % 3
+    float l = 0.0f;
+    if (t < 3 * kTrainTile) {
+        const int s = t / 3, o = t - 3 * (t / 3);
+        float gy = 0.0f;
+        if (tile0 + s < B) {
+            float y = sP[kOffB3 + o];
+#pragma unroll 16
+            for (int i = 0; i < kH; ++i) y = fmaf(sP[kOffW3 + o * kH + i], sH2[s * kTrainLd + i], y);
+            const uint64_t row = train_row(start, tile0 + s, n, pa, pb);
+            const float e = T[3 * row + o] - y;
+            const float w = e < 0.0f ? 1.0f - tau[o] : tau[o];
+            l = w * e * e;
+            gy = -2.0f * w * e / (float)B;
+        }
+        sGy[4 * s + o] = gy;
+    }
+    for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
+    if ((t & 63) == 0 && t < 3 * kTrainTile) atomicAdd(loss, l / (float)B);
+    __syncthreads();
+    // g2 = [h2 > 0] W3^T gy (sample r, units q0..q0+15)
+    {
+        const float gy0 = sGy[4 * r], gy1 = sGy[4 * r + 1], gy2 = sGy[4 * r + 2];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int i = q0 + k;
+            const float g = sP[kOffW3 + i] * gy0 + sP[kOffW3 + kH + i] * gy1 + sP[kOffW3 + 2 * kH + i] * gy2;
+            sG2[r * kTrainLd + i] = sH2[r * kTrainLd + i] > 0.0f ? g : 0.0f;
+        }
+    }
+    __syncthreads();
+    {   // g1 = [h1 > 0] W2^T g2 (sample r, units q0..q0+15)
+        float g2[kH];
+#pragma unroll
+        for (int i = 0; i < kH; ++i) g2[i] = sG2[r * kTrainLd + i];
+        for (int k = 0; k < 16; ++k) {
+            const int j = q0 + k;
+            float g = 0.0f;
+#pragma unroll
+            for (int i = 0; i < kH; ++i) g = fmaf(sW2T[j * kH + i], g2[i], g);
+            sG1[r * kTrainLd + j] = sH1[r * kTrainLd + j] > 0.0f ? g : 0.0f;
+        }
+    }
+    __syncthreads();
+    float* out = partial + (int64_t)blockIdx.x * kNParam;
+    {   // dW2 row r, columns q0..q0+15, and db2[r]
+        float acc[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[k] = 0.0f;
+        float db = 0.0f;
+        for (int s = 0; s < kTrainTile; ++s) {
+            const float g = sG2[s * kTrainLd + r];
+            db += g;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) acc[k] = fmaf(g, sH1[s * kTrainLd + q0 + k], acc[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) out[kOffW2 + r * kH + q0 + k] = acc[k];
+        if ((t & 3) == 0) out[kOffB2 + r] = db;
+    }
+    // dW1 and db1: lanes 0..191 (unit t / 3; column 0, 1 or the bias)
+    if (t < 3 * kH) {
+        const int j = t / 3, c = t - 3 * (t / 3);
+        float acc = 0.0f;
+        for (int s = 0; s < kTrainTile; ++s) acc = fmaf(sG1[s * kTrainLd + j], c < 2 ? sU[2 * s + (c & 1)] : 1.0f, acc);
+        if (c < 2) out[kOffW1 + 2 * j + c] = acc;
+        else out[kOffB1 + j] = acc;
+    } else {
+        // dW3 and db3: lanes 192..255 (unit t - 192, all three outputs)
+        const int i = t - 3 * kH;
+        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+        for (int s = 0; s < kTrainTile; ++s) {
+            const float h = sH2[s * kTrainLd + i];
+            a0 = fmaf(sGy[4 * s], h, a0);
+            a1 = fmaf(sGy[4 * s + 1], h, a1);
+            a2 = fmaf(sGy[4 * s + 2], h, a2);
+        }
+        out[kOffW3 + i] = a0;
+        out[kOffW3 + kH + i] = a1;
+        out[kOffW3 + 2 * kH + i] = a2;
+        if (i < 3) {
+            float d = 0.0f;
+            for (int s = 0; s < kTrainTile; ++s) d += sGy[4 * s + i];
+            out[kOffB3 + i] = d;
+        }
+    }
+}
+
+// Training step after k_train_tile: the batch gradient (the tiles' rows summed in
+// tile order, as k_grad_reduce) and the Adam update of k_adam, in one launch.
+__global__ __launch_bounds__(256) void k_grad_adam(const float* __restrict__ partial, int tiles, float* __restrict__ p,
+                                                   float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+                                                   float b2, float eps, float c1, float c2)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= kNParam) return;
+    float gi = 0.0f;
+    for (int t = 0; t < tiles; ++t) gi += partial[(int64_t)t * kNParam + k];
+    const float mi = b1 * m[k] + (1.0f - b1) * gi;
+    const float vi = b2 * v[k] + (1.0f - b2) * gi * gi;
+    m[k] = mi;
+    v[k] = vi;
+    p[k] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Batch gradient: the sum of the tiles' rows of `partial`, in tile order.
+__global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ partial, int tiles,
+                                                     float* __restrict__ grad)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= kNParam) return;
+    float s = 0.0f;
+    for (int t = 0; t < tiles; ++t) s += partial[(int64_t)t * kNParam + k];
+    grad[k] = s;
 }
 
 __global__ void k_zero_f32(float* p, int64_t n)
@@ -1563,16 +1649,18 @@ static int model_upload(bk_model* m, const float* hostP)
     return model_cells(m);
 }
 
-static size_t grad_scratch_floats(int64_t B) { return (size_t)B * (2 + 4 * 64 + 3); }
+// Per-tile gradient rows of one batch.
+static size_t grad_scratch_floats(int64_t B) { return (size_t)((B + kTrainTile - 1) / kTrainTile) * kNParam; }
 
 static int launch_grad(const float* params, const float* u, const float* tgt, const float* tau, int64_t B,
                        int64_t n, uint64_t pa, uint64_t pb, int64_t start, float* grad, float* loss, float* scr,
                        hipStream_t s)
 {
-    const unsigned blocks = (unsigned)((B + 255) / 256);
-    const int st = launch(k_fwd_bwd, dim3(blocks), dim3(256), s, params, u, tgt, tau, B, n, pa, pb, start, scr, loss);
+    const unsigned tiles = (unsigned)((B + kTrainTile - 1) / kTrainTile);
+    const int st = launch(k_train_tile, dim3(tiles), dim3(kTrainThreads), s, params, u, tgt, tau, B, n, pa, pb, start,
+                          scr, loss);
     if (st != BK_OK) return st;
-    return launch(k_wgrad, dim3(kNParam), dim3(256), s, scr, B, grad);
+    return launch(k_grad_reduce, dim3((kNParam + 255) / 256), dim3(256), s, (const float*)scr, (int)tiles, grad);
 }
 
 }  // namespace bk
@@ -2031,9 +2119,17 @@ extern "C" int bk_model_train(bk_model* m, const double* nu, const double* x, in
             // cosine decay of the step size to 5% of its initial value
             const double frac = (double)step / (double)total;
             const float lr = (float)(cfg->lr * (0.05 + 0.95 * 0.5 * (1.0 + cos(M_PI * frac))));
-            st = launch_grad(m->params, U, T, tau, bs, n, pa, pb, b0, grad, loss, scr, s);
-            if (st == BK_OK) st = bk_adam_step(m->params, grad, mom, vel, kNParam, (int32_t)std::min<int64_t>(step, 1 << 30),
-                                               lr, cfg->beta1, cfg->beta2, cfg->eps, s);
+            // tile gradients, then their sum and the Adam update in one launch (the same
+            // arithmetic as bk_mlp_grad followed by bk_adam_step)
+            const unsigned tiles = (unsigned)((bs + kTrainTile - 1) / kTrainTile);
+            st = launch(k_train_tile, dim3(tiles), dim3(kTrainThreads), s, (const float*)m->params, (const float*)U,
+                        (const float*)T, (const float*)tau, bs, n, pa, pb, b0, scr, loss);
+            if (st == BK_OK) {
+                const int32_t t = (int32_t)std::min<int64_t>(step, 1 << 30);
+                const float c1 = 1.0f - powf(cfg->beta1, (float)t), c2 = 1.0f - powf(cfg->beta2, (float)t);
+                st = launch(k_grad_adam, dim3((kNParam + 255) / 256), dim3(256), s, (const float*)scr, (int)tiles,
+                            m->params, mom, vel, lr, cfg->beta1, cfg->beta2, cfg->eps, c1, c2);
+            }
         }
         float hl = 0.0f;
         if (st == BK_OK && (hipMemcpyAsync(&hl, loss, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
