@@ -234,6 +234,30 @@ __device__ __forceinline__ double halley_step(double f, double f1, double f2)
 // stop once a step is below 1e-7 (peak) or 1e-5 (window ends) of t: the error
 // left after such a step is of order its cube, below 1e-15 relative.
 
+// Starting points of the root searches below. They only seed Halley's method, so
+// they come from FP32 hardware operations (a few instructions against the library
+// asinh / acosh in FP64), moved outward by 1e-4 relative so that they keep the side
+// of the root the searches start from; beyond the FP32 range, log(2y) by the
+// table logarithm.
+// Upper bound of asinh(y), y > 0.
+__device__ __forceinline__ double asinh_start(double y, const double* T)
+{
+    if (y < 1e18) {
+        const float yf = (float)y;
+        return (double)(__logf(yf + __fsqrt_rn(fmaf(yf, yf, 1.0f))) * 1.0001f);
+    }
+    return log_tab(2.0 * y, T) * 1.0001;
+}
+// Lower bound of acosh(1 + eps), eps > 0: log1p(eps + sqrt(eps (2 + eps))).
+__device__ __forceinline__ double acosh1p_start(double eps, const double* T)
+{
+    if (eps < 1e18) {
+        const float e = (float)eps;
+        return (double)(log1pf(e + __fsqrt_rn(e * (2.0f + e))) * 0.9999f);
+    }
+    return log_tab(2.0 * eps, T) * 0.9999;
+}
+
 // Maximiser t* of g over t >= 0 when nu^2 > x (Sec. IV-B: otherwise t* = 0), the
 // zero of g' = nu tanh(nu t) - x sinh t. Since nu tanh < nu, it lies left of
 // asinh(nu/x), where the iteration starts (the bracket search of FINDRANGE is
@@ -241,7 +265,7 @@ __device__ __forceinline__ double halley_step(double f, double f1, double f2)
 // that would leave t > 0 are halved.
 __device__ inline double peak_solve(double nu, double x, const double* T)
 {
-    double t = asinh(fmin(nu / x, 1e300));
+    double t = asinh_start(fmin(nu / x, 1e300), T);
     for (int it = 0; it < 64; ++it) {
         const GDer d = g_derivs(nu, x, t, T);
         const double dt = halley_step(d.g1, d.g2, d.g3);
@@ -260,7 +284,7 @@ __device__ inline double peak_solve(double nu, double x, const double* T)
 __device__ inline double window_right(double nu, double x, double tstar, double chstar,
                                       double gstar, double L, const double* T)
 {
-    double t = acosh(chstar + L / x);
+    double t = acosh1p_start((chstar - 1.0) + L / x, T);
     const double tcap = tstar + 4.0 * (t - tstar) + 1.0;
     for (int it = 0; it < 64; ++it) {
         const GDer d = g_derivs(nu, x, t, T);
