@@ -52,8 +52,8 @@ NODE_SLOTS = load_node_slots()
 # null: HBM bytes from the FETCH_SIZE and WRITE_SIZE runs scaled by a plain 1 GiB
 # copy, and SQ_INSTS_VALU of one launch without statistics.
 TRAFFIC = {
-    "grid": {"src_sha": "8430eca83b444f74", "n": 1 << 24, "bytes": 416.6e6, "valu_insts": 100.8e6},
-    "matern_large": {"src_sha": "785e14e40d4e0dd3", "bytes": 2.03131e10, "valu_insts": 1.27044e10},
+    "grid": {"src_sha": "dde8dcae2b269c33", "n": 1 << 24, "bytes": 4.20051e8, "valu_insts": 1.17952e8},
+    "matern_large": {"src_sha": "dde8dcae2b269c33", "bytes": 2.03131e10, "valu_insts": 1.24188e10},
 }
 KERNEL_SOURCES = ("bk_mlp.hip", "bk_math.hpp", "bk_internal.hpp")
 
