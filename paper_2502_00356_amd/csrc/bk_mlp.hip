@@ -40,6 +40,7 @@ typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef double double2_t __attribute__((ext_vector_type(2)));
 
 namespace bk {
 
@@ -63,9 +64,10 @@ constexpr int kCellsLx = 512, kCellsNu = 64, kCells = kCellsLx * kCellsNu;
 // Learned Matern workspace: the window table and the interval plans of the call's
 // nu (kMaternTabBytes), then the wave bitmap (one bit per wave of the call).
 constexpr size_t kMaternTableOff = 0;                                   // kTableSize float4
-constexpr size_t kMaternPlanAOff = kMaternTableOff + 16 * kTableSize;     // (kTableSize - 1) float4
-constexpr size_t kMaternPlanBOff = kMaternPlanAOff + 16 * kTableSize;     // 3 (kTableSize - 1) double4
-constexpr size_t kMaternTabBytes = kMaternPlanBOff + 96 * kTableSize;    // 128 KiB
+constexpr size_t kMaternRecBytes = 96;                                  // one interval's plan record
+constexpr int kRecQ = (int)(kMaternRecBytes / 16);                        // its float4 slots
+constexpr size_t kMaternRecOff = kMaternTableOff + 16 * kTableSize;       // (kTableSize - 1) records
+constexpr size_t kMaternTabBytes = 128 * kTableSize;                      // 128 KiB (16 KiB unused)
 
 // Device-side constants of a model for inference.
 struct MlpDev {
@@ -369,66 +371,32 @@ __device__ inline LearnedPlan learned_plan(double tlo, double thi, int N, const 
     return P;
 }
 
-// The node sum of a plan (for its nu) at one x, its prefactor and the acceptance tests.
-// kBias: the terms are taken relative to 2^eb (eb in log2 units, an estimate of the
-// largest node's exponent, from the cell), so every FP32 exponential sees an argument
-// of moderate size and the 2^k 2^f split is not needed; the prefactor carries 2^eb.
-// Else the split is made at every node.
-// Node sum of the learned forms (terms relative to node 0, or to the plan's peak
-// node with kBias). kQf: the factor 1 + e^(-2 nu t) of a node is carried in FP32 as
-// P = e^(-2 nu t) (P' = rho P), the term formed as e + e P with one rounding. Each
-// step rounds P by 2^-24 relative and rho in FP32 is off by up to 2^-24, so P_m is
-// off by m 2^-23 relative, and the term by m 2^-23 P_m / (1 + P_m) <= 2^-23 m rho^m
-// <= 2^-23 / (e ln(1 / rho)); with 2 nu h >= 1/2 (rho <= e^-1/2) that is below 9e-8.
-// Otherwise (kQf false) the factor follows Q' = rho Q + (1 - rho) in FP64 and is
-// rounded to FP32 once per node.
-template <bool kBias, bool kQf, bool kQuads>
-__device__ inline void learned_sum(WalkF& w, int N, float Pf, float rhof, float& e0, float& e1, float& eprev,
-                                   float& elast, double& Sd)
+// Node sum of the standalone learned form: terms relative to node 0, or with kBias
+// to 2^eb (eb in log2 units, an estimate of the largest node's exponent from the
+// cell), so that every FP32 exponential sees an argument of moderate size and the
+// 2^k 2^f split is not needed (the prefactor carries 2^eb); else the split is made
+// at every node. The factor Q = 1 + e^(-2 nu t) follows Q' = rho Q + (1 - rho) in
+// FP64 and is rounded to FP32 once per node. An argument d converts to FP32 with an
+// absolute error of |d| 2^-24; the terms that carry the sum lie within a few units
+// of eb, the others are smaller by 2^-|d|, so this adds a few 1e-8 to the sum. The
+// FP32 terms are summed in FP64, whose rounding is negligible next to theirs.
+template <bool kBias>
+__device__ inline void learned_sum(WalkF& w, int N, float& e0, float& e1, float& eprev, float& elast, double& Sd)
 {
-    // the exponent is not bounded above without the bias (t_lo is not the peak), so
-    // the FP32 exponential is split as 2^k 2^f with k, f formed in FP64; the FP32
-    // terms are summed in FP64, whose rounding is negligible next to theirs.
-    // With the bias, an argument d converts to FP32 with an absolute error of
-    // |d| 2^-24; the terms that carry the sum lie within a few units of eb, the
-    // others are smaller by 2^-|d|, so this adds a few 1e-8 to the sum.
     auto node = [&]() {
         const double d = walkf_exponent2(w);
         float t;
-        if constexpr (kQf) {
-            const float ex = __builtin_amdgcn_exp2f((float)d);
-            t = fmaf(ex, Pf, ex);
-            Pf *= rhof;
-            walkf_step_noq(w);
+        if (kBias) {
+            t = __builtin_amdgcn_exp2f((float)d) * (float)w.Q;
         } else {
-            if (kBias) {
-                t = __builtin_amdgcn_exp2f((float)d) * (float)w.Q;
-            } else {
-                const double kf = rint(d);
-                t = ldexpf(__builtin_amdgcn_exp2f((float)(d - kf)) * (float)w.Q, (int)kf);
-            }
-            walkf_step(w);
+            const double kf = rint(d);
+            t = ldexpf(__builtin_amdgcn_exp2f((float)(d - kf)) * (float)w.Q, (int)kf);
         }
+        walkf_step(w);
         return t;
     };
-    // Nodes go in groups of four: a group is added pairwise in FP32 (two roundings,
-    // <= 1.2e-7 of the group, all terms positive) and the groups sum in FP64.
-    if constexpr (kQuads) {
-        // N + 1 is a multiple of four (N >= 7): whole groups only
-        const float ta = node(), tb = node(), tc = node(), td = node();
-        e0 = ta;
-        e1 = tb;
-        Sd = (double)((ta + tb) + (tc + td));
-        eprev = tc;
-        elast = td;
-        for (int m = 4; m < N; m += 4) {
-            const float ua = node(), ub = node(), uc = node(), ud = node();
-            Sd += (double)((ua + ub) + (uc + ud));
-            eprev = uc;
-            elast = ud;
-        }
-        return;
-    }
+    // groups of four are added pairwise in FP32 (two roundings, <= 1.2e-7 of the
+    // group, all terms positive) and the groups sum in FP64
     e0 = node();
     e1 = node();                               // N >= kNodeMin: at least five nodes
     Sd = (double)(e0 + e1);
@@ -456,115 +424,121 @@ __device__ inline void learned_sum(WalkF& w, int N, float Pf, float rhof, float&
     }
 }
 
-// kQfOk: the caller allows the FP32 node factor (taken where 2 nu h >= 1/2).
-// kQuads: the plan's N + 1 is a multiple of four.
-// kDirect: eb is the walk's first exponent itself (log2 of node 0's term, the
-// caller's bias folded in), and o.delta is Delta without a bias.
-template <bool kBias, bool kQfOk = false, bool kQuads = false, bool kDirect = false>
+// Right tail beyond the last node t_N, in units of the trapezoid sum S (integral /
+// h). g = log cosh(nu t) - x cosh t has g'' = nu^2 sech^2(nu t) - x cosh t,
+// decreasing in t: g is convex on [0, t_c) and concave on [t_c, inf) (t_c = 0 if
+// nu^2 <= x), and g' > 0 on (0, t_c], so the peak t* lies right of t_c. If e_N <
+// e_{N-1}, the mean value theorem puts a point xi > t* in (t_{N-1}, t_N) where g'(xi)
+// is the secant slope; g' decreases right of t_c, so |g'| >= |secant| on [t_N, inf)
+// and the tail is at most e_N / |log(e_N / e_{N-1})|. First without the logarithm:
+// |log r| >= 1 - r for r = e_N / e_{N-1} < 1, so e_N e_{N-1} <= tol S (e_{N-1} -
+// e_N) already implies the bound.
+__device__ __forceinline__ bool right_tail_ok(float eprev, float elast, float S)
+{
+    if (!(elast < eprev)) return false;
+    bool ok = elast * eprev <= kTailTol * S * (eprev - elast);
+    if (__builtin_expect(!ok, 0)) {             // rare: a branch, not computed for every entry
+        const float lr = __builtin_amdgcn_logf(elast * __builtin_amdgcn_rcpf(eprev)) * 0.69314718f;
+        ok = elast <= -lr * kTailTol * S;
+    }
+    return ok;
+}
+
+// Left tail below the first node t_lo > 0 (e_0 < e_1 needed, so t_lo < t*), in
+// units of S, for the same g. t_c is the fixed point of the decreasing map F(t) =
+// acosh(nu / sqrt(x cosh t)) / nu (0 where the argument is <= 1), so F(0) >= t_c,
+// and alternate iterates from there bound t_c from below and above: lo <= t_c <= up
+// (each FP32 value moved outward by 2^-10 relative, far above its rounding). F(0)
+// alone settles most windows (t_lo >= F(0)); the others take two more pairs of
+// iterates. D = g(t_lo) - g(0) >= Delta = nu t_lo - ln 2 - x (cosh t_lo - 1) (the
+// log(1 + e^(-2 nu t_lo)) part dropped; the caller passes Delta), and ll = log(e_1 /
+// e_0) = s h, s the secant slope of the first two nodes.
+//  - t_lo >= up: as on the right, g'(t) >= s on [t_c, t_lo], so g lies below the
+//    line through t_lo of slope s there; on [0, up] g is below the chord from (0,
+//    g(0)) to (up, line(up)) (convex up to t_c, and the line bounds the rest), so
+//    the tail is at most e_0 (1 / ll + (up / h) (e^a - e^b) / (a - b)), a = -ll (t_lo
+//    - up) / h, b = -D.
+//  - t_lo <= lo: g is convex on [0, t_lo], below its chord, and the tail is at most
+//    e_0 (t_lo / h) (1 - e^-D) / D.
+//  - otherwise the window is rejected.
+__device__ inline bool left_tail_ok(double x, double nu, float tlof, float hf, float e0, float e1, float delta,
+                                    float S)
+{
+    if (!(e0 < e1)) return false;
+    const float ll = __builtin_amdgcn_logf(e1 * __builtin_amdgcn_rcpf(e0)) * 0.69314718f;
+    const float nuf = (float)nu, xf = (float)x, inu = __builtin_amdgcn_rcpf(nuf);
+    auto F = [&](float ch) {                    // ch = cosh t
+        const float y = nuf * __builtin_amdgcn_rsqf(xf * ch);
+        if (!(y > 1.0f)) return 0.0f;
+        return __builtin_amdgcn_logf(y + __builtin_amdgcn_sqrtf(fmaf(y, y, -1.0f))) * 0.69314718f * inu;
+    };
+    auto coshf_ = [](float t) {
+        const float e = __builtin_amdgcn_exp2f(t * 1.44269504f);
+        return 0.5f * (e + __builtin_amdgcn_rcpf(e));
+    };
+    const float ih = __builtin_amdgcn_rcpf(hf);
+    float up = F(1.0f) * 1.0009765625f, lo = 0.0f;
+    if (!(tlof >= up)) {                        // t_lo near t_c: narrow the bounds
+        lo = F(coshf_(up)) * 0.9990234375f;
+        up = fminf(up, F(coshf_(lo)) * 1.0009765625f);
+        lo = fmaxf(lo, F(coshf_(up)) * 0.9990234375f);
+        up = fminf(up, F(coshf_(lo)) * 1.0009765625f);
+    }
+    const float D = fmaxf(delta, 0.0f);
+    float bound;
+    if (tlof >= up) {
+        const float a = -ll * (tlof - up) * ih, b = -D, dab = a - b;
+        const float ea = __builtin_amdgcn_exp2f(a * 1.44269504f), eb2 = __builtin_amdgcn_exp2f(b * 1.44269504f);
+        // mean of e^t between b and a (at most the larger end value)
+        const float chord = fabsf(dab) > 1e-3f ? (ea - eb2) * __builtin_amdgcn_rcpf(dab) : fmaxf(ea, eb2);
+        bound = e0 * (__builtin_amdgcn_rcpf(ll) + up * ih * chord);
+    } else if (tlof <= lo) {
+        const float r = D > 1e-3f ? (1.0f - __builtin_amdgcn_exp2f(-D * 1.44269504f)) * __builtin_amdgcn_rcpf(D)
+                                  : 1.0f;       // (1 - e^-D) / D <= 1
+        bound = e0 * tlof * ih * r;
+    } else {
+        return false;
+    }
+    return bound <= kTailTol * S;
+}
+
+// The node sum of a plan (for its nu) at one x, its prefactor and the acceptance
+// tests. Reference t_ref = t_lo (node 0), outward walk only; kBias as learned_sum.
+template <bool kBias>
 __device__ inline LearnedOut learned_walk(double x, double nu, const LearnedPlan& P, double eb = 0.0)
 {
     LearnedOut o;
     o.reason = 0;
     const double tlo = P.tlo, h = P.h;
     const int N = P.N;
-    // reference t_ref = t_lo; sinh^2(t/2) = (cosh t - 1) / 2 loses ~1e-16 absolute,
-    // i.e. at most ~2e-13 relative in the scale for x <= 1e3, far inside this form's budget
+    // sinh^2(t/2) = (cosh t - 1) / 2 loses ~1e-16 absolute, i.e. at most ~2e-13
+    // relative in the scale for x <= 1e3, far inside this form's budget
     o.delta = P.dnu - x * (P.c0 - 1.0);
-    if (kBias && !kDirect) o.delta = fma(eb, kLn2, o.delta);
     WalkF w;
     w.kappa = P.kappa;
     w.c = P.c0;
     w.cn = P.c1;
     w.a2 = -x * kLog2e;
     w.b2 = P.b2;
-    if (kDirect) {
-        w.e = eb;
-    } else {
-        w.e = x * P.c0 * kLog2e;
-        if (kBias) w.e -= eb;
+    w.e = x * P.c0 * kLog2e;
+    if (kBias) {
+        w.e -= eb;
+        o.delta = fma(eb, kLn2, o.delta);
     }
     w.rho = P.rho;
     w.omr = 1.0 - P.rho;
     w.Q = P.Q0;
     float e0, e1, eprev, elast;
     double Sd;
-    if (kQfOk && P.b2 >= 0.25 * kLog2e)        // b2 = nu h log2 e: 2 nu h >= 1/2
-        learned_sum<kBias, kQfOk, kQuads>(w, N, (float)(P.Q0 - 1.0), (float)P.rho, e0, e1, eprev, elast, Sd);
-    else
-        learned_sum<kBias, false, kQuads>(w, N, 0.0f, 0.0f, e0, e1, eprev, elast, Sd);
+    learned_sum<kBias>(w, N, e0, e1, eprev, elast, Sd);
     Sd -= (double)(0.5f * (e0 + elast));       // one FP32 rounding of a term-sized value
     o.hs = h * Sd;
     if (!(Sd > 0.0) || !isfinite(Sd)) { o.reason = BK_STAT_FB_NONFINITE; return o; }
     const float S = (float)Sd;
-    // Tails beyond the ends, in units of the sum S (integral / h). g = log cosh(nu t)
-    // - x cosh t has g'' = nu^2 sech^2(nu t) - x cosh t, decreasing in t: g is convex
-    // on [0, t_c) and concave on [t_c, inf) (t_c = 0 if nu^2 <= x), and g' > 0 on
-    // (0, t_c], so the peak t* lies right of t_c.
-    // Right: if e_N < e_{N-1}, the mean value theorem puts a point xi > t* in
-    // (t_{N-1}, t_N) where g'(xi) is the secant slope; g' decreases right of t_c, so
-    // |g'| >= |secant| on [t_N, inf) and the tail is at most e_N / |log(e_N / e_{N-1})|.
-    // First without the logarithm: |log r| >= 1 - r for r = e_N / e_{N-1} < 1, so
-    // e_N e_{N-1} <= tol S (e_{N-1} - e_N) already implies the bound.
-    if (!(elast < eprev)) { o.reason = BK_STAT_FB_TAIL; return o; }
-    if (!(elast * eprev <= kTailTol * S * (eprev - elast))) {
-        const float lr = __builtin_amdgcn_logf(elast * __builtin_amdgcn_rcpf(eprev)) * 0.69314718f;
-        if (elast > -lr * kTailTol * S) { o.reason = BK_STAT_FB_TAIL; return o; }
-    }
+    if (!right_tail_ok(eprev, elast, S)) { o.reason = BK_STAT_FB_TAIL; return o; }
     if (tlo > 0.0) {
-        // Left (t_lo > 0, e_0 < e_1, so t_lo < t*). t_c is the fixed point of the
-        // decreasing map F(t) = acosh(nu / sqrt(x cosh t)) / nu (0 where the argument is
-        // <= 1), so F(0) >= t_c, and alternate iterates from there bound t_c from below
-        // and above: lo <= t_c <= up (each FP32 value moved outward by 2^-10 relative,
-        // far above its rounding). F(0) alone settles most windows (t_lo >= F(0));
-        // the others take two more pairs of iterates.
-        // D = g(t_lo) - g(0) >= Delta = nu t_lo - ln 2 - x (cosh t_lo - 1) (the
-        // log(1 + e^(-2 nu t_lo)) part is dropped), and ll = log(e_1 / e_0) = s h, s the
-        // secant slope of the first two nodes.
-        //  - t_lo >= up: as on the right, g'(t) >= s on [t_c, t_lo], so g lies below the
-        //    line through t_lo of slope s there; on [0, up] g is below the chord from
-        //    (0, g(0)) to (up, line(up)) (convex up to t_c, and the line bounds the rest),
-        //    so the tail is at most e_0 (1 / ll + (up / h) (e^a - e^b) / (a - b)),
-        //    a = -ll (t_lo - up) / h, b = -D.
-        //  - t_lo <= lo: g is convex on [0, t_lo], below its chord, and the tail is at
-        //    most e_0 (t_lo / h) (1 - e^-D) / D.
-        //  - otherwise the window is rejected.
-        const float ll = __builtin_amdgcn_logf(e1 * __builtin_amdgcn_rcpf(e0)) * 0.69314718f;
-        if (!(e0 < e1)) { o.reason = BK_STAT_FB_TAIL; return o; }
-        const float nuf = (float)nu, xf = (float)x, inu = __builtin_amdgcn_rcpf(nuf);
-        auto F = [&](float t, float ch) {           // ch = cosh t
-            const float y = nuf * __builtin_amdgcn_rsqf(xf * ch);
-            if (!(y > 1.0f)) return 0.0f;
-            return __builtin_amdgcn_logf(y + __builtin_amdgcn_sqrtf(fmaf(y, y, -1.0f))) * 0.69314718f * inu;
-        };
-        auto coshf_ = [](float t) {
-            const float e = __builtin_amdgcn_exp2f(t * 1.44269504f);
-            return 0.5f * (e + __builtin_amdgcn_rcpf(e));
-        };
-        const float tlof = (float)tlo, ih = __builtin_amdgcn_rcpf((float)h);
-        float up = F(0.0f, 1.0f) * 1.0009765625f, lo = 0.0f;
-        if (!(tlof >= up)) {                        // t_lo near t_c: narrow the bounds
-            lo = F(up, coshf_(up)) * 0.9990234375f;
-            up = fminf(up, F(lo, coshf_(lo)) * 1.0009765625f);
-            lo = fmaxf(lo, F(up, coshf_(up)) * 0.9990234375f);
-            up = fminf(up, F(lo, coshf_(lo)) * 1.0009765625f);
-        }
-        const float D = fmaxf((float)(kBias && !kDirect ? fma(-eb, kLn2, o.delta) : o.delta), 0.0f);
-        float bound;
-        if (tlof >= up) {
-            const float a = -ll * (tlof - up) * ih, b = -D, dab = a - b;
-            const float ea = __builtin_amdgcn_exp2f(a * 1.44269504f), eb2 = __builtin_amdgcn_exp2f(b * 1.44269504f);
-            // mean of e^t between b and a (at most the larger end value)
-            const float chord = fabsf(dab) > 1e-3f ? (ea - eb2) * __builtin_amdgcn_rcpf(dab) : fmaxf(ea, eb2);
-            bound = e0 * (__builtin_amdgcn_rcpf(ll) + up * ih * chord);
-        } else if (tlof <= lo) {
-            const float r = D > 1e-3f ? (1.0f - __builtin_amdgcn_exp2f(-D * 1.44269504f)) * __builtin_amdgcn_rcpf(D)
-                                      : 1.0f;       // (1 - e^-D) / D <= 1
-            bound = e0 * tlof * ih * r;
-        } else {
-            o.reason = BK_STAT_FB_TAIL;
-            return o;
-        }
-        if (!(bound <= kTailTol * S)) { o.reason = BK_STAT_FB_TAIL; return o; }
+        const float D = (float)(kBias ? fma(-eb, kLn2, o.delta) : o.delta);
+        if (!left_tail_ok(x, nu, (float)tlo, (float)h, e0, e1, D, S)) { o.reason = BK_STAT_FB_TAIL; return o; }
     }
     return o;
 }
@@ -957,19 +931,27 @@ __global__ __launch_bounds__(256) void k_matern_table_solver(MlpDev M, float nu,
 // Quadrature plans of the Matern table's cells (between rows k and k + 1) at the
 // launch's nu and node target, one lane per cell: the union of the two rows'
 // windows with the model's margins, the node count raised to the strip-bound floor
-// at the cell's larger x (the floor falls with x, so it holds over the cell), and
-// the whole walk set-up, nu included. Layout as the prediction cells' plans, with
-// the nu-dependent part (rho, Q0, b2, dnu) in a second double4 and, in a third, the
-// prefactor's pieces at the interval's lower end z_k, so that an entry needs only
-// log1p(z / z_k - 1), |z / z_k - 1| < 0.016, for log z. The walk is biased by 2^eb,
-// eb = B0 - z B1 (log2 of the term at the node m_pk of the largest term at the
-// interval's middle, relative to node 0: B0 = nu m_pk h log2 e, B1 = (cosh t_pk -
-// cosh t_lo) log2 e); the third double4 holds A2 = (pref + nu log z_k + nu t_lo -
-// ln 2) log2 e + B0, 1 / z_k, C2 = B1 + cosh(t_lo) log2 e and B0.
-__global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, double Lq, double pref,
-                                                      const float* __restrict__ table,
-                                                       float4_t* __restrict__ pa,
-                                                      double4_t* __restrict__ pb)
+// at the cell's larger x (the floor falls with x, so it holds over the cell) and then
+// to N + 1 a multiple of four, and the whole walk set-up, nu and sigma^2 included.
+// The walk is biased by 2^eb, eb = B0 - z B1 (log2 of the term at the node m_pk of
+// the largest term at the interval's middle, relative to node 0: B0 = nu m_pk h
+// log2 e, B1 = (cosh t_pk - cosh t_lo) log2 e). With zl = z log2 e, the log2 of the
+// prefactor times sigma^2 h, divided by that bias, is
+//   y = A2 + nu log2(z / z_k) - zl cosh t_pk,
+//   A2 = (pref + ln(sigma^2 h) + nu ln z_k + nu t_lo - ln 2) log2 e + B0,
+// and with y = kq + f (kq an integer) node 0's exponent is f - eb = A2 + nu log2(z /
+// z_k) - B0 - kq - zl cosh t_lo. One 96-byte record per interval (kMaternRecBytes):
+//   [0] float4  t_lo, P_0 = e^(-2 nu t_lo), rho = e^(-2 nu h) (FP32), N (int; -1: no plan)
+//   [1] double2 cosh t_lo, cosh(t_lo + h)
+//   [2] double2 2 cosh h, b2 = nu h log2 e
+//   [3] double2 A2, ln 2 / z_k
+//   [4] double2 cosh t_pk, B0
+//   [5]         rho (FP64), h (FP32), raised (int): read off the main path only
+// t_lo is rounded to FP32 first, so that every field describes the same window.
+// ln sigma^2 is folded in where sigma^2 is finite and positive; the caller applies
+// sigma^2 = 0 or +inf itself.
+__global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, double Lq, double pref, double lsig,
+                                                      const float* __restrict__ table, float4_t* __restrict__ rec)
 {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= kTableSize - 1) return;
@@ -982,46 +964,54 @@ __global__ __launch_bounds__(256) void k_matern_plans(MlpDev M, double nu, doubl
     bool raised;
     decode_window(M, fminf(t0[0], t1[0]), fmaxf(t0[1], t1[1]), fmaxf(t0[2], t1[2]), nu, exp10(lxm), Lq, tlo, thi,
                   N, raised);
+    tlo = (double)(float)tlo;
     // N + 1 raised to a multiple of four (a finer step on the same window), so that
-    // the kernel's walk runs whole groups of four nodes with no remainder code
+    // the kernel's walk runs whole groups of four nodes; N >= kNodeMin gives N >= 7
     if (N >= 0) N = ((N + 4) & ~3) - 1;
-    const bool valid = thi > tlo && isfinite(thi) && N >= 0 && N <= kNodeMax;
-    float4_t a;
-    a[0] = (float)tlo;
-    a[1] = (float)thi;
-    a[2] = __int_as_float(valid ? N : -1);
-    a[3] = __int_as_float(raised ? 1 : 0);
-    pa[k] = a;
-    LearnedPlan P = {};
+    const bool valid = thi > tlo && isfinite(thi) && N >= 7 && N <= kNodeMax;
+    double h = 0.0, c0 = 0.0, c1 = 0.0, kappa = 0.0, rho = 0.0, b2 = 0.0, A2 = 0.0, izk = 0.0, chpk = 0.0, B0 = 0.0;
+    float P0 = 0.0f;
     if (valid) {
-        P.tlo = tlo;
-        P.N = N;
-        P.h = (thi - tlo) * (double)__builtin_amdgcn_rcpf((float)N);
-        P.c0 = cosh(tlo);
-        P.c1 = cosh(tlo + P.h);
-        P.kappa = 2.0 * cosh(P.h);
-        plan_for_nu(P, nu, rule_tab().tab);
-    }
-    const double zk = exp10((double)M.lx_lo + (double)k * dlx);
-    double B0 = 0.0, B1 = 0.0;
-    if (valid) {
+        const double* T = rule_tab().tab;
+        h = (thi - tlo) * (double)__builtin_amdgcn_rcpf((float)N);
+        c0 = cosh(tlo);
+        c1 = cosh(tlo + h);
+        kappa = 2.0 * cosh(h);
+        rho = exp_tab(-2.0 * nu * h, T);
+        P0 = __expf((float)(-2.0 * nu * tlo));
+        b2 = nu * h * kLog2e;
+        const double zk = exp10((double)M.lx_lo + (double)k * dlx);
         const double zc = exp10((double)M.lx_lo + ((double)k + 0.5) * dlx);
         int mpk = 0;
         double best = 0.0;
         for (int m = 1; m <= N; ++m) {
-            const double d = nu * (double)m * P.h - zc * (cosh(tlo + (double)m * P.h) - P.c0);
+            const double d = nu * (double)m * h - zc * (cosh(tlo + (double)m * h) - c0);
             if (d > best) { best = d; mpk = m; }
         }
-        B0 = nu * (double)mpk * P.h * kLog2e;
-        B1 = (cosh(tlo + (double)mpk * P.h) - P.c0) * kLog2e;
+        B0 = nu * (double)mpk * h * kLog2e;
+        chpk = cosh(tlo + (double)mpk * h);
+        A2 = (pref + lsig + log(h) + nu * log(zk) + nu * tlo - kLn2) * kLog2e + B0;
+        izk = kLn2 / zk;
     }
-    // third double4: A2, 1 / z_k, C2, B0 (the prefactor and node 0's exponent in log2
-    // units, see k_matern_learned)
-    const double4_t b0 = {P.h, P.c0, P.c1, P.kappa}, b1 = {P.rho, P.Q0, P.b2, P.dnu};
-    const double4_t b2 = {(pref + nu * log(zk) + P.dnu) * kLog2e + B0, 1.0 / zk, B1 + P.c0 * kLog2e, B0};
-    pb[3 * k] = b0;
-    pb[3 * k + 1] = b1;
-    pb[3 * k + 2] = b2;
+    float4_t* r = rec + kRecQ * k;
+    float4_t q0;
+    q0[0] = (float)tlo;
+    q0[1] = P0;
+    q0[2] = (float)rho;
+    q0[3] = __int_as_float(valid ? N : -1);
+    r[0] = q0;
+    const double2_t q1 = {c0, c1}, q2 = {kappa, b2}, q3 = {A2, izk}, q4 = {chpk, B0};
+    *(double2_t*)(r + 1) = q1;
+    *(double2_t*)(r + 2) = q2;
+    *(double2_t*)(r + 3) = q3;
+    *(double2_t*)(r + 4) = q4;
+    double2_t q5;
+    q5[0] = rho;
+    q5[1] = 0.0;
+    float4_t q5f = __builtin_bit_cast(float4_t, q5);
+    q5f[2] = (float)h;
+    q5f[3] = __int_as_float(raised ? 1 : 0);
+    r[5] = q5f;
 }
 
 // log(1 + u) for |u| <= 0.02 in FP32, by its Taylor series through u^4: the
@@ -1072,6 +1062,58 @@ __device__ inline void wave_count_l(unsigned long long* dst, unsigned int v)
     if ((threadIdx.x & 63) == 0 && a) atomicAdd(dst, a);
 }
 
+// Node sum of the learned Matern walk over N + 1 = 4q nodes (q >= 2). Node m's
+// term is 2^(d_m) (1 + P_m): d_m = -zl c_m + e_m in log2 units, c_m = cosh t_m by
+// the recurrence c_(m+1) = kappa c_m - c_(m-1), e_m advanced by b2 = nu h log2 e,
+// and P_m = e^(-2 nu t_m).
+// kQf: P is carried in FP32 (P' = rho P) and the term formed as e + e P with one
+// rounding. Each step rounds P by 2^-24 relative and rho in FP32 is off by up to
+// 2^-24, so P_m is off by m 2^-23 relative, and the term by m 2^-23 P_m / (1 + P_m)
+// <= 2^-23 m rho^m <= 2^-23 / (e ln(1 / rho)); with 2 nu h >= 1/2 (rho <= e^-1/2)
+// that is below 9e-8. Otherwise Q = 1 + P follows Q' = rho Q + (1 - rho) in FP64
+// and is rounded to FP32 once per node.
+// Nodes go in groups of four, added pairwise in FP32 (two roundings, <= 1.2e-7 of
+// the group, all terms positive); the groups sum in FP64. The trapezoid's end
+// weights 1/2 are taken inside the first and last groups (an exact halving and the
+// group's own rounding). Returns the sum, with the first two and last two terms.
+template <bool kQf>
+__device__ inline double matern_node_sum(double zl, double c, double cn, double kappa, double e, double b2, float P,
+                                         float rhof, double Q, double rho, double omr, int N, float& e0, float& e1,
+                                         float& eprev, float& elast)
+{
+    auto node = [&]() {
+        const double d = fma(-zl, c, e);
+        const double c2 = fma(kappa, cn, -c);
+        c = cn;
+        cn = c2;
+        e += b2;
+        const float ex = __builtin_amdgcn_exp2f((float)d);
+        float t;
+        if constexpr (kQf) {
+            t = fmaf(ex, P, ex);
+            P *= rhof;
+        } else {
+            t = ex * (float)Q;
+            Q = fma(Q, rho, omr);
+        }
+        return t;
+    };
+    const float ta = node(), tb = node(), tc = node(), td = node();
+    e0 = ta;
+    e1 = tb;
+    double Sd = (double)(fmaf(ta, 0.5f, tb) + (tc + td));
+    // middle groups start at nodes 4, 8, ..., N - 7 (a counter common to the wave)
+    const int mlast = N - 7;
+    for (int m = 4; m <= mlast; m += 4) {
+        const float ua = node(), ub = node(), uc = node(), ud = node();
+        Sd += (double)((ua + ub) + (uc + ud));
+    }
+    const float ua = node(), ub = node(), uc = node(), ud = node();
+    eprev = uc;
+    elast = ud;
+    return Sd + (double)((ua + ub) + fmaf(ud, 0.5f, uc));
+}
+
 // Learned Matern. Wave w of the call (global workgroup index times 4 plus the wave
 // in the group) covers 64 rows of a tile column block and 8 of its columns. An
 // entry the learned form rejects is written as NaN and bit w of the call's wave
@@ -1080,13 +1122,16 @@ __device__ inline void wave_count_l(unsigned long long* dst, unsigned int v)
 // registers (and so its occupancy) those of the learned pass. kStats: the
 // statistics variant (lanes past a ragged tile's last row stay in the wave, idle,
 // so that the wave can sum its counts).
+// kb = log2(e) / beta; an entry's interval is fpos = fa log2(zl) + fb in
+// [0, kTableSize - 1] (zl = z log2 e); sig_mul: sigma^2 where it is 0 or +inf (the
+// records then carry no ln sigma^2), else 1 and unused.
 template <typename OutT, bool kStats>
-__global__ __launch_bounds__(256, 8) void k_matern_learned(MlpDev M, const float4_t* __restrict__ plan_a,
-                                                        const double4_t* __restrict__ plan_b,
+__global__ __launch_bounds__(256, 8) void k_matern_learned(const float4_t* __restrict__ rec,
                                                         const double* __restrict__ lx_, const double* __restrict__ ly_,
-                                                        TileGeomL g, int64_t tile_base, double sigma2,
-                                                        double inv_beta, double nu, unsigned int* __restrict__ bitmap,
-                                                        OutT* __restrict__ out, unsigned long long* __restrict__ stats)
+                                                        TileGeomL g, int64_t tile_base, double sigma2, double kb,
+                                                        float fa, float fb, int nu_ok, double nu, double sig_mul,
+                                                        unsigned int* __restrict__ bitmap, OutT* __restrict__ out,
+                                                        unsigned long long* __restrict__ stats)
 {
     constexpr int kColsPerWave = 8, kColsPerGroup = 32;
     // block -> (tile, row block, column block) in 32-bit arithmetic (a 64-bit
@@ -1109,90 +1154,107 @@ __global__ __launch_bounds__(256, 8) void k_matern_learned(MlpDev M, const float
     const int64_t base = tile_offset_l(g.n, g.ts, g.T, g.lower, I, J);
     const int64_t ilr = row_ok ? il : 0;
     const double xi = lx_[I * g.ts + ilr], yi = ly_[I * g.ts + ilr];
+    // the row point is waited for here, once: a wait for it inside the column loop
+    // would also wait for the previous column's store
+    asm volatile("" ::"v"(xi), "v"(yi));
     const int cend = (kStats && (!row_ok || jl0 >= nJ)) ? 0 : (int)min((int64_t)kColsPerWave, nJ - jl0);
-    const float tscale = (float)(kTableSize - 1) / (M.lx_hi - M.lx_lo);
-    const bool nu_ok = (float)nu >= M.nu_lo && (float)nu <= M.nu_hi;
+    const double* __restrict__ xc = lx_ + J * g.ts + jl0;      // this wave's columns
+    const double* __restrict__ yc = ly_ + J * g.ts + jl0;
     const double nul2e = nu * kLog2e;
     bool rejected = false;
     unsigned int c_ent = 0, c_nodes = 0, c_range = 0, c_tail = 0, c_nonfin = 0, c_raised = 0;
     unsigned int col_nodes[kColsPerWave] = {};      // statistics: nodes per column walked
+    double xj = 0.0, yj = 0.0;
+    if (cend > 0) {
+        xj = xc[0];
+        yj = yc[0];
+    }
     for (int c = 0; c < cend; ++c) {
-        const int64_t jl = jl0 + c;
-        const double dx = lx_[J * g.ts + jl] - xi, dy = ly_[J * g.ts + jl] - yi;
-        // r from the hardware reciprocal square root (about 5e-8 relative) and one
-        // Goldschmidt step, which squares that error (measured: <= 4.1e-15 relative
-        // over r^2 in [1e-40, 1e4]); r^2 near the bottom of the normal range takes
-        // the library sqrt
+        // the next column's point is read one column ahead
+        const int cnext = c + 1 < cend ? c + 1 : c;
+        const double xjn = xc[cnext], yjn = yc[cnext];
+        const double dx = xj - xi, dy = yj - yi;
+        xj = xjn;
+        yj = yjn;
         const double r2 = dx * dx + dy * dy;
-        double rr;
-        if (r2 > 1e-290) {
-            const double y = __builtin_amdgcn_rsq(r2);
-            const double s0 = r2 * y, h0 = 0.5 * y;
-            rr = fma(s0, fma(-s0, h0, 0.5), s0);
-        } else {
-            rr = sqrt(r2);
-        }
         OutT val = (OutT)sigma2;
-        if (rr != 0.0) {
-            const double z = rr * inv_beta;
-            const float lz = __log2f((float)z) * 0.30102999566f;
-            bool ok = nu_ok && lz >= M.lx_lo && lz <= M.lx_hi;
+        if (r2 != 0.0) {
+            // r from the hardware reciprocal square root (about 5e-8 relative) and one
+            // Goldschmidt step, which squares that error (measured: <= 4.1e-15 relative
+            // over r^2 in [1e-40, 1e4]). r^2 far below that (no such pair of distinct
+            // points within the training box's x range) gives no finite zl, or one
+            // outside the box, and fails the range test.
+            const double yr = __builtin_amdgcn_rsq(r2);
+            const double s0 = r2 * yr, h0 = 0.5 * yr;
+            const double zl = fma(s0, fma(-s0, h0, 0.5), s0) * kb;
+            const float fpos = fmaf(__builtin_amdgcn_logf((float)zl), fa, fb);
+            bool ok = nu_ok && fpos >= 0.0f && fpos <= (float)(kTableSize - 1);
             if (kStats && !ok) c_range += 1;
-            double hs = 0.0, kq = 0.0;
+            double Sd = 0.0, kq = 0.0;
+            float S = 0.0f;
             if (ok) {
-                float fpos = (lz - M.lx_lo) * tscale;
-                int k0 = min(max((int)fpos, 0), kTableSize - 2);
-                const float4_t a = plan_a[k0];
-                const int N = __float_as_int(a[2]);
-                if (kStats) c_raised += (unsigned int)(__float_as_int(a[3]) & 1);
-                if (N >= 0) {                   // N + 1 is a multiple of four (k_matern_plans)
-                    const double4_t b0 = plan_b[3 * k0], b1 = plan_b[3 * k0 + 1], b2 = plan_b[3 * k0 + 2];
-                    LearnedPlan P;
-                    P.tlo = (double)a[0];
-                    P.N = N;
-                    P.h = b0[0];
-                    P.c0 = b0[1];
-                    P.c1 = b0[2];
-                    P.kappa = b0[3];
-                    P.rho = b1[0];
-                    P.Q0 = b1[1];
-                    P.b2 = b1[2];
-                    P.dnu = b1[3];
-                    // In log2 units, with the walk's bias eb0 = B0 - z B1 (node t_pk's term
-                    // relative to node 0, k_matern_plans), the prefactor's exponent
-                    // (pref + nu log z + Delta - z) log2 e + eb0 is
-                    //   y = nu log2(z / z_k) + A2 - z C2,
-                    // A2 = (pref + nu log z_k + nu t_lo - ln 2) log2 e + B0, C2 = B1 + cosh(t_lo) log2 e,
-                    // and node 0's exponent is x cosh(t_lo) log2 e - eb0 = z C2 - B0. With
-                    // y = kq + f (|f| <= 1/2), f joins node 0's exponent (every node term
-                    // scaled by 2^f) and 2^kq is applied to the result exactly.
-                    const double y = fma(nul2e, (double)log1p_small_f((float)fma(z, b2[1], -1.0)),
-                                         fma(-z, b2[2], b2[0]));
-                    kq = rint(y);
-                    const double e_init = fma(z, b2[2], (y - kq) - b2[3]);
-                    LearnedOut lo = learned_walk<true, true, true, true>(z, nu, P, e_init);
-                    ok = lo.reason == 0;
-                    if (kStats) {
+                // the whole record is read at once (an interval without a plan, N < 0,
+                // holds zeros and is walked harmlessly, then rejected)
+                const unsigned k0 = min((unsigned)fpos, (unsigned)(kTableSize - 2));
+                const float4_t* R = rec + __umul24(k0, (unsigned)kRecQ);
+                const float4_t q0 = R[0];
+                const double2_t q1 = *(const double2_t*)(R + 1), q2 = *(const double2_t*)(R + 2);
+                const double2_t q3 = *(const double2_t*)(R + 3), q4 = *(const double2_t*)(R + 4);
+                const int N = __float_as_int(q0[3]);
+                if (kStats) c_raised += (unsigned int)(__float_as_int(R[5][3]) & 1);
+                // y = A2 + nu log2(z / z_k) - zl cosh t_pk, y = kq + f; node 0's exponent
+                // A2 + nu log2(z / z_k) - B0 - kq - zl cosh t_lo (k_matern_plans).
+                // log(z / z_k) = log1p(u), |u| < 0.016.
+                const double w = fma(nul2e, (double)log1p_small_f((float)fma(zl, q3[1], -1.0)), q3[0]);
+                kq = rint(fma(-zl, q4[0], w));
+                const double e_init = (w - q4[1]) - kq;
+                float e0, e1, eprev, elast;
+                if (q2[1] >= 0.25 * kLog2e) {       // b2 = nu h log2 e: 2 nu h >= 1/2
+                    Sd = matern_node_sum<true>(zl, q1[0], q1[1], q2[0], e_init, q2[1], q0[1], q0[2], 0.0, 0.0, 0.0,
+                                               N, e0, e1, eprev, elast);
+                } else {
+                    const double rho = *(const double*)(R + 5);
+                    Sd = matern_node_sum<false>(zl, q1[0], q1[1], q2[0], e_init, q2[1], 0.0f, 0.0f,
+                                                1.0 + (double)q0[1], rho, 1.0 - rho, N, e0, e1, eprev, elast);
+                }
+                S = (float)Sd;
+                int reason = 0;
+                if (N < 0 || !(Sd > 0.0) || !isfinite(Sd)) {
+                    reason = BK_STAT_FB_NONFINITE;
+                } else if (!right_tail_ok(eprev, elast, S)) {
+                    reason = BK_STAT_FB_TAIL;
+                } else if (q0[0] > 0.0f) {
+                    // Delta = nu t_lo - ln 2 - z (cosh t_lo - 1), without the bias
+                    const double z = zl * kLn2, tlo = (double)q0[0];
+                    const float D = (float)(fma(nu, tlo, -kLn2) - z * (q1[0] - 1.0));
+                    if (!left_tail_ok(z, nu, q0[0], R[5][2], e0, e1, D, S)) reason = BK_STAT_FB_TAIL;
+                }
+                ok = reason == 0;
+                if (kStats) {
+                    if (N >= 0) {
                         c_ent += 1;
                         c_nodes += (unsigned int)(N + 1);
                         col_nodes[c] = (unsigned int)(N + 1);
-                        c_tail += lo.reason == BK_STAT_FB_TAIL ? 1u : 0u;
-                        c_nonfin += lo.reason == BK_STAT_FB_NONFINITE ? 1u : 0u;
+                        c_tail += reason == BK_STAT_FB_TAIL ? 1u : 0u;
                     }
-                    hs = lo.hs;
-                } else {
-                    ok = false;
-                    if (kStats) c_nonfin += 1;
+                    c_nonfin += reason == BK_STAT_FB_NONFINITE ? 1u : 0u;
                 }
             }
             if (ok) {
-                val = scale2_out<OutT>(sigma2 * hs, (int)kq);
+                // Sd lies within a few powers of two of 1 (the terms are taken relative
+                // to the largest), so the FP32 scaling is exact unless the value itself
+                // leaves the FP32 range
+                if constexpr (sizeof(OutT) == sizeof(float))
+                    val = ldexpf(S, (int)kq);
+                else
+                    val = ldexp(Sd, (int)kq);
+                if (sig_mul != 1.0) val *= (OutT)sig_mul;
             } else {
                 val = (OutT)__builtin_nan("");
                 rejected = true;
             }
         }
-        out[base + il + jl * mI] = val;
+        out[base + il + (jl0 + c) * mI] = val;
     }
     // lane 0 is active whenever any lane of the wave is (rows grow with the lane)
     if (__ballot(rejected) != 0ull && lane == 0) {
@@ -1716,8 +1778,7 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
     if (!workspace || workspace_bytes < need) return BK_ENOMEM;
     char* ws = (char*)workspace;
     float* table = (float*)(ws + kMaternTableOff);
-    float4_t* plan_a = (float4_t*)(ws + kMaternPlanAOff);
-    double4_t* plan_b = (double4_t*)(ws + kMaternPlanBOff);
+    float4_t* rec = (float4_t*)(ws + kMaternRecOff);
     unsigned int* bitmap = (unsigned int*)(ws + kMaternTabBytes);
     const int64_t nwords = (int64_t)((need - kMaternTabBytes) / 4);
     const MlpDev M = make_dev(m);
@@ -1735,14 +1796,25 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
     const int64_t max_wg = 1LL << 23;                      // keeps a launch below 2^31 work-items
     const int64_t tiles_per_launch = max_wg / wg_per_tile > 0 ? max_wg / wg_per_tile : 1;
-    const double ib = 1.0 / prm->beta;
+    // ln sigma^2 goes into the plans where it is finite; sigma^2 = 0 or +inf is
+    // applied to each entry instead
+    const double sigma2 = prm->sigma2;
+    const bool sig_fold = sigma2 > 0.0 && isfinite(sigma2);
+    const double lsig = sig_fold ? log(sigma2) : 0.0;
+    const double sig_mul = sig_fold ? 1.0 : sigma2;
+    const double ib = 1.0 / prm->beta, kb = kLog2e / prm->beta;
+    // interval position from log2(zl), zl = z log2 e: (log10 z - lx_lo) (kTableSize - 1) / (lx_hi - lx_lo)
+    const double tsc = (double)(kTableSize - 1) / ((double)M.lx_hi - (double)M.lx_lo);
+    const float fa = (float)(std::log10(2.0) * tsc);
+    const float fb = (float)((-std::log2(kLog2e) * std::log10(2.0) - (double)M.lx_lo) * tsc);
+    const int nu_ok = (float)nu >= M.nu_lo && (float)nu <= M.nu_hi ? 1 : 0;
     int st = m->table_source == BK_TABLE_SOLVER
                  ? launch(k_matern_table_solver, dim3((kTableSize + 255) / 256), dim3(256), stream, M, (float)nu,
                           m->train_L[0], m->train_L[1], table)
                  : launch(k_matern_table, dim3((kTableSize + 255) / 256), dim3(256), stream, M, (float)nu, table);
     if (st == BK_OK)
-        st = launch(k_matern_plans, dim3((kTableSize + 254) / 256), dim3(256), stream, M, nu, Lq, pref,
-                    (const float*)table, plan_a, plan_b);
+        st = launch(k_matern_plans, dim3((kTableSize + 254) / 256), dim3(256), stream, M, nu, Lq, pref, lsig,
+                    (const float*)table, rec);
     if (st == BK_OK)
         st = launch(k_fill_u32, dim3((unsigned)std::min<int64_t>((nwords + 255) / 256, 4096)), dim3(256), stream,
                     bitmap, nwords);
@@ -1752,18 +1824,18 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
     for (int64_t t0 = 0; t0 < ntiles; t0 += tiles_per_launch) {
         const int64_t nt = ntiles - t0 < tiles_per_launch ? ntiles - t0 : tiles_per_launch;
         const dim3 grid((unsigned)(nt * wg_per_tile));
-        const float4_t* pa = plan_a;
-        const double4_t* pb = plan_b;
+        const float4_t* rc = rec;
         if (f32)
-            st = prm->stats ? launch(k_matern_learned<float, true>, grid, dim3(256), stream, M, pa, pb, locs->x,
-                                     locs->y, g, t0, prm->sigma2, ib, nu, bitmap, (float*)out, prm->stats)
-                            : launch(k_matern_learned<float, false>, grid, dim3(256), stream, M, pa, pb, locs->x,
-                                     locs->y, g, t0, prm->sigma2, ib, nu, bitmap, (float*)out, prm->stats);
+            st = prm->stats ? launch(k_matern_learned<float, true>, grid, dim3(256), stream, rc, locs->x, locs->y, g,
+                                     t0, sigma2, kb, fa, fb, nu_ok, nu, sig_mul, bitmap, (float*)out, prm->stats)
+                            : launch(k_matern_learned<float, false>, grid, dim3(256), stream, rc, locs->x, locs->y, g,
+                                     t0, sigma2, kb, fa, fb, nu_ok, nu, sig_mul, bitmap, (float*)out, prm->stats);
         else
-            st = prm->stats ? launch(k_matern_learned<double, true>, grid, dim3(256), stream, M, pa, pb, locs->x,
-                                     locs->y, g, t0, prm->sigma2, ib, nu, bitmap, (double*)out, prm->stats)
-                            : launch(k_matern_learned<double, false>, grid, dim3(256), stream, M, pa, pb, locs->x,
-                                     locs->y, g, t0, prm->sigma2, ib, nu, bitmap, (double*)out, prm->stats);
+            st = prm->stats ? launch(k_matern_learned<double, true>, grid, dim3(256), stream, rc, locs->x, locs->y, g,
+                                     t0, sigma2, kb, fa, fb, nu_ok, nu, sig_mul, bitmap, (double*)out, prm->stats)
+                            : launch(k_matern_learned<double, false>, grid, dim3(256), stream, rc, locs->x, locs->y,
+                                     g, t0, sigma2, kb, fa, fb, nu_ok, nu, sig_mul, bitmap, (double*)out,
+                                     prm->stats);
         if (st != BK_OK) return st;
     }
     if (mark_kernel_event(prm, 1, stream) != hipSuccess) return BK_EHIP;

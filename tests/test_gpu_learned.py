@@ -337,6 +337,33 @@ def test_learned_matern(api, orc, trained):
         assert rel_err(A[m], R[m]).max() <= TOL_MIXED, nu
 
 
+def test_learned_matern_sigma2(api, orc, trained):
+    """sigma^2 enters the learned Matern plans as ln sigma^2 in the exponent: the
+    output matches the oracle at extreme positive sigma^2 in both output types, and
+    sigma^2 = 0 or +inf (no finite logarithm) gives the constant it must."""
+    import torch
+    from paper_2502_00356_amd import workloads as w
+    n, ts, beta, nu = 300, 128, 0.05, 2.3
+    xy = w.uniform_locations(n, seed=52)
+    lx, ly = to_dev(xy[:, 0]), to_dev(xy[:, 1])
+    R1 = orc.matern_full(xy, 1.0, beta, nu)
+    for s2, odt in ((1e-30, api.OUT_F32), (3.5, api.OUT_F32), (1e30, api.OUT_F32), (1e-200, api.OUT_F64),
+                    (1e200, api.OUT_F64)):
+        out = api.matern_tiles(lx, ly, s2, beta, nu, ts, 1, mode="learned", model=trained, out_dtype=odt)
+        torch.cuda.synchronize()
+        A = api.unpack_tiles(out, n, ts, 1).numpy().astype(np.float64)
+        R = s2 * R1
+        m = np.abs(R) > 1e-36 if odt == api.OUT_F32 else np.abs(R) > 1e-300
+        assert m.sum() > n * n // 2, s2
+        assert rel_err(A[m], R[m]).max() <= TOL_MIXED, s2
+    for s2 in (0.0, float("inf")):
+        for odt in (api.OUT_F32, api.OUT_F64):
+            out = api.matern_tiles(lx, ly, s2, beta, nu, ts, 1, mode="learned", model=trained, out_dtype=odt)
+            torch.cuda.synchronize()
+            A = api.unpack_tiles(out, n, ts, 1).numpy()
+            assert np.all(A == s2), (s2, odt)
+
+
 def test_learned_gain_over_mixed(api, trained):
     """What the trained network buys: on 2^22 pairs of the standalone law the learned
     form is faster than the same FP32-compensated node sums behind the FP64 solve."""
