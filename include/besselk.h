@@ -189,7 +189,7 @@ int bk_matern_tiles(const bk_locs* locs, const bk_params* params, int32_t tile_s
 
 /* Device workspace bk_matern_tiles needs for BK_LEARNED (bytes; the other forms
  * need none): a 128 KiB window table and interval plans for the call's nu, then
- * one bit per wave of 512 entries (about 1/16384 of an FP32 output). 0 if the
+ * one bit per wave of 2048 entries (about 1/65536 of an FP32 output). 0 if the
  * sizes are invalid. */
 size_t bk_matern_workspace_bytes(int64_t n, int32_t tile_size, int32_t lower_only);
 

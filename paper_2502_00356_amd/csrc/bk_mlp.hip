@@ -66,6 +66,9 @@ constexpr int kCellsLx = 512, kCellsNu = 64, kCells = kCellsLx * kCellsNu;
 constexpr size_t kMaternTableOff = 0;                                   // kTableSize float4
 constexpr size_t kMaternRecBytes = 96;                                  // one interval's plan record
 constexpr int kRecQ = (int)(kMaternRecBytes / 16);                        // its float4 slots
+// Learned Matern launch shape: a wave covers 64 rows and kMlCols columns of a tile,
+// a workgroup four waves side by side.
+constexpr int kMlCols = 32, kMlGroupCols = 4 * kMlCols;
 constexpr size_t kMaternRecOff = kMaternTableOff + 16 * kTableSize;       // (kTableSize - 1) records
 constexpr size_t kMaternTabBytes = 128 * kTableSize;                      // 128 KiB (16 KiB unused)
 
@@ -1039,12 +1042,18 @@ __host__ __device__ inline int64_t tile_offset_l(int64_t n, int64_t ts, int64_t 
     return J * ts * n + nJ * I * ts;
 }
 
+// Tile (I, J) of packed tile p (tiles column by column). Lower: column J starts at
+// s(J) = J T - J (J - 1) / 2; the FP32 root of s(J) = p lands within a step or two of
+// J (values below 2^34 at ~6e-8 relative; the cancellation in b^2 - 8 p adds a few
+// steps only for T in the tens of thousands), and the loops settle it exactly. The
+// work is uniform across the wave: scalar integer loops after a handful of FP32
+// vector instructions.
 __device__ inline void tile_of_l(int64_t p, const TileGeomL& g, int64_t& I, int64_t& J)
 {
     int64_t T = g.T;
     if (!g.lower) { J = p / T; I = p - J * T; return; }
-    double b = 2.0 * (double)T + 1.0;
-    int64_t j = (int64_t)floor((b - sqrt(fmax(b * b - 8.0 * (double)p, 0.0))) * 0.5);
+    const float b = 2.0f * (float)T + 1.0f;
+    int64_t j = (int64_t)((b - __builtin_amdgcn_sqrtf(fmaxf(fmaf(b, b, -8.0f * (float)p), 0.0f))) * 0.5f);
     if (j < 0) j = 0;
     if (j > T - 1) j = T - 1;
     while (j > 0 && j * T - j * (j - 1) / 2 > p) --j;
@@ -1115,7 +1124,7 @@ __device__ inline double matern_node_sum(double zl, double c, double cn, double 
 }
 
 // Learned Matern. Wave w of the call (global workgroup index times 4 plus the wave
-// in the group) covers 64 rows of a tile column block and 8 of its columns. An
+// in the group) covers 64 rows of a tile column block and kMlCols of its columns. An
 // entry the learned form rejects is written as NaN and bit w of the call's wave
 // bitmap is set; k_matern_fallback then recomputes the NaN entries of the marked
 // waves with the mixed form. Keeping the fallback out of this kernel keeps its
@@ -1133,13 +1142,11 @@ __global__ __launch_bounds__(256, 8) void k_matern_learned(const float4_t* __res
                                                         unsigned int* __restrict__ bitmap, OutT* __restrict__ out,
                                                         unsigned long long* __restrict__ stats)
 {
-    constexpr int kColsPerWave = 8, kColsPerGroup = 32;
-    // block -> (tile, row block, column block) in 32-bit arithmetic (a 64-bit
-    // division is a long instruction sequence)
+    constexpr int kColsPerWave = kMlCols, kColsPerGroup = kMlGroupCols;
+    // grid: (row block, column block, tile of the launch)
     const unsigned wg_per_tile = (unsigned)g.rb_per_tile * (unsigned)g.cb_per_tile;
-    const unsigned tq = blockIdx.x / wg_per_tile, local = blockIdx.x - tq * wg_per_tile;
-    const int64_t p = tile_base + (int64_t)tq;
-    const int rb = (int)(local % (unsigned)g.rb_per_tile), cb = (int)(local / (unsigned)g.rb_per_tile);
+    const int64_t p = tile_base + (int64_t)blockIdx.z;
+    const int rb = (int)blockIdx.x, cb = (int)blockIdx.y;
     int64_t I, J;
     tile_of_l(p, g, I, J);
     const int64_t mI = min((int64_t)g.ts, g.n - I * g.ts);
@@ -1258,7 +1265,8 @@ __global__ __launch_bounds__(256, 8) void k_matern_learned(const float4_t* __res
     }
     // lane 0 is active whenever any lane of the wave is (rows grow with the lane)
     if (__ballot(rejected) != 0ull && lane == 0) {
-        const int64_t w = ((tile_base * (int64_t)wg_per_tile + (int64_t)blockIdx.x) << 2) + wave;
+        const int64_t blk = p * (int64_t)wg_per_tile + (int64_t)cb * g.rb_per_tile + rb;
+        const int64_t w = (blk << 2) + wave;
         atomicOr(bitmap + (w >> 5), 1u << (unsigned)(w & 31));
     }
     if (kStats) {
@@ -1295,7 +1303,7 @@ __global__ __launch_bounds__(256) void k_matern_fallback(const double* __restric
                                                          const unsigned int* __restrict__ bitmap, int64_t nwords,
                                                          OutT* __restrict__ out, unsigned long long* __restrict__ stats)
 {
-    constexpr int kColsPerWave = 8, kColsPerGroup = 32;
+    constexpr int kColsPerWave = kMlCols, kColsPerGroup = kMlGroupCols;
     __shared__ double s_tab[kTabLen];
     stage_tab(s_tab);
     const int lane = threadIdx.x & 63;
@@ -1764,7 +1772,7 @@ size_t matern_learned_workspace_bytes(int64_t n, int32_t tile_size, int32_t lowe
     if (n <= 0 || tile_size <= 0) return 0;
     const int64_t T = (n + tile_size - 1) / tile_size;
     const int64_t ntiles = lower_only ? T * (T + 1) / 2 : T * T;
-    const int64_t wg_per_tile = (int64_t)((tile_size + 63) / 64) * ((tile_size + 31) / 32);
+    const int64_t wg_per_tile = (int64_t)((tile_size + 63) / 64) * ((tile_size + kMlGroupCols - 1) / kMlGroupCols);
     const int64_t words = (ntiles * wg_per_tile * 4 + 31) / 32;
     return kMaternTabBytes + (((size_t)words * 4 + 255) & ~(size_t)255);
 }
@@ -1790,12 +1798,13 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
     g.T = (int32_t)((locs->n + tile_size - 1) / tile_size);
     g.lower = lower_only ? 1 : 0;
     g.rb_per_tile = (tile_size + 63) / 64;
-    g.cb_per_tile = (tile_size + 31) / 32;
+    g.cb_per_tile = (tile_size + kMlGroupCols - 1) / kMlGroupCols;
     const int64_t T = g.T;
     const int64_t ntiles = g.lower ? T * (T + 1) / 2 : T * T;
     const int64_t wg_per_tile = (int64_t)g.rb_per_tile * g.cb_per_tile;
-    const int64_t max_wg = 1LL << 23;                      // keeps a launch below 2^31 work-items
-    const int64_t tiles_per_launch = max_wg / wg_per_tile > 0 ? max_wg / wg_per_tile : 1;
+    // tiles per launch: below 2^31 work-items and within the grid's third dimension
+    const int64_t max_wg = 1LL << 23;
+    const int64_t tiles_per_launch = std::min<int64_t>(max_wg / wg_per_tile > 0 ? max_wg / wg_per_tile : 1, 65535);
     // ln sigma^2 goes into the plans where it is finite; sigma^2 = 0 or +inf is
     // applied to each entry instead
     const double sigma2 = prm->sigma2;
@@ -1823,7 +1832,7 @@ int bk_matern_learned(const bk_locs* locs, const bk_params* prm, int32_t tile_si
     const bool f32 = prm->out_dtype == BK_OUT_F32;
     for (int64_t t0 = 0; t0 < ntiles; t0 += tiles_per_launch) {
         const int64_t nt = ntiles - t0 < tiles_per_launch ? ntiles - t0 : tiles_per_launch;
-        const dim3 grid((unsigned)(nt * wg_per_tile));
+        const dim3 grid((unsigned)g.rb_per_tile, (unsigned)g.cb_per_tile, (unsigned)nt);
         const float4_t* rc = rec;
         if (f32)
             st = prm->stats ? launch(k_matern_learned<float, true>, grid, dim3(256), stream, rc, locs->x, locs->y, g,

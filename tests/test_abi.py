@@ -253,13 +253,13 @@ def test_binding_rejects_bad_caller_buffers():
 
 
 def test_matern_workspace_size():
-    """Learned Matern workspace: 128 KiB of tables plus one bit per wave of 512
+    """Learned Matern workspace: 128 KiB of tables plus one bit per wave of 64 x 32
     entries, in 256-byte units."""
     from paper_2502_00356_amd import api
     assert api.matern_workspace_bytes(0, 64, 1) == 0
     assert api.matern_workspace_bytes(10, 0, 1) == 0
-    # n = 1024 full matrix in one 1024-tile: 16 x 32 workgroups of 4 waves = 2048 bits = 256 bytes
+    # n = 1024 full matrix in one 1024-tile: 16 x 8 workgroups of 4 waves = 512 bits, one 256-byte unit
     assert api.matern_workspace_bytes(1024, 1024, 0) == 131072 + 256
-    # 316^2 grid, lower 1024-tiles: 98 tile rows, 4851 tiles of 16 x 32 workgroups
-    waves = 4851 * 16 * 32 * 4
+    # 316^2 grid, lower 1024-tiles: 98 tile rows, 4851 tiles of 16 x 8 workgroups
+    waves = 4851 * 16 * 8 * 4
     assert api.matern_workspace_bytes(99856, 1024, 1) == 131072 + ((waves + 31) // 32 * 4 + 255) // 256 * 256
