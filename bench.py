@@ -52,8 +52,8 @@ NODE_SLOTS = load_node_slots()
 # null: HBM bytes from the FETCH_SIZE and WRITE_SIZE runs scaled by a plain 1 GiB
 # copy, and SQ_INSTS_VALU of one launch without statistics.
 TRAFFIC = {
-    "grid": {"src_sha": "dde8dcae2b269c33", "n": 1 << 24, "bytes": 4.20051e8, "valu_insts": 1.17952e8},
-    "matern_large": {"src_sha": "dde8dcae2b269c33", "bytes": 2.03131e10, "valu_insts": 1.24188e10},
+    "grid": {"src_sha": "53987bbd1f5b7a90", "n": 1 << 24, "bytes": 4.22539e8, "valu_insts": 1.17947e8},
+    "matern_large": {"src_sha": "53987bbd1f5b7a90", "bytes": 2.02873e10, "valu_insts": 9.58373e9},
 }
 KERNEL_SOURCES = ("bk_mlp.hip", "bk_math.hpp", "bk_internal.hpp")
 
