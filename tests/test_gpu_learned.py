@@ -337,6 +337,30 @@ def test_learned_matern(api, orc, trained):
         assert rel_err(A[m], R[m]).max() <= TOL_MIXED, nu
 
 
+@pytest.mark.parametrize("ts,lower", [(24, 1), (64, 0), (100, 1), (129, 0), (257, 1)])
+def test_learned_matern_tile_shapes(api, orc, trained, ts, lower):
+    """Tile sizes that leave a workgroup's last waves idle (below 128 columns), split a
+    column group or a row block, or hold the whole matrix in one tile; full and
+    lower layouts. Learned tiles against the oracle (FP32 output) and bit for bit
+    against the statistics variant."""
+    import torch
+    from paper_2502_00356_amd import workloads as w
+    n, beta, nu = 257, 0.04, 1.7
+    xy = w.uniform_locations(n, seed=53)
+    lx, ly = to_dev(xy[:, 0]), to_dev(xy[:, 1])
+    out = api.matern_tiles(lx, ly, 1.0, beta, nu, ts, lower, mode="learned", model=trained, out_dtype=api.OUT_F32)
+    st = torch.zeros(api.STATS_LEN, dtype=torch.int64, device="cuda")
+    out2 = api.matern_tiles(lx, ly, 1.0, beta, nu, ts, lower, mode="learned", model=trained, out_dtype=api.OUT_F32,
+                            stats=st)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+    A = api.unpack_tiles(out, n, ts, lower).numpy().astype(np.float64)
+    R = orc.matern_full(xy, 1.0, beta, nu)
+    m = R > 1e-36
+    assert rel_err(A[m], R[m]).max() <= TOL_MIXED
+    assert np.all(np.diag(A) == 1.0)
+
+
 def test_learned_matern_sigma2(api, orc, trained):
     """sigma^2 enters the learned Matern plans as ln sigma^2 in the exponent: the
     output matches the oracle at extreme positive sigma^2 in both output types, and
