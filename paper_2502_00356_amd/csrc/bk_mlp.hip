@@ -1123,8 +1123,9 @@ __device__ inline double matern_node_sum(double zl, double c, double cn, double 
     return Sd + (double)((ua + ub) + fmaf(ud, 0.5f, uc));
 }
 
-// Learned Matern. Wave w of the call (global workgroup index times 4 plus the wave
-// in the group) covers 64 rows of a tile column block and kMlCols of its columns. An
+// Learned Matern. Wave w of the call (the workgroup's index (tile x column blocks +
+// column block) x row blocks + row block, times 4, plus the wave in the group)
+// covers 64 rows of a tile column block and kMlCols of its columns. An
 // entry the learned form rejects is written as NaN and bit w of the call's wave
 // bitmap is set; k_matern_fallback then recomputes the NaN entries of the marked
 // waves with the mixed form. Keeping the fallback out of this kernel keeps its
@@ -1188,9 +1189,9 @@ __global__ __launch_bounds__(256, 8) void k_matern_learned(const float4_t* __res
         if (r2 != 0.0) {
             // r from the hardware reciprocal square root (about 5e-8 relative) and one
             // Goldschmidt step, which squares that error (measured: <= 4.1e-15 relative
-            // over r^2 in [1e-40, 1e4]). r^2 far below that (no such pair of distinct
-            // points within the training box's x range) gives no finite zl, or one
-            // outside the box, and fails the range test.
+            // over r^2 in [1e-40, 1e4]). An r^2 below the normal range can give no
+            // finite zl (a flushed reciprocal square root), which fails the range test:
+            // the fallback recomputes that entry.
             const double yr = __builtin_amdgcn_rsq(r2);
             const double s0 = r2 * yr, h0 = 0.5 * yr;
             const double zl = fma(s0, fma(-s0, h0, 0.5), s0) * kb;
