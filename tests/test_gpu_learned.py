@@ -337,6 +337,31 @@ def test_learned_matern(api, orc, trained):
         assert rel_err(A[m], R[m]).max() <= TOL_MIXED, nu
 
 
+@pytest.mark.parametrize("nu,beta", [(0.05, 0.3), (0.3, 0.002), (0.6, 1.5), (6.0, 0.01), (9.5, 0.05)])
+def test_learned_matern_order_and_range_extremes(api, orc, trained, nu, beta):
+    """Orders near the training box's ends and ranges that put z near both ends of
+    its x span (small z: windows that start right of 0 and take the left-tail
+    bound; small 2 nu h: the FP64 node factor): learned tiles against the oracle,
+    FP32 and FP64 output, and the counting variant bit for bit."""
+    import torch
+    from paper_2502_00356_amd import workloads as w
+    n, ts = 200, 128
+    xy = w.uniform_locations(n, seed=54)
+    lx, ly = to_dev(xy[:, 0]), to_dev(xy[:, 1])
+    R = orc.matern_full(xy, 1.0, beta, nu)
+    for odt, floor in ((api.OUT_F32, 1e-36), (api.OUT_F64, 1e-300)):
+        out = api.matern_tiles(lx, ly, 1.0, beta, nu, ts, 1, mode="learned", model=trained, out_dtype=odt)
+        st = torch.zeros(api.STATS_LEN, dtype=torch.int64, device="cuda")
+        out2 = api.matern_tiles(lx, ly, 1.0, beta, nu, ts, 1, mode="learned", model=trained, out_dtype=odt,
+                                stats=st)
+        torch.cuda.synchronize()
+        assert torch.equal(out, out2)
+        A = api.unpack_tiles(out, n, ts, 1).numpy().astype(np.float64)
+        m = R > floor
+        assert rel_err(A[m], R[m]).max() <= TOL_MIXED, (nu, beta, odt)
+        assert int(st[api.STAT_ENTRIES]) > 0
+
+
 @pytest.mark.parametrize("ts,lower", [(24, 1), (64, 0), (100, 1), (129, 0), (257, 1)])
 def test_learned_matern_tile_shapes(api, orc, trained, ts, lower):
     """Tile sizes that leave a workgroup's last waves idle (below 128 columns), split a
