@@ -201,8 +201,8 @@ size_t bk_matern_workspace_bytes(int64_t n, int32_t tile_size, int32_t lower_onl
  * params->workspace and params->workspace_bytes are ignored. The forms other than
  * BK_LEARNED use no workspace and behave exactly as bk_matern_tiles.
  * Limits and errors: BK_ENOMEM if bk_matern_workspace_bytes(n, tile_size,
- * lower_only) exceeds BK_NOALLOC_SCRATCH_BYTES (about 1.6e10 stored entries with
- * 1,024-tiles; the 316 x 316-point lower-tile build needs 1.4 MiB); BK_EINVAL if a
+ * lower_only) exceeds BK_NOALLOC_SCRATCH_BYTES (about 6.7e10 stored entries with
+ * 1,024-tiles; the 316 x 316-point lower-tile build needs 0.42 MiB); BK_EINVAL if a
  * non-NULL stream belongs to another device than the current one; otherwise the
  * statuses of bk_matern_tiles.
  * No call allocates or frees memory. Every call on one GPU uses that GPU's one
