@@ -176,7 +176,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: the K_nu and Matern paths need no "
-              "cross-GPU exchange, and multi-GPU runs are not part of this build "
+              "cross-GPU exchange, and no multi-GPU run is provided "
               "(requested --gpus %d)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     import torch

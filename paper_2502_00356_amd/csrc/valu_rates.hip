@@ -6,7 +6,7 @@
 // loop of `iters` trips, over `blocks` workgroups of 256 lanes. The host times one
 // launch with a pair of HIP events and returns milliseconds; the caller turns that
 // into wave64 instructions per CU-clock. The results are written to `sink` so that
-// no chain is dead code. This is a measurement aid of the build, not part of the
+// no chain is dead code. This is a measurement aid, not part of the
 // K_nu path, and is built into its own library (libvalurates.so).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
